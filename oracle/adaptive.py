@@ -1,0 +1,143 @@
+"""Adaptive coarse degrees of freedom from pair eigenproblems (oracle, FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section 4: for every pair of subdomains s, t sharing a face, the localized
+generalized eigenproblem (eq. eig-matrix)
+
+    Pi (I-E^st)^T S^st (I-E^st) Pi w = lambda Pi S^st Pi w
+
+is solved on the factor space modulo null(Pi S^st Pi).  Eigenvectors with
+lambda above the threshold tau give the constraint rows (eq. d-def)
+c_l = w_l^T Pi (I-E)^T S (I-E) Pi, whose two halves are equal up to sign
+(Prop. 1).  One half, restricted to the face DOFs (edge and corner entries
+dropped, Section 7), is orthonormalised by a reduced QR and added to both
+C^s and C^t.  Alg. 2 picks, per pair, the smallest k with
+lambda_{k+1} <= tau, capped at nev_max (Section 8 uses at most 10).
+
+Readings: D = [C^s_shared, -C^t_shared] (one row per shared initial coarse
+DOF: the coarse DOFs of s and t agree); the pair weights are the
+stiffness-scaling weights renormalised over {s, t}; when both subdomains
+are floating, the pair-continuous rigid modes (in null D and null S^st)
+are removed from the factor space; the QR rank tolerance is 1e-10 max|R_jj|.
+
+The solve here is a dense generalized eigendecomposition of the deflated
+pair problem (brute force); the GPU library uses LOBPCG for the same
+eigenpairs.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+QR_RANK_TOL = 1e-10
+
+
+def pair_operators(L, s, t):
+    """Dense pair operators on [Gamma^s; Gamma^t].
+
+    Returns dict with S (block diagonal), IE (= I - E^st), D, and index data.
+    """
+    nIs, nIt = L.n_I[s], L.n_I[t]
+    Gs = L.sub_dofs[s][nIs:]
+    Gt = L.sub_dofs[t][nIt:]
+    ns, nt = len(Gs), len(Gt)
+    n = ns + nt
+    S = np.zeros((n, n))
+    S[:ns, :ns] = L.S[s]
+    S[ns:, ns:] = L.S[t]
+    shared, is_, it_ = np.intersect1d(Gs, Gt, return_indices=True)
+    ks = np.diag(L.K[s])[nIs:][is_]
+    kt = np.diag(L.K[t])[nIt:][it_]
+    ds = ks / (ks + kt)
+    dt = 1.0 - ds
+    # E^st: weighted average on Gamma^st, identity elsewhere
+    E = np.eye(n)
+    a = is_
+    b = ns + it_
+    E[a, a] = ds
+    E[a, b] = dt
+    E[b, a] = ds
+    E[b, b] = dt
+    IE = np.eye(n) - E
+    # D: shared initial coarse DOFs must agree
+    common = np.intersect1d(L.Rc[s], L.Rc[t])
+    rows = []
+    for cid in common:
+        rs = np.flatnonzero(L.Rc[s] == cid)[0]
+        rt = np.flatnonzero(L.Rc[t] == cid)[0]
+        rows.append(np.concatenate([L.C[s][rs], -L.C[t][rt]]))
+    D = np.array(rows).reshape(len(rows), n)
+    return dict(S=S, IE=IE, D=D, Gs=Gs, Gt=Gt, ns=ns, nt=nt, shared=shared,
+                is_=is_, it_=it_, ds=ds)
+
+
+def pair_rigid(L, s, t, ops):
+    """Pair-continuous rigid modes restricted to [Gamma^s; Gamma^t]."""
+    R = L.inp.rigid
+    return np.vstack([R[ops["Gs"]], R[ops["Gt"]]])
+
+
+def pair_eigenproblem(L, s, t, face_glob, tau, nev_max):
+    """Dense solution of the pair eigenproblem and the resulting constraints."""
+    ops = pair_operators(L, s, t)
+    n = ops["ns"] + ops["nt"]
+    D = ops["D"]
+    QD = sla.null_space(D) if D.shape[0] else np.eye(n)
+    Q = QD
+    both_floating = bool(L.inp.sub_floating[s] and L.inp.sub_floating[t])
+    if both_floating:
+        Y = QD.T @ pair_rigid(L, s, t, ops)
+        Q = QD @ sla.null_space(Y.T)
+    Afull = ops["IE"].T @ ops["S"] @ ops["IE"]
+    Ah = Q.T @ Afull @ Q
+    Bh = Q.T @ ops["S"] @ Q
+    Ah = 0.5 * (Ah + Ah.T)
+    Bh = 0.5 * (Bh + Bh.T)
+    bev = np.linalg.eigvalsh(Bh)
+    if bev[0] <= 1e-11 * bev[-1]:
+        raise AssertionError(f"Assumption 1 violated on pair ({s},{t}): "
+                             f"min eig(B) / max = {bev[0] / bev[-1]:.3e}")
+    lam, W = sla.eigh(Ah, Bh)
+    lam = lam[::-1]
+    W = W[:, ::-1]
+    k = int(min(np.count_nonzero(lam > tau), nev_max))
+    lam_next = float(lam[k]) if k < len(lam) else 0.0
+    face = face_glob["dofs"]
+    pos = np.searchsorted(ops["Gs"], face)
+    rows = np.zeros((0, len(face)))
+    c_full = None
+    if k > 0:
+        Wf = Q @ W[:, :k]
+        PiD = QD @ QD.T
+        c_full = PiD @ Afull @ Wf                 # eq. d-def, columns c_l
+        F = c_full[pos, :]                        # s-half on the face DOFs
+        Qr, Rr = np.linalg.qr(F, mode="reduced")
+        dR = np.abs(np.diag(Rr))
+        keep = dR > QR_RANK_TOL * dR.max() if dR.size else np.zeros(0, bool)
+        rows = Qr[:, keep].T
+    return dict(s=s, t=t, lam=lam, k=k, lam_next=lam_next, rows=rows, face_dofs=face,
+                c_full=c_full, n=n, n_factor=Q.shape[1], both_floating=both_floating)
+
+
+def enrich_level(L, tau, nev_max, pairs=None):
+    """Alg. 2 on one level: solve every pair problem and append the adaptive
+    face constraints to C^s and C^t.  Records omega_i (max lambda_{k+1})."""
+    from .substructure import rebuild_constraint_matrices
+    results = []
+    sel = range(len(L.pairs)) if pairs is None else pairs
+    for p in sel:
+        s, t, g = L.pairs[p]
+        res = pair_eigenproblem(L, s, t, L.globs[g], tau, nev_max)
+        res["pair"] = p
+        results.append(res)
+    for res in results:
+        g = L.pairs[res["pair"]][2]
+        for r in res["rows"]:
+            L.glob_cons[g].append(len(L.constraints))
+            L.constraints.append(dict(glob=g, dofs=res["face_dofs"], w=r.copy(), adaptive=True))
+    rebuild_constraint_matrices(L)
+    omega = max([r["lam_next"] for r in results], default=0.0)
+    L.adaptive = dict(results=results, omega=omega,
+                      n_added=int(sum(len(r["rows"]) for r in results)))
+    return L.adaptive
