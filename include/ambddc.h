@@ -1,0 +1,207 @@
+/*
+ * ambddc.h -- C ABI of the MI355X Adaptive-Multilevel BDDC library.
+ *
+ * Adaptive-Multilevel BDDC (Sousedik, Sistek, Mandel) for symmetric positive
+ * definite Q1 finite-element systems (3D Poisson, 1 DOF per node; linear
+ * elasticity, 3 DOF per node).  The library computes, on one GPU:
+ *   - per-subdomain interior factorisations and interface Schur complements
+ *     (Section 2: S = K_GG - K_GI K_II^{-1} K_IG);
+ *   - the adaptive set-up of Alg. 3: per level, BDDC structures with the
+ *     initial constraints (corners + edge averages, Section 7), the pair
+ *     generalized eigenproblems of eq. eig-matrix solved by LOBPCG with the
+ *     BDDC pair preconditioner of eq. bddc_pair (Section 5), selection of
+ *     eigenvalues above tau (Alg. 2), face constraint rows from eq. d-def
+ *     (Prop. 1; edge entries dropped and rows orthonormalised, Section 7),
+ *     enriched BDDC structures, and recursion to the next level (Section 3);
+ *   - PCG preconditioned by Multilevel BDDC (Alg. 1) with a Lanczos
+ *     condition estimate (Section 8);
+ *   - the element gradient -lambda^T (dK/dtheta_e) x of a misfit with
+ *     respect to element log10-coefficients.
+ *
+ * Conventions for every call:
+ *   - Status codes are returned; ambddc_last_error() gives a message for the
+ *     calling thread, valid until that thread's next call.
+ *   - Indices are 0-based int32.  Matrices are column-major.
+ *   - Free-DOF numbering: node-major, component-minor (DOF id = node*d + c),
+ *     Dirichlet DOFs removed, remaining DOFs keep their order.
+ *   - Element local node order is lexicographic: local index a + 2b + 4c is
+ *     the node at offset (a, b, c) from the element's lowest corner.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are GPU
+ *     memory on the handle's device (e.g. torch tensor data_ptr()).
+ *   - The caller owns every buffer it passes; the library copies what it
+ *     keeps and owns all memory inside the handle.  One handle must not be
+ *     used by two threads at the same time.
+ */
+#ifndef AMBDDC_H
+#define AMBDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMBDDC_OK = 0,
+  AMBDDC_E_INVALID_ARG = 1,   /* bad pointer, size or option */
+  AMBDDC_E_NOT_SPD = 2,       /* a Cholesky pivot was not positive (message names the matrix) */
+  AMBDDC_E_ASSUMPTION = 3,    /* Assumption 1 fails on a pair (message names the pair) */
+  AMBDDC_E_NO_CONVERGENCE = 4,/* PCG hit maxit; x holds the last iterate */
+  AMBDDC_E_OOM = 5,           /* device allocation failed */
+  AMBDDC_E_DEVICE = 6,        /* HIP runtime error */
+  AMBDDC_E_STATE = 7          /* call out of order (e.g. solve before setup) */
+} ambddc_status;
+
+typedef struct ambddc_ctx* ambddc_handle;
+
+/* Conforming hexahedral mesh (Section 2).  All pointers are host. */
+typedef struct {
+  int32_t n_nodes;
+  int32_t n_elems;
+  int32_t dof_per_node;        /* 1 = Poisson, 3 = elasticity */
+  const double* coords;        /* [n_nodes*3] x,y,z per node */
+  const int32_t* elem_nodes;   /* [n_elems*8] lexicographic local order */
+  const uint8_t* dirichlet;    /* [n_nodes*dof_per_node] 1 = DOF fixed to zero */
+} ambddc_mesh;
+
+/* Decomposition into subdomains (unions of elements) and agglomerated
+ * higher levels (Section 3).  All pointers are host. */
+typedef struct {
+  int32_t levels;                  /* L >= 2: levels 1..L-1 are substructured, level L solved directly */
+  const int32_t* elem_to_sub;      /* [n_elems] level-1 subdomain of each element */
+  const int32_t* const* parents;   /* [levels-2] arrays: level-i subdomain -> level-(i+1) subdomain */
+} ambddc_decomp;
+
+typedef struct {
+  double tau;                  /* adaptive threshold (Alg. 2); <= 0 or inf disables adaptivity */
+  int32_t nev_max;             /* cap on adaptive constraints per face (10 in Section 8) */
+  int32_t lobpcg_maxit;        /* LOBPCG iteration cap (e.g. 100) */
+  int32_t lobpcg_block;        /* LOBPCG block size m >= nev_max+1 (e.g. 16) */
+  double lobpcg_tol;           /* relative residual tolerance (e.g. 1e-8) */
+  int32_t precision;           /* 0 = FP64 everywhere (only value accepted so far) */
+  int32_t face_averages;       /* 1 = add face averages to the initial constraints (c+e+f) */
+  uint64_t seed;               /* LOBPCG start vectors */
+  void* stream;                /* hipStream_t for all work (NULL = default stream) */
+} ambddc_options;
+
+/* Fill *opt with defaults: tau 10, nev_max 10, maxit 100, block 16, tol 1e-7, FP64. */
+void ambddc_default_options(ambddc_options* opt);
+
+/* Level-1 structure counts (the columns n, n_Gamma, n_f of Section 8's
+ * tables) computed on the host only; touches no GPU. */
+typedef struct {
+  int32_t n_free;              /* unknowns after Dirichlet removal */
+  int32_t n_sub;
+  int32_t n_interface;         /* free DOFs on the interface Gamma */
+  int32_t n_faces, n_edges, n_corners;   /* globs with at least one free DOF */
+  int32_t n_coarse_initial;    /* initial constraints (corners + edge averages [+ faces]) */
+  int32_t n_pairs;             /* adjacent pairs = faces */
+} ambddc_analysis;
+
+/* sub_sizes_host may be NULL, else [2*n_sub]: (n_I, n_Gamma) per subdomain.
+ * Pass n_sub_cap = its capacity in subdomains; E_INVALID_ARG if too small. */
+ambddc_status ambddc_analyze(const ambddc_mesh* mesh, const ambddc_decomp* decomp,
+                             int32_t face_averages, ambddc_analysis* out,
+                             int32_t* sub_sizes_host, int32_t n_sub_cap);
+
+/* Analyse the mesh and decomposition: level-1 DOF numbering, interface and
+ * glob classification (faces, edges, corners; Section 2), initial
+ * constraints, pair lists, device index maps.  Copies everything it needs;
+ * the inputs may be freed afterwards.  Errors: E_INVALID_ARG for
+ * inconsistent sizes or ids, E_OOM, E_DEVICE. */
+ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* decomp,
+                            const ambddc_options* opt, ambddc_handle* out);
+
+/* Numeric set-up (Alg. 3) for element coefficients resident on the device:
+ * coeff[n_elems] = kappa (Poisson) or Young's modulus E (elasticity),
+ * nu[n_elems] = Poisson ratio (elasticity; NULL for Poisson).  May be called
+ * again with new coefficients; the previous hierarchy is replaced.
+ * Errors: E_NOT_SPD, E_ASSUMPTION, E_INVALID_ARG, E_OOM, E_DEVICE. */
+ambddc_status ambddc_setup(ambddc_handle h, const double* coeff_dev, const double* nu_dev);
+
+/* PCG with the Multilevel BDDC preconditioner (Alg. 1), x0 = 0, stopping when
+ * ||f - K x||_2 / ||f||_2 <= rtol per column (FP64 residual).
+ * rhs_dev, x_dev: device [n_free*nrhs] column-major (ld = n_free).
+ * iterations_host[nrhs], cond_host[nrhs] (Lanczos estimate of the
+ * preconditioned condition number) may be NULL.  The columns are
+ * independent recurrences advanced in lockstep.  Errors: E_STATE before
+ * setup, E_NO_CONVERGENCE (x holds the last iterate), E_DEVICE. */
+ambddc_status ambddc_solve(ambddc_handle h, const double* rhs_dev, int32_t nrhs, double rtol,
+                           int32_t maxit, double* x_dev, int32_t* iterations_host,
+                           double* cond_host);
+
+/* Element gradient of a misfit w.r.t. element log10-coefficients theta_e,
+ * K = sum_e 10^theta_e Khat_e:  grad[e] = -ln(10) sum_k lam_k,e^T K_e x_k,e
+ * with the element matrices of the last setup.  X_dev, Lam_dev: device
+ * [n_free*nrhs] column-major; grad_dev: device [n_elems]. */
+ambddc_status ambddc_element_gradient(ambddc_handle h, const double* X_dev, const double* Lam_dev,
+                                      int32_t nrhs, double* grad_dev);
+
+/* Set-up statistics, per level i < 8 (paper's reported quantities). */
+typedef struct {
+  int32_t levels;                /* substructured levels (L-1) */
+  int32_t n_free;                /* level-1 unknowns */
+  int32_t n_sub[8];
+  int32_t n_pairs[8];            /* faces = adjacent pairs */
+  int32_t n_coarse[8];           /* coarse DOFs after enrichment */
+  int32_t n_adaptive[8];         /* adaptive constraints added */
+  int32_t lobpcg_iters[8];       /* LOBPCG iterations run (lockstep) */
+  int32_t n_unconverged[8];      /* pairs not converged at lobpcg_maxit */
+  double omega_tilde[8];         /* max over pairs of the first unselected eigenvalue */
+  double t_phase[16];            /* seconds: 0 assembly+Schur, 1 BDDC init, 2 LOBPCG,
+                                    3 selection, 4 enriched BDDC, 5 coarse, 6 total setup,
+                                    7 last solve */
+} ambddc_stats;
+
+ambddc_status ambddc_get_stats(ambddc_handle h, ambddc_stats* out);
+
+/* ---- introspection (copies to host; for parity checks and tooling) ---- */
+
+/* Sizes of substructured level `level` (0-based). Any out pointer may be NULL. */
+ambddc_status ambddc_level_info(ambddc_handle h, int32_t level, int32_t* n_dof, int32_t* n_sub,
+                                int32_t* n_pairs, int32_t* n_coarse);
+
+/* Level DOF ids of subdomain `sub`, interior first then interface, each
+ * group ascending.  dofs_host may be NULL to query n_I, n_G only. */
+ambddc_status ambddc_sub_dofs(ambddc_handle h, int32_t level, int32_t sub, int32_t* dofs_host,
+                              int32_t* n_I, int32_t* n_G);
+
+/* Interface Schur complement S of `sub`, n_G x n_G column-major, host. */
+ambddc_status ambddc_get_schur(ambddc_handle h, int32_t level, int32_t sub, double* S_host);
+
+/* Subdomains of pair `pair` (one pair per face glob). */
+ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int32_t* s, int32_t* t,
+                               int32_t* n_face);
+
+/* Result of the pair eigenproblem: lam_host[lobpcg_block] (descending),
+ * resid_host[lobpcg_block] relative residuals |A x - lam B x| / (|A x| + |lam| |B x|),
+ * number of selected constraints k (after the QR rank test), the first
+ * unselected eigenvalue, LOBPCG iterations and a converged flag.  Any output
+ * pointer may be NULL. */
+ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, double* lam_host,
+                                     double* resid_host, int32_t* k, double* lam_next,
+                                     int32_t* iters, int32_t* converged);
+
+/* Adaptive constraint rows of the face of `pair`: rows_host[k*n_face],
+ * row-major (row l = l-th orthonormal row), and the face's level DOF ids
+ * face_dofs_host[n_face], ascending.  Either pointer may be NULL. */
+ambddc_status ambddc_get_face_constraints(ambddc_handle h, int32_t level, int32_t pair,
+                                          double* rows_host, int32_t* face_dofs_host);
+
+/* Coarse element matrix K_c^s = Psi^T S Psi of `sub` (n_c x n_c, column-major,
+ * rows in ascending coarse id, Section 5), host.  n_c from *nc (may be
+ * queried with Kc_host = NULL). */
+ambddc_status ambddc_get_coarse_element(ambddc_handle h, int32_t level, int32_t sub,
+                                        double* Kc_host, int32_t* nc);
+
+/* Assembled coarse matrix of the top level (n_coarse x n_coarse of the last
+ * substructured level), host, column-major. */
+ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc_host, int32_t* n);
+
+const char* ambddc_last_error(void);
+void ambddc_destroy(ambddc_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMBDDC_H */

@@ -1,0 +1,381 @@
+// Batched dense kernels on uneven batches (see dense.hpp).
+#include <algorithm>
+#include <cmath>
+
+#include "dense.hpp"
+#include "jacobi_dev.hpp"
+#include "mfma_tile.hpp"
+
+namespace ambddc {
+
+__device__ __forceinline__ int ceil_div_dev(int a, int b) { return (a + b - 1) / b; }
+
+// --------------------------------------------------------------------------
+// GEMM
+// --------------------------------------------------------------------------
+
+template <bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, int nd, double alpha,
+                                              double beta) {
+  __shared__ TileSmem<WM, WN> sm;
+  const int tile = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc g = d[lo];
+  if (g.flag && *g.flag == 0) return;
+  const int lt = tile - g.tile_start;
+  const int tm = lt % g.tiles_m, tn = lt / g.tiles_m;
+  mfma_tile<TA, TB, WM, WN>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N, g.K,
+                            tm * TileShape<WM, WN>::TM, tn * TileShape<WM, WN>::TN, alpha, beta,
+                            -1, sm);
+}
+
+void GemmOp::finalize(hipStream_t st) {
+  const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
+  tiles = 0;
+  for (auto& g : h) {
+    g.tiles_m = ceil_div(g.M, TM);
+    g.tile_start = tiles;
+    tiles += g.tiles_m * ceil_div(g.N, TN);
+  }
+  d.upload(h, st);
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+template <bool TA, bool TB>
+static void gemm_dispatch(const GemmOp& op, double alpha, double beta, hipStream_t st) {
+  if (op.narrow)
+    k_gemm<TA, TB, 4, 1><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+  else
+    k_gemm<TA, TB, 2, 2><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+}
+
+void GemmOp::run(double alpha, double beta, hipStream_t st) const {
+  if (h.empty() || tiles == 0) return;
+  if (!ta && !tb) gemm_dispatch<false, false>(*this, alpha, beta, st);
+  else if (ta && !tb) gemm_dispatch<true, false>(*this, alpha, beta, st);
+  else if (!ta && tb) gemm_dispatch<false, true>(*this, alpha, beta, st);
+  else gemm_dispatch<true, true>(*this, alpha, beta, st);
+  AMB_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
+// GEMV (transposed, several right-hand sides): one wave per output column
+// --------------------------------------------------------------------------
+
+template <int R>
+__global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, int nd, double alpha,
+                                                double beta) {
+  const int wg = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
+  }
+  const GemvDesc g = d[lo];
+  const int col = (wg - g.wg_start) * 4 + (threadIdx.x >> 6);
+  if (col >= g.M) return;
+  const int lane = threadIdx.x & 63;
+  const double* a = g.A + (size_t)col * g.lda;
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int i = lane; i < g.K; i += 64) {
+    const double av = a[i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = acc[r];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    acc[r] = v;
+  }
+  if (lane < R) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r == lane) v = acc[r];
+    double* y = g.Y + col + (size_t)lane * g.ldy;
+    *y = alpha * v + (beta != 0.0 ? beta * (*y) : 0.0);
+  }
+}
+
+void GemvOp::finalize(hipStream_t st) {
+  wgs = 0;
+  for (auto& g : h) {
+    g.wg_start = wgs;
+    wgs += ceil_div(g.M, 4);
+  }
+  d.upload(h, st);
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
+  if (h.empty() || wgs == 0) return;
+  const int nd = int(h.size());
+  switch (nrhs) {
+#define AMB_CASE(R) case R: k_gemv_t<R><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+    AMB_CASE(1) AMB_CASE(2) AMB_CASE(3) AMB_CASE(4) AMB_CASE(5) AMB_CASE(6) AMB_CASE(7)
+    AMB_CASE(8) AMB_CASE(9) AMB_CASE(10) AMB_CASE(11) AMB_CASE(12) AMB_CASE(13) AMB_CASE(14)
+    AMB_CASE(15) AMB_CASE(16)
+#undef AMB_CASE
+    default: throw Error(1, "GemvOp: nrhs must be in 1..16");
+  }
+  AMB_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
+// Signed partial LDL^T, right-looking, panel width NB
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ int find_active(const int* pre, int n, int x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Factor the NB x NB diagonal block of every active matrix in place.
+__global__ __launch_bounds__(256) void k_ldlt_diag(const LdltDesc* __restrict__ d,
+                                                   const int* __restrict__ act, int k0, int* info) {
+  constexpr int NB = LdltOp::NB;
+  __shared__ double L[NB][NB + 1];
+  const LdltDesc g = d[act[blockIdx.x]];
+  const int kb = min(NB, g.p - k0);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i % NB, c = i / NB;
+    L[r][c] = (r < kb && c < kb) ? g.A[(k0 + r) + (size_t)(k0 + c) * g.lda] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    const double sg = (k0 + j < g.q) ? 1.0 : -1.0;
+    const double dj = L[j][j] * sg;
+    const bool bad = !(dj > 0.0);
+    const double piv = bad ? 1.0 : sqrt(dj);
+    __syncthreads();
+    if (tid == 0) {
+      if (bad) atomicCAS(info, 0, act[blockIdx.x] + 1);
+      L[j][j] = piv;
+    }
+    for (int i = j + 1 + tid; i < kb; i += 256) L[i][j] /= (sg * piv);
+    __syncthreads();
+    const int rem = kb - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      const int i = j + 1 + idx % rem, l = j + 1 + idx / rem;
+      if (l <= i) L[i][l] -= sg * L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < kb * kb; i += 256) {
+    const int r = i % kb, c = i / kb;
+    if (r >= c) g.A[(k0 + r) + (size_t)(k0 + c) * g.lda] = L[r][c];
+  }
+}
+
+// Panel: rows below the diagonal block, L_i = A_i (L_kk D)^{-T}.
+__global__ __launch_bounds__(256) void k_ldlt_panel(const LdltDesc* __restrict__ d,
+                                                    const int* __restrict__ act,
+                                                    const int* __restrict__ pre, int nact, int k0) {
+  constexpr int NB = LdltOp::NB;
+  __shared__ double L[NB][NB + 1];
+  const int a = find_active(pre, nact, blockIdx.x);
+  const LdltDesc g = d[act[a]];
+  const int chunk = blockIdx.x - pre[a];
+  const int kb = min(NB, g.p - k0);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i % NB, c = i / NB;
+    L[r][c] = (r < kb && c < kb && r >= c) ? g.A[(k0 + r) + (size_t)(k0 + c) * g.lda] : 0.0;
+  }
+  __syncthreads();
+  const int row = k0 + kb + chunk * LdltOp::ROWS + tid;
+  if (row >= g.N) return;
+  double x[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) x[j] = (j < kb) ? g.A[row + (size_t)(k0 + j) * g.lda] : 0.0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < kb) {
+      double v = x[j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) {
+        const double sp = (k0 + p < g.q) ? 1.0 : -1.0;
+        v -= x[p] * sp * L[j][p];
+      }
+      const double sj = (k0 + j < g.q) ? 1.0 : -1.0;
+      x[j] = v / (sj * L[j][j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    if (j < kb) g.A[row + (size_t)(k0 + j) * g.lda] = x[j];
+}
+
+// Trailing update: A_ij -= L_i D L_j^T on lower tiles of the trailing block.
+__global__ __launch_bounds__(256) void k_ldlt_update(const LdltDesc* __restrict__ d,
+                                                     const int* __restrict__ act,
+                                                     const int* __restrict__ pre, int nact, int k0) {
+  __shared__ TileSmem<2, 2> sm;
+  const int a = find_active(pre, nact, blockIdx.x);
+  const LdltDesc g = d[act[a]];
+  const int l = blockIdx.x - pre[a];
+  int ti2 = int((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((ti2 + 1) * (ti2 + 2) / 2 <= l) ++ti2;
+  while (ti2 * (ti2 + 1) / 2 > l) --ti2;
+  const int tj = l - ti2 * (ti2 + 1) / 2;
+  const int kb = min(LdltOp::NB, g.p - k0);
+  const int r0 = k0 + kb;
+  const int m0 = r0 + ti2 * LdltOp::TILE, n0 = r0 + tj * LdltOp::TILE;
+  const double* P = g.A + (size_t)k0 * g.lda;   // panel columns
+  // C[m0.., n0..] -= sum_p P[m, p] sigma_p P[n, p]
+  // panel column p is a negative pivot when k0 + p >= q (clamped: all negative when q <= k0)
+  mfma_tile<false, true, 2, 2>(P, g.lda, P, g.lda, g.A, g.lda, g.N, g.N, kb, m0, n0, -1.0, 1.0,
+                               max(g.q - k0, 0), sm);
+}
+
+void LdltOp::finalize(hipStream_t st) {
+  int maxp = 0;
+  for (auto& g : h) maxp = std::max(maxp, g.p);
+  steps = (maxp + NB - 1) / NB;
+  std::vector<int> a, pp, up;
+  step_off.assign(steps + 1, 0);
+  pan_total.assign(steps, 0);
+  upd_total.assign(steps, 0);
+  nact.assign(steps, 0);
+  std::vector<int> pp_all, up_all;
+  for (int s = 0; s < steps; ++s) {
+    const int k0 = s * NB;
+    int ptot = 0, utot = 0, na = 0;
+    for (size_t i = 0; i < h.size(); ++i) {
+      const auto& g = h[i];
+      if (g.p <= k0) continue;
+      const int kb = std::min(NB, g.p - k0);
+      const int rows = g.N - k0 - kb;
+      a.push_back(int(i));
+      pp_all.push_back(ptot);
+      up_all.push_back(utot);
+      ptot += rows > 0 ? ceil_div(rows, ROWS) : 0;
+      const int nt = rows > 0 ? ceil_div(rows, TILE) : 0;
+      utot += nt * (nt + 1) / 2;
+      ++na;
+    }
+    step_off[s + 1] = step_off[s] + na;
+    pan_total[s] = ptot;
+    upd_total[s] = utot;
+    nact[s] = na;
+  }
+  d.upload(h, st);
+  act.upload(a, st);
+  pan_pre.upload(pp_all, st);
+  upd_pre.upload(up_all, st);
+  info.alloc(1);
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void LdltOp::run(hipStream_t st) {
+  if (h.empty()) return;
+  info.zero(st);
+  for (int s = 0; s < steps; ++s) {
+    const int k0 = s * NB;
+    const int off = step_off[s];
+    if (nact[s] == 0) continue;
+    k_ldlt_diag<<<nact[s], 256, 0, st>>>(d.p, act.p + off, k0, info.p);
+    if (pan_total[s] > 0)
+      k_ldlt_panel<<<pan_total[s], 256, 0, st>>>(d.p, act.p + off, pan_pre.p + off, nact[s], k0);
+    if (upd_total[s] > 0)
+      k_ldlt_update<<<upd_total[s], 256, 0, st>>>(d.p, act.p + off, upd_pre.p + off, nact[s], k0);
+  }
+  AMB_LAUNCH_CHECK();
+}
+
+int LdltOp::failed(hipStream_t st) {
+  int v = 0;
+  AMB_HIP(hipMemcpyAsync(&v, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  AMB_HIP(hipStreamSynchronize(st));
+  return v - 1;
+}
+
+// --------------------------------------------------------------------------
+// lower -> upper copy on a square block [n0, n0+n)^2
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_sym(const SymOp::Desc* __restrict__ d, int nd) {
+  const int blk = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].start <= blk) lo = mid; else hi = mid - 1;
+  }
+  const SymOp::Desc g = d[lo];
+  const int nt = ceil_div_dev(g.n, 32);
+  const int l = blk - g.start;
+  const int bi = l % nt, bj = l / nt;   // tile (bi, bj) of the upper triangle, bi <= bj
+  if (bi > bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r = bi * 32 + tx, c = bj * 32 + yy;   // upper entry (r < c)
+    if (r < g.n && c < g.n && r < c)
+      g.A[(g.n0 + r) + (size_t)(g.n0 + c) * g.lda] = g.A[(g.n0 + c) + (size_t)(g.n0 + r) * g.lda];
+  }
+}
+
+void SymOp::finalize(hipStream_t st) {
+  tiles = 0;
+  for (auto& g : h) {
+    g.start = tiles;
+    const int nt = ceil_div(g.n, 32);
+    tiles += nt * nt;
+  }
+  d.upload(h, st);
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void SymOp::run(hipStream_t st) const {
+  if (h.empty() || tiles == 0) return;
+  k_sym<<<tiles, 256, 0, st>>>(d.p, int(h.size()));
+  AMB_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
+// batched Jacobi eigensolver (n <= 64 in LDS)
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_jacobi(double* const* A, const int* n, double* const* W,
+                                                double* const* V) {
+  extern __shared__ double smem[];
+  const int b = blockIdx.x;
+  const int nb = n[b];
+  if (nb <= 0) return;
+  double* a = smem;
+  double* v = a + nb * nb;
+  double* rot = v + nb * nb;
+  double* red = rot + 4 * ((nb + 2) / 2);
+  int* perm = reinterpret_cast<int*>(red + 16);
+  for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) a[i] = A[b][i];
+  __syncthreads();
+  jacobi_lds(a, v, nb, rot, red);
+  sort_desc_lds(a, nb, perm);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) W[b][i] = a[perm[i] + perm[i] * nb];
+  for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) {
+    const int r = i % nb, c = i / nb;
+    V[b][r + c * nb] = v[r + perm[c] * nb];
+  }
+}
+
+void jacobi_eig_batched(double* const* A, const int* n, double* const* W, double* const* V,
+                        int batch, int nmax, hipStream_t st) {
+  if (batch == 0) return;
+  const size_t sm = sizeof(double) * (2 * nmax * nmax + 4 * ((nmax + 2) / 2) + 16) +
+                    sizeof(int) * (nmax + 1);
+  k_jacobi<<<batch, 256, sm, st>>>(A, n, W, V);
+  AMB_LAUNCH_CHECK();
+}
+
+}  // namespace ambddc

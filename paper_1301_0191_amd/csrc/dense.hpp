@@ -1,0 +1,104 @@
+// Batched dense linear algebra on uneven batches (FP64), gfx950.
+//   GemmOp : C_b = alpha op(A_b) op(B_b) + beta C_b on MFMA 16x16x4 tiles
+//   GemvOp : Y_b = alpha A_b^T X_b + beta Y_b for a few right-hand sides
+//   LdltOp : signed partial LDL^T (Cholesky with fixed pivot signs), the
+//            trailing block becomes the Schur complement
+//   SymOp  : copy the lower triangle of a square block to the upper one
+#pragma once
+#include "common.hpp"
+
+namespace ambddc {
+
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int lda, ldb, ldc;
+  int M, N, K;
+  int tiles_m, tile_start;
+  const int* flag;  // optional: skip the product when *flag == 0
+};
+
+class GemmOp {
+ public:
+  bool ta = false, tb = false, narrow = false;  // narrow: 128x32 tiles (N <= 32)
+  std::vector<GemmDesc> h;
+  DBuf<GemmDesc> d;
+  int tiles = 0;
+  void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
+           int K, const int* flag = nullptr) {
+    if (M <= 0 || N <= 0) return;
+    h.push_back(GemmDesc{A, B, C, lda, ldb, ldc, M, N, K, 0, 0, flag});
+  }
+  void finalize(hipStream_t st);
+  void run(double alpha, double beta, hipStream_t st) const;
+  bool empty() const { return h.empty(); }
+};
+
+struct GemvDesc {
+  const double* A;  // K x M block, column-major
+  int lda, K, M;
+  const double* X;  // K x nrhs
+  int ldx;
+  double* Y;        // M x nrhs
+  int ldy;
+  int wg_start;
+};
+
+class GemvOp {
+ public:
+  std::vector<GemvDesc> h;
+  DBuf<GemvDesc> d;
+  int wgs = 0;
+  void add(const double* A, int lda, int K, int M, const double* X, int ldx, double* Y, int ldy) {
+    if (M <= 0) return;
+    h.push_back(GemvDesc{A, lda, K, M, X, ldx, Y, ldy, 0});
+  }
+  void finalize(hipStream_t st);
+  // Y = alpha A^T X + beta Y, nrhs in 1..16
+  void run(double alpha, double beta, int nrhs, hipStream_t st) const;
+  bool empty() const { return h.empty(); }
+};
+
+struct LdltDesc {
+  double* A;
+  int lda, N, p, q;  // eliminate p pivots; pivots < q positive, the rest negative
+};
+
+class LdltOp {
+ public:
+  static constexpr int NB = 32;     // panel width
+  static constexpr int TILE = 64;   // trailing update tile
+  static constexpr int ROWS = 256;  // panel rows per workgroup
+  std::vector<LdltDesc> h;
+  DBuf<LdltDesc> d;
+  // per step: active matrices with work prefix (panel chunks / update tiles)
+  std::vector<int> step_off;        // into lists, size steps+1
+  DBuf<int> act, pan_pre, upd_pre;  // matrix ids, prefix sums
+  std::vector<int> pan_total, upd_total, nact;
+  DBuf<int> info;                   // first failing matrix + 1 (0 = ok)
+  int steps = 0;
+  void add(double* A, int lda, int N, int p, int q) { h.push_back(LdltDesc{A, lda, N, p, q}); }
+  void finalize(hipStream_t st);
+  void run(hipStream_t st);
+  int failed(hipStream_t st);       // returns failing matrix index or -1
+};
+
+class SymOp {
+ public:
+  struct Desc { double* A; int lda, n0, n; int start; };
+  std::vector<Desc> h;
+  DBuf<Desc> d;
+  int tiles = 0;
+  void add(double* A, int lda, int n0, int n) { if (n > 0) h.push_back(Desc{A, lda, n0, n, 0}); }
+  void finalize(hipStream_t st);
+  void run(hipStream_t st) const;
+};
+
+// Batched symmetric eigensolver for small matrices (cyclic Jacobi in LDS).
+// A_b (n_b x n_b, ld = ldA) is overwritten; eigenvalues (descending) in
+// W_b, eigenvectors in V_b (ld = n_b).
+void jacobi_eig_batched(double* const* A, const int* n, double* const* W, double* const* V,
+                        int batch, int nmax, hipStream_t st);
+
+}  // namespace ambddc

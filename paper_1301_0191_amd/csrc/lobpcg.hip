@@ -1,0 +1,676 @@
+// Pair kernels of the batched LOBPCG (one workgroup per face pair).
+//
+// Pair vectors live on [Gamma^s; Gamma^t].  With pair weights
+// d_s = K^s_jj / (K^s_jj + K^t_jj), d_t = 1 - d_s on a shared DOF j, the
+// operator I - E^st acts on the two copies (w_s, w_t) as
+//   (I-E)w = (d_t (w_s - w_t), d_s (w_t - w_s)),
+//   (I-E)^T y = (d_t y_s - d_s y_t, -d_t y_s + d_s y_t),
+// and is zero off the shared DOFs (E^st is the identity there, Section 7).
+// Pi is the orthogonal projection onto null(D), D = [C^s_sh, -C^t_sh]; the
+// rows of D have disjoint supports, so Pi = I - sum_r d_r d_r^T / |d_r|^2.
+#include <algorithm>
+#include <cmath>
+
+#include "jacobi_dev.hpp"
+#include "lobpcg.hpp"
+
+namespace ambddc {
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// X block: uniform(-1, 1) from a counter-based hash of (seed, pair, entry).
+__global__ __launch_bounds__(256) void k_random(const PairDev* P, double* V, int m, uint64_t seed) {
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  double* X = V + p.v_off;
+  for (int i = threadIdx.x; i < n * m; i += blockDim.x) {
+    const uint64_t h = mix64(seed ^ mix64((uint64_t(blockIdx.x) << 32) + uint64_t(i)));
+    X[i] = (double(h >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+  }
+}
+
+void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStream_t st) {
+  if (np == 0) return;
+  k_random<<<np, 256, 0, st>>>(P, V, m, seed);
+  AMB_LAUNCH_CHECK();
+}
+
+// v <- Pi v (and, when deflating, remove the orthonormal pair rigid modes).
+__device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, const double* C,
+                             const int* dr_s, const int* dr_t, const double* rb, bool deflate,
+                             double* sm) {
+  const int n = p.nGs + p.nGt;
+  const int nd = p.dr1 - p.dr0;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // coefficients coef[r * ncol + c] = (d_r . v_c) / |d_r|^2
+  double* coef = sm;
+  for (int idx = tid; idx < nd * ncol; idx += nt) {
+    const int r = idx / ncol, c = idx % ncol;
+    const double* cs = C + p.cs_off + dr_s[p.dr0 + r];
+    const double* ct = C + p.ct_off + dr_t[p.dr0 + r];
+    const double* vc = v + (size_t)c * ldv;
+    double dot = 0.0, nrm = 0.0;
+    for (int i = 0; i < p.nGs; ++i) {
+      const double a = cs[(size_t)i * p.ncs];
+      dot += a * vc[i];
+      nrm += a * a;
+    }
+    for (int i = 0; i < p.nGt; ++i) {
+      const double a = ct[(size_t)i * p.nct];
+      dot -= a * vc[p.nGs + i];
+      nrm += a * a;
+    }
+    coef[idx] = nrm > 0.0 ? dot / nrm : 0.0;
+  }
+  __syncthreads();
+  if (nd > 0) {
+    for (int idx = tid; idx < n * ncol; idx += nt) {
+      const int i = idx % n, c = idx / n;
+      double corr = 0.0;
+      if (i < p.nGs) {
+        for (int r = 0; r < nd; ++r)
+          corr += coef[r * ncol + c] * C[p.cs_off + dr_s[p.dr0 + r] + (size_t)i * p.ncs];
+      } else {
+        const int it = i - p.nGs;
+        for (int r = 0; r < nd; ++r)
+          corr -= coef[r * ncol + c] * C[p.ct_off + dr_t[p.dr0 + r] + (size_t)it * p.nct];
+      }
+      v[i + (size_t)c * ldv] -= corr;
+    }
+  }
+  __syncthreads();
+  if (deflate && p.nrb > 0) {
+    const double* R = rb + p.rb_off;
+    for (int idx = tid; idx < p.nrb * ncol; idx += nt) {
+      const int r = idx / ncol, c = idx % ncol;
+      const double* vc = v + (size_t)c * ldv;
+      const double* rr = R + (size_t)r * n;
+      double dot = 0.0;
+      for (int i = 0; i < n; ++i) dot += rr[i] * vc[i];
+      coef[idx] = dot;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * ncol; idx += nt) {
+      const int i = idx % n, c = idx / n;
+      double corr = 0.0;
+      for (int r = 0; r < p.nrb; ++r) corr += coef[r * ncol + c] * R[i + (size_t)r * n];
+      v[i + (size_t)c * ldv] -= corr;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_project(const PairDev* P, double* V, int m, int col,
+                                                 const double* C, const int* dr_s, const int* dr_t,
+                                                 const double* rb, const int* active, bool deflate) {
+  __shared__ double sm[64 * 16];
+  if (active && !active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  pair_project(p, V + p.v_off + (size_t)col * m * n, n, m, C, dr_s, dr_t, rb, deflate, sm);
+}
+
+void lp_project(const PairDev* P, int np, double* V, int m, int col, const double* C,
+                const int* dr_s, const int* dr_t, const double* rb, const int* active, bool deflate,
+                hipStream_t st) {
+  if (np == 0) return;
+  k_project<<<np, 256, 0, st>>>(P, V, m, col, C, dr_s, dr_t, rb, active, deflate);
+  AMB_LAUNCH_CHECK();
+}
+
+__device__ inline double pair_ds(const PairDev& p, const double* diagG, int is, int it) {
+  const double a = diagG[p.gs_off + is], b = diagG[p.gt_off + it];
+  return a / (a + b);
+}
+
+// Copy the column block `col` of V into the pair's slots of U^s and U^t;
+// with_ie also writes (I-E) of the block into the next m slot columns.
+__global__ __launch_bounds__(256) void k_to_slab(const PairDev* P, const double* V, int m, int col,
+                                                 bool with_ie, const double* diagG, const int* sh_s,
+                                                 const int* sh_t, double* U, const int* active) {
+  if (active && !active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  const double* v = V + p.v_off + (size_t)col * m * n;
+  double* us = U + p.us_off;
+  double* ut = U + p.ut_off;
+  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    const double x = v[idx];
+    if (i < p.nGs) us[i + (size_t)c * p.nGs] = x;
+    else ut[(i - p.nGs) + (size_t)c * p.nGt] = x;
+  }
+  if (!with_ie) return;
+  for (int idx = threadIdx.x; idx < p.nGs * m; idx += blockDim.x)
+    us[(size_t)m * p.nGs + idx] = 0.0;
+  for (int idx = threadIdx.x; idx < p.nGt * m; idx += blockDim.x)
+    ut[(size_t)m * p.nGt + idx] = 0.0;
+  __syncthreads();
+  const int nsh = p.sh1 - p.sh0;
+  for (int idx = threadIdx.x; idx < nsh * m; idx += blockDim.x) {
+    const int q = idx % nsh, c = idx / nsh;
+    const int is = sh_s[p.sh0 + q], it = sh_t[p.sh0 + q];
+    const double ds = pair_ds(p, diagG, is, it), dt = 1.0 - ds;
+    const double ws = v[is + (size_t)c * n], wt = v[p.nGs + it + (size_t)c * n];
+    us[(size_t)(m + c) * p.nGs + is] = dt * (ws - wt);
+    ut[(size_t)(m + c) * p.nGt + it] = ds * (wt - ws);
+  }
+}
+
+void lp_to_slab(const PairDev* P, int np, const double* V, int m, int col, bool with_ie,
+                const double* diagG, const int* sh_s, const int* sh_t, double* U, const int* active,
+                hipStream_t st) {
+  if (np == 0) return;
+  k_to_slab<<<np, 256, 0, st>>>(P, V, m, col, with_ie, diagG, sh_s, sh_t, U, active);
+  AMB_LAUNCH_CHECK();
+}
+
+// BV = Pi (S w),  AV = Pi (I-E)^T (S (I-E) w)   from the slots of Y^s, Y^t.
+__global__ __launch_bounds__(256) void k_from_slab_ab(const PairDev* P, const double* Y, int m,
+                                                      int col, double* AV, double* BV,
+                                                      const double* diagG, const int* sh_s,
+                                                      const int* sh_t, const double* C,
+                                                      const int* dr_s, const int* dr_t,
+                                                      const int* active) {
+  __shared__ double sm[64 * 16];
+  if (active && !active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  const double* ys = Y + p.ys_off;
+  const double* yt = Y + p.yt_off;
+  double* bv = BV + p.v_off + (size_t)col * m * n;
+  double* av = AV + p.v_off + (size_t)col * m * n;
+  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    bv[idx] = (i < p.nGs) ? ys[i + (size_t)c * p.nls] : yt[(i - p.nGs) + (size_t)c * p.nlt];
+    av[idx] = 0.0;
+  }
+  __syncthreads();
+  const int nsh = p.sh1 - p.sh0;
+  for (int idx = threadIdx.x; idx < nsh * m; idx += blockDim.x) {
+    const int q = idx % nsh, c = idx / nsh;
+    const int is = sh_s[p.sh0 + q], it = sh_t[p.sh0 + q];
+    const double ds = pair_ds(p, diagG, is, it), dt = 1.0 - ds;
+    const double a = ys[is + (size_t)(m + c) * p.nls];
+    const double b = yt[it + (size_t)(m + c) * p.nlt];
+    av[is + (size_t)c * n] = dt * a - ds * b;
+    av[p.nGs + it + (size_t)c * n] = -dt * a + ds * b;
+  }
+  __syncthreads();
+  pair_project(p, bv, n, m, C, dr_s, dr_t, nullptr, false, sm);
+  pair_project(p, av, n, m, C, dr_s, dr_t, nullptr, false, sm);
+}
+
+void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, double* AV,
+                     double* BV, const double* diagG, const int* sh_s, const int* sh_t,
+                     const double* C, const int* dr_s, const int* dr_t, const int* active,
+                     hipStream_t st) {
+  if (np == 0) return;
+  k_from_slab_ab<<<np, 256, 0, st>>>(P, Y, m, col, AV, BV, diagG, sh_s, sh_t, C, dr_s, dr_t,
+                                     active);
+  AMB_LAUNCH_CHECK();
+}
+
+// Pair coarse correction: y_c = Psi^T u (from -Y rows nG..nl of both
+// subdomains, summed over shared coarse DOFs), z_c = K_p^+ y_c, written to
+// the coarse slabs of s and t.
+__global__ __launch_bounds__(256) void k_coarse(const PairDev* P, const double* Y, int m,
+                                                const double* Kp, const int* pc_s, const int* pc_t,
+                                                double* Zc, const int* active) {
+  __shared__ double yc[64 * 16];
+  __shared__ double zc[64 * 16];
+  if (active && !active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int ncp = p.ncp;
+  for (int i = threadIdx.x; i < ncp * m; i += blockDim.x) yc[i] = 0.0;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < p.ncs * m; idx += blockDim.x) {
+    const int r = idx % p.ncs, c = idx / p.ncs;
+    yc[pc_s[p.pcs0 + r] + c * ncp] -= Y[p.ys_off + p.nGs + r + (size_t)c * p.nls];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < p.nct * m; idx += blockDim.x) {
+    const int r = idx % p.nct, c = idx / p.nct;
+    yc[pc_t[p.pct0 + r] + c * ncp] -= Y[p.yt_off + p.nGt + r + (size_t)c * p.nlt];
+  }
+  __syncthreads();
+  const double* K = Kp + p.kp_off;
+  for (int idx = threadIdx.x; idx < ncp * m; idx += blockDim.x) {
+    const int i = idx % ncp, c = idx / ncp;
+    double v = 0.0;
+    for (int j = 0; j < ncp; ++j) v += K[i + (size_t)j * ncp] * yc[j + c * ncp];
+    zc[idx] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < p.ncs * m; idx += blockDim.x) {
+    const int r = idx % p.ncs, c = idx / p.ncs;
+    Zc[p.zs_off + r + (size_t)c * p.ncs] = zc[pc_s[p.pcs0 + r] + c * ncp];
+  }
+  for (int idx = threadIdx.x; idx < p.nct * m; idx += blockDim.x) {
+    const int r = idx % p.nct, c = idx / p.nct;
+    Zc[p.zt_off + r + (size_t)c * p.nct] = zc[pc_t[p.pct0 + r] + c * ncp];
+  }
+}
+
+void lp_coarse(const PairDev* P, int np, const double* Y, int m, const double* Kp,
+               const int* pc_s, const int* pc_t, double* Zc, const int* active, hipStream_t st) {
+  if (np == 0) return;
+  k_coarse<<<np, 256, 0, st>>>(P, Y, m, Kp, pc_s, pc_t, Zc, active);
+  AMB_LAUNCH_CHECK();
+}
+
+// W = -(Y rows 0..nG of s and t)  (the slab holds -(Z u + Psi z_c))
+__global__ __launch_bounds__(256) void k_from_slab_w(const PairDev* P, const double* Y, int m,
+                                                     double* V, const int* active) {
+  if (active && !active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  double* w = V + p.v_off + (size_t)m * n;
+  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    w[idx] = -((i < p.nGs) ? Y[p.ys_off + i + (size_t)c * p.nls]
+                           : Y[p.yt_off + (i - p.nGs) + (size_t)c * p.nlt]);
+  }
+}
+
+void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V, const int* active,
+                    hipStream_t st) {
+  if (np == 0) return;
+  k_from_slab_w<<<np, 256, 0, st>>>(P, Y, m, V, active);
+  AMB_LAUNCH_CHECK();
+}
+
+// R = AX - BX diag(lam) into the W block; per-column relative residuals;
+// a pair stays active until its first nconv columns have converged.
+__global__ __launch_bounds__(256) void k_residual(const PairDev* P, double* V, const double* AV,
+                                                  const double* BV, const double* lam, int m,
+                                                  int nconv, double tol, int* active,
+                                                  double* resn) {
+  __shared__ double red[8];
+  __shared__ int all_ok;
+  if (!active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  const double* ax = AV + p.v_off;
+  const double* bx = BV + p.v_off;
+  double* w = V + p.v_off + (size_t)m * n;
+  const double* l = lam + (size_t)blockIdx.x * m;
+  if (threadIdx.x == 0) all_ok = 1;
+  __syncthreads();
+  for (int c = 0; c < m; ++c) {
+    double rr = 0.0, aa = 0.0, bb = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double a = ax[i + (size_t)c * n], b = bx[i + (size_t)c * n];
+      const double r = a - l[c] * b;
+      w[i + (size_t)c * n] = r;
+      rr += r * r;
+      aa += a * a;
+      bb += b * b;
+    }
+    rr = block_sum(rr, red);
+    aa = block_sum(aa, red);
+    bb = block_sum(bb, red);
+    const double den = sqrt(aa) + fabs(l[c]) * sqrt(bb);
+    const double rel = den > 0.0 ? sqrt(rr) / den : 0.0;
+    if (threadIdx.x == 0) {
+      resn[(size_t)blockIdx.x * m + c] = rel;
+      if (c < nconv && !(rel <= tol)) all_ok = 0;
+    }
+    // soft locking: a converged column contributes no search direction
+    if (rel <= tol)
+      for (int i = threadIdx.x; i < n; i += blockDim.x) w[i + (size_t)c * n] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && all_ok) active[blockIdx.x] = 0;
+}
+
+void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,
+                 const double* lam, int m, int nconv, double tol, int* active, double* resn,
+                 hipStream_t st) {
+  if (np == 0) return;
+  k_residual<<<np, 256, 0, st>>>(P, V, AV, BV, lam, m, nconv, tol, active, resn);
+  AMB_LAUNCH_CHECK();
+}
+
+// Rayleigh-Ritz on span(V) with SVQB orthonormalisation in the B inner
+// product: D = diag(GB)^{-1/2}, D GB D = U Theta U^T, keep theta > 1e-10
+// theta_max, T = D U Theta^{-1/2}; eig(T^T GA T) = Y Lambda Y^T, descending;
+// coefficients Cf = T Y[:, :m] (columns 0..m-1 of Cf2) and the same with the
+// X rows zeroed (columns m..2m-1, giving the new P).  Cf2 has ld 3m.
+__global__ __launch_bounds__(256) void k_rr(const PairDev* P, const double* GA, const double* GB,
+                                            int nb, int m, double* Cf2, double* lam,
+                                            const int* active) {
+  extern __shared__ double sm[];
+  if (active && !active[blockIdx.x]) return;
+  const int M3 = 3 * m;
+  const double* ga = GA + (size_t)blockIdx.x * M3 * M3;
+  const double* gb = GB + (size_t)blockIdx.x * M3 * M3;
+  double* A = sm;                 // nb*nb
+  double* B = A + nb * nb;        // nb*nb
+  double* Cb = B + nb * nb;       // nb*nb
+  double* dsc = Cb + nb * nb;     // nb
+  double* rot = dsc + nb;         // 4*(nb/2+1)
+  double* red = rot + 4 * (nb / 2 + 1);
+  int* keep = reinterpret_cast<int*>(red + 16);   // nb
+  int* perm = keep + nb;                          // nb
+  __shared__ int r_s;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < nb; i += nt) {
+    const double d = gb[i + (size_t)i * nb];
+    dsc[i] = d > 1e-300 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * nb; idx += nt) {
+    const int i = idx % nb, j = idx / nb;
+    A[idx] = 0.5 * (gb[i + (size_t)j * nb] + gb[j + (size_t)i * nb]) * dsc[i] * dsc[j];
+  }
+  __syncthreads();
+  jacobi_lds(A, B, nb, rot, red);
+  if (tid == 0) {
+    double tmax = 0.0;
+    for (int j = 0; j < nb; ++j) tmax = fmax(tmax, A[j + j * nb]);
+    int r = 0;
+    for (int j = 0; j < nb; ++j)
+      if (A[j + j * nb] > 1e-10 * tmax) keep[r++] = j;
+    r_s = r;
+  }
+  __syncthreads();
+  const int r = r_s;
+  // T (nb x r) into Cb, ld nb
+  for (int idx = tid; idx < nb * r; idx += nt) {
+    const int i = idx % nb, c = idx / nb;
+    const int j = keep[c];
+    Cb[i + c * nb] = dsc[i] * B[i + j * nb] / sqrt(A[j + j * nb]);
+  }
+  __syncthreads();
+  // B <- GA T (nb x r), ld nb
+  for (int idx = tid; idx < nb * r; idx += nt) {
+    const int i = idx % nb, c = idx / nb;
+    double v = 0.0;
+    for (int l = 0; l < nb; ++l)
+      v += 0.5 * (ga[i + (size_t)l * nb] + ga[l + (size_t)i * nb]) * Cb[l + c * nb];
+    B[idx] = v;
+  }
+  __syncthreads();
+  // A <- T^T (GA T) (r x r), ld r
+  for (int idx = tid; idx < r * r; idx += nt) {
+    const int i = idx % r, c = idx / r;
+    double v = 0.0;
+    for (int l = 0; l < nb; ++l) v += Cb[l + i * nb] * B[l + c * nb];
+    A[idx] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < r * r; idx += nt) {
+    const int i = idx % r, c = idx / r;
+    if (i < c) {
+      const double s = 0.5 * (A[i + c * r] + A[c + i * r]);
+      A[i + c * r] = s;
+      A[c + i * r] = s;
+    }
+  }
+  __syncthreads();
+  jacobi_lds(A, B, r, rot, red);   // eigenvectors Y in B (ld r)
+  sort_desc_lds(A, r, perm);
+  const int mm = min(m, r);
+  double* cf = Cf2 + (size_t)blockIdx.x * M3 * 2 * m;
+  for (int idx = tid; idx < nb * 2 * m; idx += nt) {
+    const int i = idx % nb, c = idx / nb;
+    const int cc = c % m;
+    double v = 0.0;
+    if (cc < mm) {
+      const int pc = perm[cc];
+      for (int l = 0; l < r; ++l) v += Cb[i + l * nb] * B[l + pc * r];
+    }
+    if (c >= m && i < m) v = 0.0;
+    cf[i + (size_t)c * M3] = v;
+  }
+  for (int c = tid; c < m; c += nt)
+    lam[(size_t)blockIdx.x * m + c] = c < mm ? A[perm[c] + perm[c] * r] : 0.0;
+}
+
+void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,
+           double* Cf, double* lam, const int* active, hipStream_t st) {
+  if (np == 0) return;
+  const size_t sm = sizeof(double) * (3 * nb * nb + nb + 4 * (nb / 2 + 1) + 16) +
+                    sizeof(int) * 2 * nb;
+  k_rr<<<np, 256, sm, st>>>(P, GA, GB, nb, m, Cf, lam, active);
+  AMB_LAUNCH_CHECK();
+}
+
+// X <- T[:, 0:m], P <- T[:, m:2m] for V (and AV, BV unless only_v); the T
+// blocks are n x 2m per operand, stored consecutively from 2 * v_off.
+__global__ __launch_bounds__(256) void k_commit(const PairDev* P, double* V, double* AV,
+                                                double* BV, const double* T, int m, bool with_p,
+                                                bool only_v, const int* active) {
+  if (active && !active[blockIdx.x]) return;
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  // T layout per pair: [TV | TAV | TBV], each n x 2m, at offset v_off (same 3m*n footprint x2)
+  const double* t = T + 2 * p.v_off;
+  double* dst[3] = {V + p.v_off, AV + p.v_off, BV + p.v_off};
+  for (int o = 0; o < (only_v ? 1 : 3); ++o) {
+    const double* src = t + (size_t)o * n * 2 * m;
+    for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+      dst[o][idx] = src[idx];
+      if (with_p) dst[o][(size_t)2 * m * n + idx] = src[(size_t)m * n + idx];
+    }
+  }
+}
+
+void lp_commit(const PairDev* P, int np, double* V, double* AV, double* BV, const double* T,
+               int m, bool with_p, bool only_v, const int* active, hipStream_t st) {
+  if (np == 0) return;
+  k_commit<<<np, 256, 0, st>>>(P, V, AV, BV, T, m, with_p, only_v, active);
+  AMB_LAUNCH_CHECK();
+}
+
+// Pair coarse matrix Psi^T S^st Psi = R_c^s^T K_c^s R_c^s + R_c^t^T K_c^t R_c^t.
+__global__ __launch_bounds__(256) void k_pair_coarse(const PairDev* P, const double* kc,
+                                                     const int64_t* kc_off, const int* pc_s,
+                                                     const int* pc_t, double* Kp) {
+  const PairDev p = P[blockIdx.x];
+  double* K = Kp + p.kp_off;
+  const int ncp = p.ncp;
+  for (int i = threadIdx.x; i < ncp * ncp; i += blockDim.x) K[i] = 0.0;
+  __syncthreads();
+  const double* ks = kc + kc_off[p.s];
+  for (int idx = threadIdx.x; idx < p.ncs * p.ncs; idx += blockDim.x) {
+    const int a = idx % p.ncs, b = idx / p.ncs;
+    K[pc_s[p.pcs0 + a] + pc_s[p.pcs0 + b] * ncp] += ks[idx];
+  }
+  __syncthreads();
+  const double* kt = kc + kc_off[p.t];
+  for (int idx = threadIdx.x; idx < p.nct * p.nct; idx += blockDim.x) {
+    const int a = idx % p.nct, b = idx / p.nct;
+    K[pc_t[p.pct0 + a] + pc_t[p.pct0 + b] * ncp] += kt[idx];
+  }
+}
+
+void lp_pair_coarse(const PairDev* P, int np, const double* kc, const int64_t* kc_off,
+                    const int* pc_s, const int* pc_t, double* Kp, hipStream_t st) {
+  if (np == 0) return;
+  k_pair_coarse<<<np, 256, 0, st>>>(P, kc, kc_off, pc_s, pc_t, Kp);
+  AMB_LAUNCH_CHECK();
+}
+
+// Generalised inverse of the pair coarse matrix K (Section 5 uses a dense
+// eigendecomposition that drops the smallest eigenvalues).  K is first scaled
+// to unit diagonal, D^{-1/2} K D^{-1/2} = V L V^T (Jacobi, accurate for the
+// small eigenvalues of a well-scaled SPD matrix), and exactly the expected
+// null space is dropped: the nrb pair rigid modes when both subdomains
+// float, nothing otherwise.  G = D^{-1/2} V L'^{-1} V^T D^{-1/2} satisfies
+// K G K = K, which is all the preconditioner needs (its input lies in
+// range(K) and null(K) maps onto the deflated rigid modes).  nnull[p] counts
+// the scaled eigenvalues below tol * max for the Assumption 1 check.
+__global__ __launch_bounds__(256) void k_pinv(const PairDev* P, double* Kp, double tol, int* nnull) {
+  extern __shared__ double sm[];
+  const PairDev p = P[blockIdx.x];
+  const int n = p.ncp;
+  double* A = sm;
+  double* V = A + n * n;
+  double* rot = V + n * n;
+  double* red = rot + 4 * (n / 2 + 1);
+  double* dsc = red + 16;
+  int* perm = reinterpret_cast<int*>(dsc + n);
+  double* K = Kp + p.kp_off;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = K[i + i * n];
+    dsc[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+    const int r = i % n, c = i / n;
+    A[i] = 0.5 * (K[r + c * n] + K[c + r * n]) * dsc[r] * dsc[c];
+  }
+  __syncthreads();
+  jacobi_lds(A, V, n, rot, red);
+  sort_desc_lds(A, n, perm);
+  const double lmax = A[perm[0] + perm[0] * n];
+  const int keep = n - p.nrb;   // drop the nrb smallest
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int r = idx % n, c = idx / n;
+    double v = 0.0;
+    for (int q = 0; q < keep; ++q) {
+      const int j = perm[q];
+      const double l = A[j + j * n];
+      if (l > 0.0) v += V[r + j * n] * V[c + j * n] / l;
+    }
+    K[idx] = v * dsc[r] * dsc[c];
+  }
+  if (threadIdx.x == 0) {
+    int z = 0;
+    for (int j = 0; j < n; ++j) z += !(A[j + j * n] > tol * lmax);
+    nnull[blockIdx.x] = z;
+  }
+}
+
+void lp_pinv(const PairDev* P, int np, double* Kp, int ncp_max, double tol, int* nnull,
+             hipStream_t st) {
+  if (np == 0) return;
+  const size_t sm = sizeof(double) * (2 * ncp_max * ncp_max + 4 * (ncp_max / 2 + 1) + 16 + ncp_max) +
+                    sizeof(int) * (ncp_max + 1);
+  k_pinv<<<np, 256, sm, st>>>(P, Kp, tol, nnull);
+  AMB_LAUNCH_CHECK();
+}
+
+// Orthonormal pair-continuous rigid modes on [Gamma^s; Gamma^t] (pairs whose
+// two subdomains float); modified Gram-Schmidt applied twice.
+__global__ __launch_bounds__(256) void k_rigid(const PairDev* P, const double* rigid, int nrbl,
+                                               int ndof, const int* gdof, double* rb) {
+  __shared__ double red[8];
+  const PairDev p = P[blockIdx.x];
+  if (p.nrb == 0) return;
+  const int n = p.nGs + p.nGt;
+  double* R = rb + p.rb_off;
+  for (int idx = threadIdx.x; idx < n * p.nrb; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    const int j = (i < p.nGs) ? gdof[p.gs_off + i] : gdof[p.gt_off + i - p.nGs];
+    R[idx] = rigid[j + (size_t)c * ndof];
+  }
+  __syncthreads();
+  for (int c = 0; c < p.nrb; ++c) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = 0; q < c; ++q) {
+        double d = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) d += R[i + (size_t)q * n] * R[i + (size_t)c * n];
+        d = block_sum(d, red);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) R[i + (size_t)c * n] -= d * R[i + (size_t)q * n];
+        __syncthreads();
+      }
+    }
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += R[i + (size_t)c * n] * R[i + (size_t)c * n];
+    s = block_sum(s, red);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) R[i + (size_t)c * n] *= inv;
+    __syncthreads();
+  }
+}
+
+void lp_rigid(const PairDev* P, int np, const double* rigid, int ndof, const int* gdof,
+              double* rb, hipStream_t st) {
+  if (np == 0) return;
+  k_rigid<<<np, 256, 0, st>>>(P, rigid, 0, ndof, gdof, rb);
+  AMB_LAUNCH_CHECK();
+}
+
+// Selection (Alg. 2) and constraint rows: k = #{lambda_j > tau, j < nev_max};
+// c_l = (A w_l) restricted to the face DOFs of s (edge and corner entries
+// dropped), orthonormalised by Gram-Schmidt (twice) with the rank test
+// |R_jj| > 1e-10 max |R_jj|; rows stored row-major (nev_max x nface).
+__global__ __launch_bounds__(256) void k_select(const PairDev* P, const double* AV,
+                                                const double* lam, int m, int nev_max, double tau,
+                                                const int* face_s, double* fc, int* kout,
+                                                double* lam_next) {
+  extern __shared__ double sm[];
+  __shared__ double red[8];
+  __shared__ double rdiag[32];
+  const PairDev p = P[blockIdx.x];
+  const int n = p.nGs + p.nGt;
+  const double* l = lam + (size_t)blockIdx.x * m;
+  const int cap = min(nev_max, m);
+  int k = 0;
+  while (k < cap && l[k] > tau) ++k;
+  if (threadIdx.x == 0) lam_next[blockIdx.x] = (k < m) ? l[k] : 0.0;
+  const int nf = p.nface;
+  double* Q = sm;   // k x nf (row-major)
+  for (int idx = threadIdx.x; idx < k * nf; idx += blockDim.x) {
+    const int j = idx / nf, q = idx % nf;
+    Q[idx] = AV[p.v_off + face_s[p.face0 + q] + (size_t)j * n];
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < j; ++i) {
+        double d = 0.0;
+        for (int q = threadIdx.x; q < nf; q += blockDim.x) d += Q[i * nf + q] * Q[j * nf + q];
+        d = block_sum(d, red);
+        for (int q = threadIdx.x; q < nf; q += blockDim.x) Q[j * nf + q] -= d * Q[i * nf + q];
+        __syncthreads();
+      }
+    }
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nf; q += blockDim.x) s += Q[j * nf + q] * Q[j * nf + q];
+    s = sqrt(block_sum(s, red));
+    if (threadIdx.x == 0) rdiag[j] = s;
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int q = threadIdx.x; q < nf; q += blockDim.x) Q[j * nf + q] *= inv;
+    __syncthreads();
+  }
+  double rmax = 0.0;
+  for (int j = 0; j < k; ++j) rmax = fmax(rmax, rdiag[j]);
+  int kk = 0;
+  for (int j = 0; j < k; ++j) {
+    if (!(rdiag[j] > 1e-10 * rmax)) continue;
+    for (int q = threadIdx.x; q < nf; q += blockDim.x) fc[p.fc_off + (size_t)kk * nf + q] = Q[j * nf + q];
+    ++kk;
+  }
+  if (threadIdx.x == 0) kout[blockIdx.x] = kk;
+}
+
+void lp_select(const PairDev* P, int np, const double* AV, const double* lam, int m, int nev_max,
+               double tau, const int* face_s, int nface_max, double* fc, int* kout,
+               double* lam_next, hipStream_t st) {
+  if (np == 0) return;
+  const size_t sm = sizeof(double) * size_t(std::min(nev_max, m)) * nface_max;
+  k_select<<<np, 256, sm, st>>>(P, AV, lam, m, nev_max, tau, face_s, fc, kout, lam_next);
+  AMB_LAUNCH_CHECK();
+}
+
+}  // namespace ambddc

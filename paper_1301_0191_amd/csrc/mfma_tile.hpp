@@ -1,0 +1,109 @@
+// One workgroup tile of C = alpha * op(A) * diag(sigma) * op(B) + beta * C on
+// CDNA MFMA (v_mfma_f64_16x16x4f64), FP64.  256 threads = 4 waves arranged
+// WM x WN; every wave owns a 32x32 sub-tile (2x2 MFMA blocks).  K is staged
+// through LDS in chunks of KC so that global reads are coalesced for either
+// operand orientation.
+//
+// MFMA 16x16x4 operand layout (per wave of 64 lanes):
+//   A (16x4):  lane l holds A[l % 16][l / 16]
+//   B (4x16):  lane l holds B[l / 16][l % 16]
+//   D (16x16): lane l, element r holds D[4 * r + l / 16][l % 16]   (FP64 variant)
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ambddc {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int WM, int WN>
+struct TileShape {
+  static constexpr int TM = 32 * WM;
+  static constexpr int TN = 32 * WN;
+  static constexpr int KC = 16;
+  static constexpr int PAD = 4;
+};
+
+template <int WM, int WN>
+struct TileSmem {
+  double As[TileShape<WM, WN>::KC][TileShape<WM, WN>::TM + TileShape<WM, WN>::PAD];
+  double Bs[TileShape<WM, WN>::KC][TileShape<WM, WN>::TN + TileShape<WM, WN>::PAD];
+};
+
+// op(A)(m, k) = TA ? A[k + m*lda] : A[m + k*lda]
+// op(B)(k, n) = TB ? B[n + k*ldb] : B[k + n*ldb]
+// sign_split >= 0: column k of op(A) is scaled by +1 if k < sign_split, else -1.
+template <bool TA, bool TB, int WM, int WN>
+__device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int lda,
+                                          const double* __restrict__ B, int ldb, double* C, int ldc,
+                                          int M, int N, int K, int m0, int n0, double alpha,
+                                          double beta, int sign_split, TileSmem<WM, WN>& sm) {
+  using S = TileShape<WM, WN>;
+  constexpr int TM = S::TM, TN = S::TN, KC = S::KC;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    // stage op(A)[m0:m0+TM, k0:k0+KC] as As[k][m]
+#pragma unroll
+    for (int idx = tid; idx < KC * TM; idx += 256) {
+      int m, k;
+      if (!TA) { m = idx % TM; k = idx / TM; }
+      else { k = idx % KC; m = idx / KC; }
+      const int gm = m0 + m, gk = k0 + k;
+      double v = 0.0;
+      if (gm < M && gk < K) v = TA ? A[gk + (size_t)gm * lda] : A[gm + (size_t)gk * lda];
+      if (sign_split >= 0 && gk >= sign_split) v = -v;
+      sm.As[k][m] = v;
+    }
+#pragma unroll
+    for (int idx = tid; idx < KC * TN; idx += 256) {
+      int n, k;
+      if (TB) { n = idx % TN; k = idx / TN; }
+      else { k = idx % KC; n = idx / KC; }
+      const int gn = n0 + n, gk = k0 + k;
+      double v = 0.0;
+      if (gn < N && gk < K) v = TB ? B[gn + (size_t)gk * ldb] : B[gk + (size_t)gn * ldb];
+      sm.Bs[k][n] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sm.As[kr][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sm.Bs[kr][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + i * 16 + 4 * r + (lane >> 4);
+        const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          double* c = C + gm + (size_t)gn * ldc;
+          double v = alpha * acc[i][j][r];
+          if (beta != 0.0) v += beta * (*c);
+          *c = v;
+        }
+      }
+}
+
+}  // namespace ambddc

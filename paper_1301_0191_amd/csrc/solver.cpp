@@ -1,0 +1,1383 @@
+// Set-up (Alg. 3), Multilevel BDDC application (Alg. 1), PCG, and the C ABI.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <string>
+
+#include "../../include/ambddc.h"
+#include "level.hpp"
+
+using namespace ambddc;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct LocalIndex {   // sorted (dof, local) pairs of one subdomain
+  std::vector<std::pair<int, int>> v;
+  void build(const std::vector<int>& dofs) {
+    v.resize(dofs.size());
+    for (size_t i = 0; i < dofs.size(); ++i) v[i] = {dofs[i], int(i)};
+    std::sort(v.begin(), v.end());
+  }
+  int find(int dof) const {
+    auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(dof, -1));
+    return (it != v.end() && it->first == dof) ? it->second : -1;
+  }
+};
+
+// Column-incidence maps: element matrices -> dense blocks of `ntgt` targets.
+void build_assembly(AssemblyMaps& am, int nelem, const std::vector<int>& elem_tgt,
+                    const std::vector<int64_t>& edptr, const std::vector<int>& edofs,
+                    const std::vector<int64_t>& emat_off, const std::vector<LocalIndex>& loc,
+                    const std::vector<int>& tgt_ncols, hipStream_t st) {
+  const int ntgt = int(tgt_ncols.size());
+  std::vector<int64_t> colbase(ntgt + 1, 0);
+  for (int s = 0; s < ntgt; ++s) colbase[s + 1] = colbase[s] + tgt_ncols[s];
+  const int64_t ncols = colbase[ntgt];
+  std::vector<int> eloc(edofs.size(), -1);
+  std::vector<int64_t> eloc_off(nelem + 1), cnt(ncols + 1, 0);
+  std::vector<int> ene(nelem);
+  for (int e = 0; e < nelem; ++e) {
+    eloc_off[e] = edptr[e];
+    ene[e] = int(edptr[e + 1] - edptr[e]);
+    const int s = elem_tgt[e];
+    for (int64_t p = edptr[e]; p < edptr[e + 1]; ++p) {
+      if (edofs[p] < 0) continue;
+      const int j = loc[s].find(edofs[p]);
+      if (j < 0) throw Error(AMBDDC_E_INVALID_ARG, "element DOF missing from its subdomain");
+      eloc[p] = j;
+      cnt[colbase[s] + j + 1]++;
+    }
+  }
+  eloc_off[nelem] = edptr[nelem];
+  for (int64_t c = 0; c < ncols; ++c) cnt[c + 1] += cnt[c];
+  std::vector<int> inc_e(cnt[ncols]), inc_a(cnt[ncols]);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int e = 0; e < nelem; ++e) {
+    const int s = elem_tgt[e];
+    for (int64_t p = edptr[e]; p < edptr[e + 1]; ++p) {
+      if (eloc[p] < 0) continue;
+      const int64_t c = colbase[s] + eloc[p];
+      inc_e[fill[c]] = e;
+      inc_a[fill[c]] = int(p - edptr[e]);
+      fill[c]++;
+    }
+  }
+  std::vector<int> col_sub(ncols), col_j(ncols);
+  for (int s = 0; s < ntgt; ++s)
+    for (int j = 0; j < tgt_ncols[s]; ++j) {
+      col_sub[colbase[s] + j] = s;
+      col_j[colbase[s] + j] = j;
+    }
+  am.ncols = int(ncols);
+  am.col_sub.upload(col_sub, st);
+  am.col_j.upload(col_j, st);
+  am.inc_ptr.upload(cnt, st);
+  am.inc_e.upload(inc_e, st);
+  am.inc_a.upload(inc_a, st);
+  am.emat_off.upload(emat_off, st);
+  am.elem_ne.upload(ene, st);
+  am.eloc_off.upload(eloc_off, st);
+  am.eloc.upload(eloc, st);
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+struct ambddc_ctx {
+  hipStream_t st = nullptr;
+  ambddc_options opt{};
+  int n_nodes = 0, n_elems = 0, dof = 1, levels = 2;
+  std::vector<int> free_of_full;
+  std::vector<std::vector<int>> parents;
+  LevelPlan plan0;
+  DBuf<double> coords;
+  DBuf<int> en, edofs;
+  CsrMaps csr;
+  DBuf<double> csr_vals, Ke;
+  std::vector<std::unique_ptr<Level>> L;
+  Top top;
+  bool ready = false;
+  ambddc_stats stats{};
+  // PCG workspace
+  int pcg_cap = 0, pcg_maxit = 0;
+  DBuf<double> px, pr, pz, pp, pq, pdot, ppart, pah, pbh, plz;
+  DBuf<int> pact, pnal;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// level structure
+// ---------------------------------------------------------------------------
+
+void build_level_maps(ambddc_ctx& c, Level& L, const double* emat,
+                      const std::vector<int64_t>& emat_off) {
+  hipStream_t st = c.st;
+  const LevelPlan& P = L.plan;
+  L.nsub = P.in.n_sub;
+  L.ndof = P.in.n_dof;
+  L.nrb = P.in.n_rb;
+  const int ns = L.nsub;
+  L.nI.resize(ns); L.nG.resize(ns); L.ns.resize(ns); L.augN.resize(ns);
+  L.aug_off.assign(ns + 1, 0); L.Ioff.assign(ns + 1, 0); L.Goff.assign(ns + 1, 0);
+  L.y1off.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    L.nI[s] = P.subs[s].nI;
+    L.nG[s] = P.subs[s].nG;
+    L.ns[s] = L.nI[s] + L.nG[s];
+    L.augN[s] = L.ns[s] + L.nI[s];
+    L.aug_off[s + 1] = L.aug_off[s] + int64_t(L.augN[s]) * L.augN[s];
+    L.Ioff[s + 1] = L.Ioff[s] + L.nI[s];
+    L.Goff[s + 1] = L.Goff[s] + L.nG[s];
+    L.y1off[s + 1] = L.y1off[s] + L.nG[s] + L.nI[s];
+  }
+  L.aug_total = L.aug_off[ns];
+  L.nI_tot = L.Ioff[ns];
+  L.nG_tot = L.Goff[ns];
+  L.y1_tot = L.y1off[ns];
+  L.aug.alloc(size_t(L.aug_total));
+  L.d_aug_off.upload(std::vector<int64_t>(L.aug_off.begin(), L.aug_off.end() - 1), st);
+  L.d_augN.upload(L.augN, st);
+  L.d_nI.upload(L.nI, st);
+  L.d_nG.upload(L.nG, st);
+  L.d_ns.upload(L.ns, st);
+  // assembly: elements of this level into the leading blocks of Aug^s
+  std::vector<LocalIndex> loc(ns);
+  for (int s = 0; s < ns; ++s) loc[s].build(P.subs[s].dofs);
+  build_assembly(L.am, P.in.n_elem, P.in.elem_sub, P.in.elem_dof_ptr, P.in.elem_dofs, emat_off, loc,
+                 L.ns, st);
+  L.emat = emat;
+  // stacked maps
+  std::vector<int64_t> Imap(L.nI_tot), I2y1(L.nI_tot), g2y1(L.nG_tot), g2y2(L.nG_tot),
+      diagpos(L.nG_tot);
+  std::vector<int> Gdof(L.nG_tot);
+  std::vector<int> incptr(L.ndof + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    const auto& d = P.subs[s].dofs;
+    for (int i = 0; i < L.nI[s]; ++i) {
+      Imap[L.Ioff[s] + i] = d[i];
+      I2y1[L.Ioff[s] + i] = L.y1off[s] + L.nG[s] + i;
+    }
+    for (int i = 0; i < L.nG[s]; ++i) {
+      const int64_t k = L.Goff[s] + i;
+      Gdof[k] = d[L.nI[s] + i];
+      g2y1[k] = L.y1off[s] + i;
+      diagpos[k] = L.aug_off[s] + (L.nI[s] + i) + int64_t(L.nI[s] + i) * L.augN[s];
+      incptr[Gdof[k] + 1]++;
+    }
+  }
+  for (int j = 0; j < L.ndof; ++j) incptr[j + 1] += incptr[j];
+  std::vector<int> incpos(L.nG_tot);
+  {
+    std::vector<int> f(incptr.begin(), incptr.end() - 1);
+    for (int64_t k = 0; k < L.nG_tot; ++k) incpos[f[Gdof[k]]++] = int(k);
+  }
+  L.Imap.upload(Imap, st);
+  L.I2y1.upload(I2y1, st);
+  L.g2y1.upload(g2y1, st);
+  L.diagpos.upload(diagpos, st);
+  L.Gdof.upload(Gdof, st);
+  L.incptr.upload(incptr, st);
+  L.incpos.upload(incpos, st);
+  L.diagG.alloc(L.nG_tot);
+  L.delta.alloc(L.nG_tot);
+  L.rho.alloc(ns);
+  (void)g2y2;
+  // batched partial factorisation of Aug^s = [[K, I_I^T], [I_I, 0]]: nI positive pivots
+  L.ldl_aug = LdltOp();
+  L.sym_aug = SymOp();
+  L.g1 = GemvOp();
+  L.g4 = GemvOp();
+  for (int s = 0; s < ns; ++s) {
+    double* A = L.aug.p + L.aug_off[s];
+    const int N = L.augN[s];
+    L.ldl_aug.add(A, N, N, L.nI[s], L.nI[s]);
+    L.sym_aug.add(A, N, L.nI[s], L.nG[s] + L.nI[s]);
+  }
+  L.ldl_aug.finalize(st);
+  L.sym_aug.finalize(st);
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void alloc_workspace(Level& L, int nrhs) {
+  if (L.nrhs_cap >= nrhs) return;
+  L.nrhs_cap = nrhs;
+  L.w_xI.alloc(size_t(std::max<int64_t>(L.nI_tot, 1)) * nrhs);
+  L.w_y1.alloc(size_t(std::max<int64_t>(L.y1_tot, 1)) * nrhs);
+  L.w_rBs.alloc(size_t(std::max<int64_t>(L.nG_tot, 1)) * nrhs);
+  L.w_uBs.alloc(size_t(std::max<int64_t>(L.nG_tot, 1)) * nrhs);
+}
+
+void alloc_coarse_workspace(Level& L, int nrhs) {
+  L.w_y2.alloc(size_t(std::max<int64_t>(L.y2_tot, 1)) * nrhs);
+  L.w_rc.alloc(size_t(std::max(L.ncoarse, 1)) * nrhs);
+  L.w_uc.alloc(size_t(std::max(L.ncoarse, 1)) * nrhs);
+  L.w_ucl.alloc(size_t(std::max<int64_t>(L.cl_tot, 1)) * nrhs);
+}
+
+// GEMV descriptors of the preconditioner (depend on workspace pointers)
+void build_apply_ops(ambddc_ctx& c, Level& L) {
+  hipStream_t st = c.st;
+  L.g1 = GemvOp();
+  L.g2 = GemvOp();
+  L.g3 = GemvOp();
+  L.g4 = GemvOp();
+  for (int s = 0; s < L.nsub; ++s) {
+    const int N = L.augN[s], nI = L.nI[s], nG = L.nG[s], nsl = L.ns[s];
+    double* A = L.aug.p + L.aug_off[s];
+    // [g; -K_II^{-1} r_I] = M^T r_I,  M = Aug[ns:ns+nI, nI:nI+nG+nI]
+    L.g1.add(A + nsl + int64_t(nI) * N, N, nI, nG + nI, L.w_xI.p + L.Ioff[s], int(L.nI_tot),
+             L.w_y1.p + L.y1off[s], int(L.y1_tot));
+    // interior:  Tr[nG:, 0:nG] u_B = (Aug[nI:nI+nG, ns:ns+nI])^T u_B
+    L.g4.add(A + nI + int64_t(nsl) * N, N, nG, nI, L.w_uBs.p + L.Goff[s], int(L.nG_tot),
+             L.w_y1.p + L.y1off[s] + nG, int(L.y1_tot));
+    const int nl = L.nl[s], NN = L.naugN[s];
+    double* B = L.naug.p + L.naug_off[s];
+    // [-Z r; -Psi^T r] = (Trn[0:nG, 0:nl])^T r
+    L.g2.add(B + nl + int64_t(nl) * NN, NN, nG, nl, L.w_rBs.p + L.Goff[s], int(L.nG_tot),
+             L.w_y2.p + L.y2off[s], int(L.y2_tot));
+    // -Psi u_c = (Trn[nG:nl, 0:nG])^T u_c
+    L.g3.add(B + nl + nG + int64_t(nl) * NN, NN, L.nc[s], nG, L.w_ucl.p + L.cloff[s],
+             int(std::max<int64_t>(L.cl_tot, 1)), L.w_y2.p + L.y2off[s], int(L.y2_tot));
+  }
+  L.g1.finalize(st);
+  L.g2.finalize(st);
+  L.g3.finalize(st);
+  L.g4.finalize(st);
+}
+
+// constraint-dependent structures (sizes from plan.subs[s].cons)
+void build_constraint_maps(ambddc_ctx& c, Level& L) {
+  hipStream_t st = c.st;
+  const LevelPlan& P = L.plan;
+  const int ns = L.nsub;
+  L.ncoarse = int(P.cons.size());
+  L.nc.resize(ns); L.nl.resize(ns); L.naugN.resize(ns);
+  L.c_off.assign(ns + 1, 0); L.naug_off.assign(ns + 1, 0); L.kc_off.assign(ns + 1, 0);
+  L.y2off.assign(ns + 1, 0); L.cloff.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    L.nc[s] = int(P.subs[s].cons.size());
+    L.nl[s] = L.nG[s] + L.nc[s];
+    L.naugN[s] = 2 * L.nl[s];
+    L.c_off[s + 1] = L.c_off[s] + int64_t(L.nc[s]) * L.nG[s];
+    L.naug_off[s + 1] = L.naug_off[s] + int64_t(L.naugN[s]) * L.naugN[s];
+    L.kc_off[s + 1] = L.kc_off[s] + int64_t(L.nc[s]) * L.nc[s];
+    L.y2off[s + 1] = L.y2off[s] + L.nl[s];
+    L.cloff[s + 1] = L.cloff[s] + L.nc[s];
+  }
+  L.c_total = L.c_off[ns];
+  L.naug_total = L.naug_off[ns];
+  L.kc_total = L.kc_off[ns];
+  L.y2_tot = L.y2off[ns];
+  L.cl_tot = L.cloff[ns];
+  L.C.alloc(std::max<int64_t>(L.c_total, 1));
+  L.naug.alloc(std::max<int64_t>(L.naug_total, 1));
+  L.kc.alloc(std::max<int64_t>(L.kc_total, 1));
+  L.d_naug_off.upload(std::vector<int64_t>(L.naug_off.begin(), L.naug_off.end() - 1), st);
+  L.d_kc_off.upload(std::vector<int64_t>(L.kc_off.begin(), L.kc_off.end() - 1), st);
+  L.d_nc.upload(L.nc, st);
+  L.d_nl.upload(L.nl, st);
+  L.d_naugN.upload(L.naugN, st);
+  // C entries: initial constraints get 1 or 1/m, adaptive ones copy from fc
+  std::vector<int64_t> fpos, apos, asrc;
+  std::vector<double> fval;
+  std::vector<int64_t> g2y2(L.nG_tot);
+  std::vector<LocalIndex> gl(ns);
+  for (int s = 0; s < ns; ++s) {
+    std::vector<int> G(P.subs[s].dofs.begin() + L.nI[s], P.subs[s].dofs.end());
+    gl[s].build(G);
+    for (int i = 0; i < L.nG[s]; ++i) g2y2[L.Goff[s] + i] = L.y2off[s] + i;
+  }
+  std::vector<int> cptr(L.ncoarse + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    const auto& cs = P.subs[s].cons;
+    for (int r = 0; r < L.nc[s]; ++r) {
+      const Constraint& K = P.cons[cs[r]];
+      cptr[cs[r] + 1]++;
+      for (size_t q = 0; q < K.dofs.size(); ++q) {
+        const int i = gl[s].find(K.dofs[q]);
+        if (i < 0) throw Error(AMBDDC_E_INVALID_ARG, "constraint DOF outside the interface");
+        const int64_t pos = L.c_off[s] + r + int64_t(i) * L.nc[s];
+        if (K.kind == CONS_ADAPT) {
+          apos.push_back(pos);
+          asrc.push_back(L.fc_off[K.pair] + int64_t(K.row) * L.face_nf[K.pair] + int64_t(q));
+        } else {
+          fpos.push_back(pos);
+          fval.push_back(K.kind == CONS_UNIT ? 1.0 : 1.0 / double(K.dofs.size()));
+        }
+      }
+    }
+  }
+  for (int k = 0; k < L.ncoarse; ++k) cptr[k + 1] += cptr[k];
+  std::vector<int64_t> cpos(cptr[L.ncoarse]), clmap(L.cl_tot);
+  {
+    std::vector<int> f(cptr.begin(), cptr.end() - 1);
+    for (int s = 0; s < ns; ++s) {
+      const auto& cs = P.subs[s].cons;
+      for (int r = 0; r < L.nc[s]; ++r) {
+        cpos[f[cs[r]]++] = L.y2off[s] + L.nG[s] + r;
+        clmap[L.cloff[s] + r] = cs[r];
+      }
+    }
+  }
+  L.cfill_pos.upload(fpos, st);
+  L.cfill_val.upload(fval, st);
+  L.cadapt_pos.upload(apos, st);
+  L.cadapt_src.upload(asrc, st);
+  L.cptr.upload(cptr, st);
+  L.cpos.upload(cpos, st);
+  L.clmap.upload(clmap, st);
+  L.g2y2.upload(g2y2, st);
+  // Neumann augmented matrices and their factorisation
+  std::vector<NeuDesc> nd(ns);
+  L.neu_cols = 0;
+  L.ldl_naug = LdltOp();
+  L.sym_naug = SymOp();
+  for (int s = 0; s < ns; ++s) {
+    const int N = L.augN[s];
+    nd[s].S = L.aug.p + L.aug_off[s] + L.nI[s] + int64_t(L.nI[s]) * N;
+    nd[s].lds = N;
+    nd[s].C = L.C.p + L.c_off[s];
+    nd[s].nc = L.nc[s];
+    nd[s].A = L.naug.p + L.naug_off[s];
+    nd[s].lda = L.naugN[s];
+    nd[s].nG = L.nG[s];
+    nd[s].rho = L.rho.p + s;
+    nd[s].col_start = L.neu_cols;
+    L.neu_cols += L.nl[s];
+    L.ldl_naug.add(nd[s].A, L.naugN[s], L.naugN[s], L.nl[s], L.nG[s]);
+    L.sym_naug.add(nd[s].A, L.naugN[s], L.nl[s], L.nl[s]);
+  }
+  L.neu.upload(nd, st);
+  L.ldl_naug.finalize(st);
+  L.sym_naug.finalize(st);
+  alloc_coarse_workspace(L, std::max(L.nrhs_cap, 1));
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void check_ldlt(LdltOp& op, hipStream_t st, const char* what, int level) {
+  const int f = op.failed(st);
+  if (f >= 0)
+    throw Error(AMBDDC_E_NOT_SPD, std::string(what) + ": non-positive pivot in matrix " +
+                                      std::to_string(f) + " on level " + std::to_string(level + 1));
+}
+
+// assemble K^s, weights, Schur complements (Section 2, Section 7)
+void numeric_schur(ambddc_ctx& c, Level& L, int li) {
+  hipStream_t st = c.st;
+  L.aug.zero(st);
+  launch_assemble(L.am, L.emat, L.d_aug_off.p, L.d_augN.p, L.aug.p, st);
+  // identity coupling Aug[ns + i, i] = Aug[i, ns + i] = 1, i < nI
+  {
+    std::vector<int> zero(L.nsub, 0);
+    DBuf<int> dz;
+    dz.upload(zero, st);
+    launch_aug_identity(L.nsub, L.d_aug_off.p, L.d_augN.p, L.d_nI.p, dz.p, L.d_ns.p, st, L.aug.p);
+    AMB_HIP(hipStreamSynchronize(st));
+  }
+  launch_diag_copy(int(L.nG_tot), L.diagpos.p, L.aug.p, L.diagG.p, st);
+  launch_weights(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.diagG.p, L.delta.p, st);
+  L.ldl_aug.run(st);
+  check_ldlt(L.ldl_aug, st, "interior factorisation", li);
+  L.sym_aug.run(st);
+  // rho_s = mean diag(S^s)
+  {
+    std::vector<int> n0(L.nsub);
+    for (int s = 0; s < L.nsub; ++s) n0[s] = L.nI[s];
+    DBuf<int> dn0;
+    dn0.upload(n0, st);
+    launch_diag_mean(L.nsub, L.d_aug_off.p, L.d_augN.p, dn0.p, L.d_nG.p, L.aug.p, L.rho.p, st);
+    AMB_HIP(hipStreamSynchronize(st));
+  }
+}
+
+// constraint matrices, constrained Neumann operators, coarse basis (Section 5)
+void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
+  hipStream_t st = c.st;
+  L.C.zero(st);
+  launch_fill_values(int(L.cfill_pos.n), L.cfill_pos.p, L.cfill_val.p, L.C.p, st);
+  if (L.cadapt_pos.n) {
+    DBuf<double> tmp;
+    tmp.alloc(L.cadapt_pos.n);
+    launch_gather(int(L.cadapt_pos.n), L.cadapt_src.p, L.fc.p, 0, tmp.p, 0, 1, 1.0, st);
+    launch_fill_values(int(L.cadapt_pos.n), L.cadapt_pos.p, tmp.p, L.C.p, st);
+    AMB_HIP(hipStreamSynchronize(st));
+  }
+  L.naug.zero(st);
+  launch_neumann_fill(L.neu.p, L.nsub, L.neu_cols, st);
+  L.ldl_naug.run(st);
+  check_ldlt(L.ldl_naug, st, "constrained Neumann factorisation", li);
+  L.sym_naug.run(st);
+  launch_extract_kc(L.nsub, L.d_naug_off.p, L.d_naugN.p, L.d_nG.p, L.d_nc.p, L.d_kc_off.p, L.rho.p,
+                    L.naug.p, L.kc.p, st);
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// adaptive selection on one level: batched LOBPCG over all face pairs
+// ---------------------------------------------------------------------------
+
+struct PairWork {
+  int np = 0, m = 0, ncp_max = 0, nface_max = 0;
+  std::vector<PairDev> hp;
+  DBuf<PairDev> dp;
+  PairIdx idx;
+  DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw;
+  DBuf<int> active, kout, nnull;
+  GemmOp gS, gM1, gM2, gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
+};
+
+void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
+  hipStream_t st = c.st;
+  const LevelPlan& P = L.plan;
+  const int m = W.m;
+  W.np = int(P.pairs.size());
+  std::vector<int64_t> Uoff(L.nsub + 1, 0), Yoff(L.nsub + 1, 0), Zoff(L.nsub + 1, 0);
+  for (int s = 0; s < L.nsub; ++s) {
+    const int64_t cols = int64_t(P.sub_npairs[s]) * 2 * m;
+    Uoff[s + 1] = Uoff[s] + cols * L.nG[s];
+    Yoff[s + 1] = Yoff[s] + cols * L.nl[s];
+    Zoff[s + 1] = Zoff[s] + cols * L.nc[s];
+  }
+  std::vector<int> sh_s, sh_t, dr_s, dr_t, pc_s, pc_t, face_s;
+  int64_t voff = 0, kpoff = 0, rboff = 0, fcoff = 0;
+  W.hp.resize(W.np);
+  L.fc_off.assign(W.np, 0);
+  L.face_nf.assign(W.np, 0);
+  for (int p = 0; p < W.np; ++p) {
+    const Pair& Q = P.pairs[p];
+    PairDev d{};
+    d.s = Q.s;
+    d.t = Q.t;
+    d.nGs = L.nG[Q.s];
+    d.nGt = L.nG[Q.t];
+    d.gs_off = L.Goff[Q.s];
+    d.gt_off = L.Goff[Q.t];
+    const int n = d.nGs + d.nGt;
+    d.v_off = voff;
+    voff += int64_t(n) * 3 * m;
+    d.us_off = Uoff[Q.s] + int64_t(Q.slot_s) * 2 * m * d.nGs;
+    d.ut_off = Uoff[Q.t] + int64_t(Q.slot_t) * 2 * m * d.nGt;
+    d.nls = L.nl[Q.s];
+    d.nlt = L.nl[Q.t];
+    d.ys_off = Yoff[Q.s] + int64_t(Q.slot_s) * 2 * m * d.nls;
+    d.yt_off = Yoff[Q.t] + int64_t(Q.slot_t) * 2 * m * d.nlt;
+    d.ncs = L.nc[Q.s];
+    d.nct = L.nc[Q.t];
+    d.zs_off = Zoff[Q.s] + int64_t(Q.slot_s) * 2 * m * d.ncs;
+    d.zt_off = Zoff[Q.t] + int64_t(Q.slot_t) * 2 * m * d.nct;
+    d.sh0 = int(sh_s.size());
+    sh_s.insert(sh_s.end(), Q.sh_s.begin(), Q.sh_s.end());
+    sh_t.insert(sh_t.end(), Q.sh_t.begin(), Q.sh_t.end());
+    d.sh1 = int(sh_s.size());
+    d.dr0 = int(dr_s.size());
+    dr_s.insert(dr_s.end(), Q.dr_s.begin(), Q.dr_s.end());
+    dr_t.insert(dr_t.end(), Q.dr_t.begin(), Q.dr_t.end());
+    d.dr1 = int(dr_s.size());
+    d.cs_off = L.c_off[Q.s];
+    d.ct_off = L.c_off[Q.t];
+    d.pcs0 = int(pc_s.size());
+    pc_s.insert(pc_s.end(), Q.pc_s.begin(), Q.pc_s.end());
+    d.pct0 = int(pc_t.size());
+    pc_t.insert(pc_t.end(), Q.pc_t.begin(), Q.pc_t.end());
+    d.ncp = Q.n_cp;
+    d.kp_off = kpoff;
+    kpoff += int64_t(Q.n_cp) * Q.n_cp;
+    W.ncp_max = std::max(W.ncp_max, Q.n_cp);
+    d.face0 = int(face_s.size());
+    face_s.insert(face_s.end(), Q.face_s.begin(), Q.face_s.end());
+    d.nface = int(Q.face_s.size());
+    W.nface_max = std::max(W.nface_max, d.nface);
+    d.nrb = Q.both_floating ? L.nrb : 0;
+    d.rb_off = rboff;
+    rboff += int64_t(n) * d.nrb;
+    d.fc_off = fcoff;
+    L.fc_off[p] = fcoff;
+    L.face_nf[p] = d.nface;
+    fcoff += int64_t(c.opt.nev_max) * d.nface;
+    W.hp[p] = d;
+  }
+  if (W.ncp_max > 60)
+    throw Error(AMBDDC_E_INVALID_ARG, "pair coarse space larger than 60 is not supported yet");
+  W.dp.upload(W.hp, st);
+  W.idx.sh_s.upload(sh_s, st);
+  W.idx.sh_t.upload(sh_t, st);
+  W.idx.dr_s.upload(dr_s, st);
+  W.idx.dr_t.upload(dr_t, st);
+  W.idx.pc_s.upload(pc_s, st);
+  W.idx.pc_t.upload(pc_t, st);
+  W.idx.face_s.upload(face_s, st);
+  W.V.alloc(voff); W.AV.alloc(voff); W.BV.alloc(voff); W.T.alloc(2 * voff);
+  W.V.zero(st); W.AV.zero(st); W.BV.zero(st);
+  W.GA.alloc(size_t(W.np) * 9 * m * m);
+  W.GB.alloc(size_t(W.np) * 9 * m * m);
+  W.Cf.alloc(size_t(W.np) * 3 * m * 2 * m);
+  W.Cxw.alloc(size_t(W.np) * m * m);
+  W.lam.alloc(size_t(W.np) * m);
+  W.lam.zero(st);
+  W.resn.alloc(size_t(W.np) * m);
+  W.U.alloc(std::max<int64_t>(Uoff[L.nsub], 1));
+  W.Y.alloc(std::max<int64_t>(Yoff[L.nsub], 1));
+  W.Zc.alloc(std::max<int64_t>(Zoff[L.nsub], 1));
+  W.U.zero(st); W.Y.zero(st); W.Zc.zero(st);
+  W.Kp.alloc(std::max<int64_t>(kpoff, 1));
+  W.rb.alloc(std::max<int64_t>(rboff, 1));
+  W.lnext.alloc(W.np);
+  W.active.alloc(W.np);
+  W.kout.alloc(W.np);
+  W.nnull.alloc(W.np);
+  L.fc.alloc(std::max<int64_t>(fcoff, 1));
+  L.fc.zero(st);
+  // grouped S / Z / Psi products: one GEMM per subdomain over all its pair slots
+  W.gS = GemmOp(); W.gM1 = GemmOp(); W.gM2 = GemmOp();
+  for (int s = 0; s < L.nsub; ++s) {
+    const int cols = P.sub_npairs[s] * 2 * m;
+    if (cols == 0) continue;
+    const int N = L.augN[s], nI = L.nI[s], nG = L.nG[s], nl = L.nl[s], NN = L.naugN[s];
+    const double* S = L.aug.p + L.aug_off[s] + nI + int64_t(nI) * N;
+    const double* Tn = L.naug.p + L.naug_off[s] + nl + int64_t(nl) * NN;
+    W.gS.add(S, N, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nG, cols, nG);
+    W.gM1.add(Tn, NN, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nl, cols, nG);
+    if (L.nc[s] > 0)
+      W.gM2.add(Tn + int64_t(nG) * NN, NN, W.Zc.p + Zoff[s], L.nc[s], W.Y.p + Yoff[s], nl, nG, cols,
+                L.nc[s]);
+  }
+  W.gS.finalize(st);
+  W.gM1.finalize(st);
+  W.gM2.finalize(st);
+  // W <- W - X (BX^T W): B-orthogonalise the search directions against X
+  W.orth_c = GemmOp();
+  W.orth_u = GemmOp();
+  W.orth_c.ta = true;
+  W.orth_u.narrow = (m <= 32);
+  for (int p = 0; p < W.np; ++p) {
+    const PairDev& d = W.hp[p];
+    const int n = d.nGs + d.nGt;
+    const int* fl = W.active.p + p;
+    double* cx = W.Cxw.p + size_t(p) * m * m;
+    W.orth_c.add(W.BV.p + d.v_off, n, W.V.p + d.v_off + int64_t(m) * n, n, cx, m, m, m, n, fl);
+    W.orth_u.add(W.V.p + d.v_off, n, cx, m, W.V.p + d.v_off + int64_t(m) * n, n, n, m, m, fl);
+  }
+  W.orth_c.finalize(st);
+  W.orth_u.finalize(st);
+  // P <- P - X (BX^T P): keeps the P block from collapsing onto X near convergence
+  W.orthp_c = GemmOp();
+  W.orthp_u = GemmOp();
+  W.orthp_c.ta = true;
+  W.orthp_u.narrow = (m <= 32);
+  for (int p = 0; p < W.np; ++p) {
+    const PairDev& d = W.hp[p];
+    const int n = d.nGs + d.nGt;
+    const int* fl = W.active.p + p;
+    double* cx = W.Cxw.p + size_t(p) * m * m;
+    W.orthp_c.add(W.BV.p + d.v_off, n, W.V.p + d.v_off + int64_t(2 * m) * n, n, cx, m, m, m, n, fl);
+    W.orthp_u.add(W.V.p + d.v_off, n, cx, m, W.V.p + d.v_off + int64_t(2 * m) * n, n, n, m, m, fl);
+  }
+  W.orthp_c.finalize(st);
+  W.orthp_u.finalize(st);
+  for (int v = 0; v < 3; ++v) {
+    const int nb = (v + 1) * m;
+    W.gram_a[v] = GemmOp(); W.gram_b[v] = GemmOp();
+    W.upd_v[v] = GemmOp();
+    W.gram_a[v].ta = W.gram_b[v].ta = true;
+    W.upd_v[v].narrow = (2 * m <= 32);
+    for (int p = 0; p < W.np; ++p) {
+      const PairDev& d = W.hp[p];
+      const int n = d.nGs + d.nGt;
+      const int* fl = W.active.p + p;
+      W.gram_a[v].add(W.V.p + d.v_off, n, W.AV.p + d.v_off, n, W.GA.p + size_t(p) * 9 * m * m, nb,
+                      nb, nb, n, fl);
+      W.gram_b[v].add(W.V.p + d.v_off, n, W.BV.p + d.v_off, n, W.GB.p + size_t(p) * 9 * m * m, nb,
+                      nb, nb, n, fl);
+      const double* cf = W.Cf.p + size_t(p) * 3 * m * 2 * m;
+      double* t = W.T.p + 2 * d.v_off;
+      W.upd_v[v].add(W.V.p + d.v_off, n, cf, 3 * m, t, n, n, 2 * m, nb, fl);
+    }
+    W.gram_a[v].finalize(st); W.gram_b[v].finalize(st);
+    W.upd_v[v].finalize(st);
+  }
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
+  lp_to_slab(W.dp.p, W.np, W.V.p, W.m, col, true, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
+             W.active.p, st);
+  W.gS.run(1.0, 0.0, st);
+  lp_from_slab_ab(W.dp.p, W.np, W.Y.p, W.m, col, W.AV.p, W.BV.p, L.diagG.p, W.idx.sh_s.p,
+                  W.idx.sh_t.p, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.active.p, st);
+}
+
+// Rayleigh-Ritz on span(V) and the new X, P (the products AV, BV are always
+// recomputed explicitly from the current blocks, never updated implicitly:
+// with coefficient jumps the implicit updates drift out of the factor space).
+void rayleigh_ritz(Level& L, PairWork& W, int v, bool with_p, hipStream_t st) {
+  const int nb = (v + 1) * W.m;
+  W.gram_a[v].run(1.0, 0.0, st);
+  W.gram_b[v].run(1.0, 0.0, st);
+  lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
+  W.upd_v[v].run(1.0, 0.0, st);
+  lp_commit(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.T.p, W.m, with_p, true, W.active.p, st);
+  lp_project(W.dp.p, W.np, W.V.p, W.m, 0, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p, W.active.p,
+             true, st);
+  if (with_p)
+    lp_project(W.dp.p, W.np, W.V.p, W.m, 2, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p,
+               W.active.p, true, st);
+}
+
+int count_active(PairWork& W, hipStream_t st) {
+  std::vector<int> a = W.active.download(st);
+  int n = 0;
+  for (int x : a) n += x != 0;
+  return n;
+}
+
+void adaptive_level(ambddc_ctx& c, Level& L, int li) {
+  hipStream_t st = c.st;
+  PairWork W;
+  const int nev = c.opt.nev_max;
+  W.m = std::max(c.opt.lobpcg_block, nev + 1);
+  if (W.m > 16) throw Error(AMBDDC_E_INVALID_ARG, "lobpcg_block larger than 16 is not supported");
+  L.m = W.m;
+  build_pair_work(c, L, W);
+  if (W.np == 0) {
+    L.omega = 0.0;
+    return;
+  }
+  // pair coarse pseudo-inverses and rigid modes
+  lp_pair_coarse(W.dp.p, W.np, L.kc.p, L.d_kc_off.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Kp.p, st);
+  lp_pinv(W.dp.p, W.np, W.Kp.p, W.ncp_max, 1e-10, W.nnull.p, st);
+  lp_rigid(W.dp.p, W.np, L.rigid.p, L.ndof, L.Gdof.p, W.rb.p, st);
+  {
+    std::vector<int> nn = W.nnull.download(st);
+    L.pair_nnull = nn;
+    for (int p = 0; p < W.np; ++p) {
+      const int expect = W.hp[p].nrb;
+      if (nn[p] > expect)
+        throw Error(AMBDDC_E_ASSUMPTION,
+                    "Assumption 1 fails on level " + std::to_string(li + 1) + " pair (" +
+                        std::to_string(W.hp[p].s) + "," + std::to_string(W.hp[p].t) +
+                        "): pair coarse matrix has " + std::to_string(nn[p]) +
+                        " null vectors, rigid modes " + std::to_string(expect));
+    }
+  }
+  const int m = W.m;
+  const int nconv = std::min(nev + 1, m);
+  std::vector<int> ones(W.np, 1);
+  W.active.upload(ones, st);
+  // start block, projected; first Rayleigh-Ritz on X alone
+  lp_random(W.dp.p, W.np, W.V.p, m, c.opt.seed + uint64_t(li) * 7919u, st);
+  lp_project(W.dp.p, W.np, W.V.p, m, 0, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p, nullptr, true, st);
+  apply_ab(L, W, 0, st);
+  rayleigh_ritz(L, W, 0, false, st);
+  int it = 0;
+  for (it = 1; it <= c.opt.lobpcg_maxit; ++it) {
+    apply_ab(L, W, 0, st);
+    if (it >= 2) {
+      W.orthp_c.run(1.0, 0.0, st);
+      W.orthp_u.run(-1.0, 1.0, st);
+      apply_ab(L, W, 2, st);
+    }
+    lp_residual(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.lam.p, m, nconv, c.opt.lobpcg_tol,
+                W.active.p, W.resn.p, st);
+    if (count_active(W, st) == 0) break;
+    // W = M R  (eq. bddc_pair: Z^st R + Psi (Psi^T S Psi)^+ Psi^T R, then Pi and deflation)
+    lp_to_slab(W.dp.p, W.np, W.V.p, m, 1, false, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
+               W.active.p, st);
+    W.gM1.run(1.0, 0.0, st);
+    lp_coarse(W.dp.p, W.np, W.Y.p, m, W.Kp.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Zc.p, W.active.p, st);
+    W.gM2.run(1.0, 1.0, st);
+    lp_from_slab_w(W.dp.p, W.np, W.Y.p, m, W.V.p, W.active.p, st);
+    lp_project(W.dp.p, W.np, W.V.p, m, 1, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p, W.active.p,
+               true, st);
+    W.orth_c.run(1.0, 0.0, st);
+    W.orth_u.run(-1.0, 1.0, st);
+    apply_ab(L, W, 1, st);
+    rayleigh_ritz(L, W, it == 1 ? 1 : 2, true, st);
+  }
+  if (it > c.opt.lobpcg_maxit) apply_ab(L, W, 0, st);   // products of the final X
+  L.lobpcg_its = std::min(it, c.opt.lobpcg_maxit);
+  L.n_unconv = count_active(W, st);
+  lp_select(W.dp.p, W.np, W.AV.p, W.lam.p, m, nev, c.opt.tau, W.idx.face_s.p, W.nface_max, L.fc.p,
+            W.kout.p, W.lnext.p, st);
+  L.pair_k = W.kout.download(st);
+  L.pair_lnext = W.lnext.download(st);
+  L.pair_lam = W.lam.download(st);
+  L.pair_res = W.resn.download(st);
+  std::vector<int> act = W.active.download(st);
+  L.pair_conv.resize(W.np);
+  for (int p = 0; p < W.np; ++p) L.pair_conv[p] = act[p] == 0;
+  L.omega = 0.0;
+  L.n_added = 0;
+  for (int p = 0; p < W.np; ++p) {
+    L.omega = std::max(L.omega, L.pair_lnext[p]);
+    L.n_added += L.pair_k[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// next level, top coarse problem, preconditioner application
+// ---------------------------------------------------------------------------
+
+void build_top(ambddc_ctx& c) {
+  hipStream_t st = c.st;
+  Level& L = *c.L.back();
+  Top& T = c.top;
+  T = Top();
+  T.n = L.ncoarse;
+  if (T.n == 0) return;
+  const int n = T.n, N = 2 * n;
+  T.aug.alloc(size_t(N) * N);
+  T.aug.zero(st);
+  std::vector<int64_t> edptr(L.nsub + 1, 0);
+  std::vector<int> edofs;
+  for (int s = 0; s < L.nsub; ++s) {
+    const auto& cs = L.plan.subs[s].cons;
+    edofs.insert(edofs.end(), cs.begin(), cs.end());
+    edptr[s + 1] = int64_t(edofs.size());
+  }
+  std::vector<int> tgt(L.nsub, 0);
+  std::vector<LocalIndex> loc(1);
+  std::vector<int> ident(n);
+  std::iota(ident.begin(), ident.end(), 0);
+  loc[0].build(ident);
+  std::vector<int64_t> koff(L.kc_off.begin(), L.kc_off.end() - 1);
+  build_assembly(T.am, L.nsub, tgt, edptr, edofs, koff, loc, {n}, st);
+  T.d_off.upload(std::vector<int64_t>{0}, st);
+  T.d_ld.upload(std::vector<int>{N}, st);
+  launch_assemble(T.am, L.kc.p, T.d_off.p, T.d_ld.p, T.aug.p, st);
+  if (n <= 4096) {
+    T.Kc.alloc(size_t(n) * n);
+    DBuf<int64_t> so, dof;
+    DBuf<int> sl, r0, rr, dl;
+    so.upload(std::vector<int64_t>{0}, st);
+    dof.upload(std::vector<int64_t>{0}, st);
+    sl.upload(std::vector<int>{N}, st);
+    r0.upload(std::vector<int>{0}, st);
+    rr.upload(std::vector<int>{n}, st);
+    dl.upload(std::vector<int>{n}, st);
+    launch_copy_block(1, so.p, sl.p, r0.p, rr.p, rr.p, dof.p, dl.p, T.aug.p, T.Kc.p, st);
+    AMB_HIP(hipStreamSynchronize(st));
+  }
+  {
+    DBuf<int> nid, c0, r0;
+    nid.upload(std::vector<int>{n}, st);
+    c0.upload(std::vector<int>{0}, st);
+    r0.upload(std::vector<int>{n}, st);
+    launch_aug_identity(1, T.d_off.p, T.d_ld.p, nid.p, c0.p, r0.p, st, T.aug.p);
+    AMB_HIP(hipStreamSynchronize(st));
+  }
+  T.ldl.add(T.aug.p, N, N, n, n);
+  T.ldl.finalize(st);
+  T.sym.add(T.aug.p, N, n, n);
+  T.sym.finalize(st);
+  T.ldl.run(st);
+  check_ldlt(T.ldl, st, "coarsest factorisation", int(c.L.size()));
+  T.sym.run(st);
+}
+
+void build_top_solve(ambddc_ctx& c) {
+  Top& T = c.top;
+  if (T.n == 0) return;
+  Level& L = *c.L.back();
+  const int n = T.n, N = 2 * n;
+  T.solve = GemvOp();
+  T.solve.add(T.aug.p + n + int64_t(n) * N, N, n, n, L.w_rc.p, n, L.w_uc.p, n);
+  T.solve.finalize(c.st);
+}
+
+void ensure_workspace(ambddc_ctx& c, int nrhs) {
+  bool changed = false;
+  for (auto& lp : c.L) {
+    Level& L = *lp;
+    if (L.nrhs_cap < nrhs) {
+      alloc_workspace(L, nrhs);
+      alloc_coarse_workspace(L, nrhs);
+      changed = true;
+    }
+  }
+  if (changed) {
+    for (auto& lp : c.L) build_apply_ops(c, *lp);
+    build_top_solve(c);
+  }
+}
+
+// Alg. 1 on level li: r (ld ldr) -> u (ld ldu)
+void apply_level(ambddc_ctx& c, int li, const double* r, int64_t ldr, double* u, int64_t ldu,
+                 int nrhs) {
+  hipStream_t st = c.st;
+  Level& L = *c.L[li];
+  // interior pre-correction and updated residual on the interface
+  launch_gather(int(L.nI_tot), L.Imap.p, r, ldr, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
+  L.g1.run(1.0, 0.0, nrhs, st);
+  launch_interface_residual(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.g2y1.p, L.delta.p,
+                            r, ldr, L.w_y1.p, L.y1_tot, L.w_rBs.p, L.nG_tot, nrhs, st);
+  // substructure corrections and coarse right-hand side
+  L.g2.run(1.0, 0.0, nrhs, st);
+  if (L.ncoarse > 0) {
+    launch_segment_sum(L.ncoarse, L.cptr.p, L.cpos.p, L.w_y2.p, L.y2_tot, L.w_rc.p, L.ncoarse, nrhs,
+                       -1.0, st);
+    if (li + 1 == int(c.L.size())) c.top.solve.run(-1.0, 0.0, nrhs, st);
+    else apply_level(c, li + 1, L.w_rc.p, L.ncoarse, L.w_uc.p, L.ncoarse, nrhs);
+    launch_gather(int(L.cl_tot), L.clmap.p, L.w_uc.p, L.ncoarse, L.w_ucl.p, L.cl_tot, nrhs, 1.0, st);
+  }
+  L.g3.run(-1.0, -1.0, nrhs, st);
+  // averaging, interior post-correction, combination
+  launch_average(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.g2y2.p, L.delta.p, L.w_y2.p,
+                 L.y2_tot, L.w_uBs.p, L.nG_tot, u, ldu, nrhs, st);
+  L.g4.run(1.0, -1.0, nrhs, st);
+  launch_move(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, u, ldu, nrhs, st);
+}
+
+void next_level(ambddc_ctx& c, int li) {
+  hipStream_t st = c.st;
+  Level& L = *c.L[li];
+  auto N = std::make_unique<Level>();
+  std::string e = next_level_input(L.plan, c.parents[li], N->plan.in);
+  if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
+  e = build_level_plan(N->plan, c.opt.face_averages != 0);
+  if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
+  std::vector<int64_t> koff(L.kc_off.begin(), L.kc_off.end() - 1);
+  build_level_maps(c, *N, L.kc.p, koff);
+  // coarse values of the level-li rigid modes
+  N->rigid.alloc(size_t(N->ndof) * N->nrb);
+  {
+    std::vector<int> sub_of(N->ndof, -1), row_of(N->ndof, -1);
+    for (int s = 0; s < L.nsub; ++s) {
+      const auto& cs = L.plan.subs[s].cons;
+      for (int r = 0; r < int(cs.size()); ++r)
+        if (sub_of[cs[r]] < 0) { sub_of[cs[r]] = s; row_of[cs[r]] = r; }
+    }
+    DBuf<int> ds, dr, dnc;
+    DBuf<int64_t> dco, dgo;
+    ds.upload(sub_of, st);
+    dr.upload(row_of, st);
+    dnc.upload(L.nc, st);
+    dco.upload(std::vector<int64_t>(L.c_off.begin(), L.c_off.end() - 1), st);
+    dgo.upload(std::vector<int64_t>(L.Goff.begin(), L.Goff.end() - 1), st);
+    launch_coarse_rigid(N->ndof, N->nrb, ds.p, dr.p, dco.p, dnc.p, L.d_nG.p, dgo.p, L.Gdof.p, L.C.p,
+                        L.rigid.p, L.ndof, N->rigid.p, st);
+    AMB_HIP(hipStreamSynchronize(st));
+  }
+  c.L.push_back(std::move(N));
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
+  hipStream_t st = c.st;
+  const double t0 = now_s();
+  c.ready = false;
+  std::memset(&c.stats, 0, sizeof(c.stats));
+  const int ne = 8 * c.dof;
+  launch_element_matrices(c.coords.p, c.en.p, coeff, nu, c.n_elems, c.dof, c.Ke.p, st);
+  launch_csr_values(c.csr, c.edofs.p, ne, c.Ke.p, c.csr_vals.p, st);
+  c.L.resize(1);
+  Level& L0 = *c.L[0];
+  L0.plan = c.plan0;
+  L0.nrhs_cap = 0;
+  const bool adaptive = c.opt.tau > 0.0 && std::isfinite(c.opt.tau);
+  double tph[8] = {0};
+  for (int li = 0; li < c.levels - 1; ++li) {
+    if (li > 0) next_level(c, li - 1);
+    Level& L = *c.L[li];
+    AMB_HIP(hipStreamSynchronize(st));
+    double ta = now_s();
+    numeric_schur(c, L, li);
+    AMB_HIP(hipStreamSynchronize(st));
+    double tb = now_s();
+    tph[0] += tb - ta;
+    build_constraint_maps(c, L);
+    numeric_neumann(c, L, li);
+    AMB_HIP(hipStreamSynchronize(st));
+    double tcc = now_s();
+    tph[1] += tcc - tb;
+    if (adaptive) {
+      adaptive_level(c, L, li);
+      AMB_HIP(hipStreamSynchronize(st));
+      double td = now_s();
+      tph[2] += td - tcc;
+      add_adaptive_constraints(L.plan, L.pair_k);
+      build_constraint_maps(c, L);
+      numeric_neumann(c, L, li);
+      AMB_HIP(hipStreamSynchronize(st));
+      tph[4] += now_s() - td;
+    }
+  }
+  double te = now_s();
+  build_top(c);
+  AMB_HIP(hipStreamSynchronize(st));
+  tph[5] += now_s() - te;
+  for (auto& lp : c.L) lp->nrhs_cap = 0;
+  ensure_workspace(c, 1);
+  AMB_HIP(hipStreamSynchronize(st));
+  c.stats.levels = int(c.L.size());
+  c.stats.n_free = c.L[0]->ndof;
+  for (int i = 0; i < int(c.L.size()) && i < 8; ++i) {
+    const Level& L = *c.L[i];
+    c.stats.n_sub[i] = L.nsub;
+    c.stats.n_pairs[i] = int(L.plan.pairs.size());
+    c.stats.n_coarse[i] = L.ncoarse;
+    c.stats.n_adaptive[i] = L.n_added;
+    c.stats.lobpcg_iters[i] = L.lobpcg_its;
+    c.stats.n_unconverged[i] = L.n_unconv;
+    c.stats.omega_tilde[i] = L.omega;
+  }
+  for (int k = 0; k < 6; ++k) c.stats.t_phase[k] = tph[k];
+  c.stats.t_phase[6] = now_s() - t0;
+  c.ready = true;
+}
+
+// ---------------------------------------------------------------------------
+// PCG
+// ---------------------------------------------------------------------------
+
+int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, double* x,
+             int* its, double* cond) {
+  hipStream_t st = c.st;
+  const double t0 = now_s();
+  const int n = c.L[0]->ndof;
+  ensure_workspace(c, nrhs);
+  if (c.pcg_cap < nrhs || c.pcg_maxit < maxit) {
+    c.pcg_cap = std::max(c.pcg_cap, nrhs);
+    c.pcg_maxit = std::max(c.pcg_maxit, maxit);
+    const size_t nn = size_t(n) * c.pcg_cap;
+    c.pr.alloc(nn); c.pz.alloc(nn); c.pp.alloc(nn); c.pq.alloc(nn);
+    c.pdot.alloc(8 * c.pcg_cap);
+    c.ppart.alloc(256 * c.pcg_cap);
+    c.pah.alloc(size_t(c.pcg_maxit) * c.pcg_cap);
+    c.pbh.alloc(size_t(c.pcg_maxit) * c.pcg_cap);
+    c.plz.alloc(3 * c.pcg_cap + 2 * size_t(c.pcg_maxit) * c.pcg_cap);
+    c.pact.alloc(c.pcg_cap);
+    c.pnal.alloc(c.pcg_cap);
+  }
+  const size_t nn = size_t(n) * nrhs;
+  double* rz = c.pdot.p;              // rz[0:nrhs], beta scratch rz[nrhs:2nrhs]
+  double* pq = c.pdot.p + 2 * nrhs;
+  double* rr = c.pdot.p + 3 * nrhs;
+  double* rzn = c.pdot.p + 4 * nrhs;
+  double* ff = c.pdot.p + 5 * nrhs;
+  launch_fill(x, nn, 0.0, st);
+  launch_copy(c.pr.p, f, nn, st);
+  launch_dot_cols(n, nrhs, f, f, c.ppart.p, ff, st);
+  std::vector<double> hff(nrhs), hrr(nrhs);
+  AMB_HIP(hipMemcpyAsync(hff.data(), ff, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  std::vector<int> act(nrhs, 1), nal(nrhs, 0);
+  for (int k = 0; k < nrhs; ++k) {
+    its[k] = 0;
+  }
+  AMB_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < nrhs; ++k)
+    if (hff[k] == 0.0) act[k] = 0;
+  c.pact.upload(act, st);
+  apply_level(c, 0, c.pr.p, n, c.pz.p, n, nrhs);
+  launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rz, st);
+  launch_copy(c.pp.p, c.pz.p, nn, st);
+  int nact = 0;
+  for (int a : act) nact += a;
+  int it = 0;
+  for (it = 0; it < maxit && nact > 0; ++it) {
+    launch_spmv(c.csr, c.csr_vals.p, c.pp.p, c.pq.p, nrhs, st);
+    launch_dot_cols(n, nrhs, c.pp.p, c.pq.p, c.ppart.p, pq, st);
+    launch_pcg_update_x_r(n, nrhs, rz, pq, c.pact.p, x, c.pr.p, c.pp.p, c.pq.p, c.pah.p, it,
+                          c.pcg_maxit, st);
+    launch_dot_cols(n, nrhs, c.pr.p, c.pr.p, c.ppart.p, rr, st);
+    AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    AMB_HIP(hipStreamSynchronize(st));
+    bool changed = false;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!act[k]) continue;
+      nal[k] = it + 1;
+      its[k] = it + 1;
+      if (hrr[k] <= rtol * rtol * hff[k]) {
+        act[k] = 0;
+        changed = true;
+        --nact;
+      }
+    }
+    if (nact == 0) break;
+    if (changed) c.pact.upload(act, st);
+    apply_level(c, 0, c.pr.p, n, c.pz.p, n, nrhs);
+    launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rzn, st);
+    launch_pcg_update_p(n, nrhs, rzn, rz, c.pact.p, c.pp.p, c.pz.p, c.pbh.p, it, c.pcg_maxit, st);
+  }
+  if (cond) {
+    c.pnal.upload(nal, st);
+    launch_lanczos_cond(nrhs, c.pnal.p, c.pah.p, c.pbh.p, c.pcg_maxit, c.plz.p, st);
+    AMB_HIP(hipMemcpyAsync(cond, c.plz.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  }
+  AMB_HIP(hipStreamSynchronize(st));
+  c.stats.t_phase[7] = now_s() - t0;
+  return nact;
+}
+
+int guard(const std::function<void()>& fn) {
+  try {
+    fn();
+    g_err.clear();
+    return AMBDDC_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return AMBDDC_E_DEVICE;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void ambddc_default_options(ambddc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tau = 10.0;
+  o->nev_max = 10;
+  o->lobpcg_maxit = 100;
+  o->lobpcg_block = 16;
+  o->lobpcg_tol = 1e-7;
+  o->precision = 0;
+  o->face_averages = 0;
+  o->seed = 12345;
+  o->stream = nullptr;
+}
+
+const char* ambddc_last_error(void) { return g_err.c_str(); }
+
+ambddc_status ambddc_analyze(const ambddc_mesh* mesh, const ambddc_decomp* dec,
+                             int32_t face_averages, ambddc_analysis* out, int32_t* sizes,
+                             int32_t n_sub_cap) {
+  return ambddc_status(guard([&] {
+    if (!mesh || !dec || !out || !mesh->elem_nodes || !mesh->dirichlet || !dec->elem_to_sub)
+      throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (mesh->dof_per_node != 1 && mesh->dof_per_node != 3)
+      throw Error(AMBDDC_E_INVALID_ARG, "dof_per_node must be 1 or 3");
+    LevelPlan P;
+    std::vector<int> fof;
+    std::string e = level1_input(mesh->n_nodes, mesh->n_elems, mesh->dof_per_node, mesh->elem_nodes,
+                                 mesh->dirichlet, dec->elem_to_sub, P.in, fof);
+    if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
+    e = build_level_plan(P, face_averages != 0);
+    if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
+    std::memset(out, 0, sizeof(*out));
+    out->n_free = P.in.n_dof;
+    out->n_sub = P.in.n_sub;
+    for (const auto& g : P.globs) {
+      out->n_interface += int(g.dofs.size());
+      if (g.type == GLOB_FACE) out->n_faces++;
+      else if (g.type == GLOB_EDGE) out->n_edges++;
+      else out->n_corners++;
+    }
+    out->n_coarse_initial = P.n_cons_initial;
+    out->n_pairs = int(P.pairs.size());
+    if (sizes) {
+      if (n_sub_cap < P.in.n_sub) throw Error(AMBDDC_E_INVALID_ARG, "sub_sizes too small");
+      for (int s = 0; s < P.in.n_sub; ++s) {
+        sizes[2 * s] = P.subs[s].nI;
+        sizes[2 * s + 1] = P.subs[s].nG;
+      }
+    }
+  }));
+}
+
+ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
+                            const ambddc_options* opt, ambddc_handle* out) {
+  return ambddc_status(guard([&] {
+    if (!mesh || !dec || !opt || !out) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (mesh->dof_per_node != 1 && mesh->dof_per_node != 3)
+      throw Error(AMBDDC_E_INVALID_ARG, "dof_per_node must be 1 or 3");
+    if (mesh->n_nodes <= 0 || mesh->n_elems <= 0 || !mesh->coords || !mesh->elem_nodes ||
+        !mesh->dirichlet)
+      throw Error(AMBDDC_E_INVALID_ARG, "empty or missing mesh arrays");
+    if (dec->levels < 2 || dec->levels > 8 || !dec->elem_to_sub)
+      throw Error(AMBDDC_E_INVALID_ARG, "levels must be in 2..8 with an element map");
+    if (dec->levels > 2 && !dec->parents) throw Error(AMBDDC_E_INVALID_ARG, "missing parent maps");
+    if (opt->precision != 0) throw Error(AMBDDC_E_INVALID_ARG, "only precision 0 (FP64) is built");
+    if (opt->nev_max < 0 || opt->lobpcg_maxit < 1 || opt->lobpcg_tol <= 0.0)
+      throw Error(AMBDDC_E_INVALID_ARG, "bad LOBPCG options");
+    auto c = std::make_unique<ambddc_ctx>();
+    c->opt = *opt;
+    c->st = static_cast<hipStream_t>(opt->stream);
+    c->n_nodes = mesh->n_nodes;
+    c->n_elems = mesh->n_elems;
+    c->dof = mesh->dof_per_node;
+    c->levels = dec->levels;
+    std::string e = level1_input(mesh->n_nodes, mesh->n_elems, mesh->dof_per_node, mesh->elem_nodes,
+                                 mesh->dirichlet, dec->elem_to_sub, c->plan0.in, c->free_of_full);
+    if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
+    e = build_level_plan(c->plan0, opt->face_averages != 0);
+    if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
+    // parent maps, checked level by level
+    int nsub = c->plan0.in.n_sub;
+    for (int i = 0; i < dec->levels - 2; ++i) {
+      if (!dec->parents[i]) throw Error(AMBDDC_E_INVALID_ARG, "null parent map");
+      std::vector<int> p(dec->parents[i], dec->parents[i] + nsub);
+      int np = 0;
+      for (int v : p) {
+        if (v < 0) throw Error(AMBDDC_E_INVALID_ARG, "negative parent id");
+        np = std::max(np, v + 1);
+      }
+      c->parents.push_back(p);
+      nsub = np;
+    }
+    hipStream_t st = c->st;
+    std::vector<double> xy(mesh->coords, mesh->coords + size_t(mesh->n_nodes) * 3);
+    c->coords.upload(xy, st);
+    std::vector<int> en(mesh->elem_nodes, mesh->elem_nodes + size_t(mesh->n_elems) * 8);
+    c->en.upload(en, st);
+    c->edofs.upload(c->plan0.in.elem_dofs, st);
+    const int ne = 8 * c->dof;
+    c->Ke.alloc(size_t(mesh->n_elems) * ne * ne);
+    // global CSR pattern of the free DOFs and row incidences
+    {
+      const int nn = mesh->n_nodes, d = c->dof;
+      std::vector<int> nptr(nn + 1, 0);
+      for (int e2 = 0; e2 < mesh->n_elems; ++e2)
+        for (int a = 0; a < 8; ++a) nptr[en[size_t(e2) * 8 + a] + 1]++;
+      for (int i = 0; i < nn; ++i) nptr[i + 1] += nptr[i];
+      std::vector<int> nel(nptr[nn]), nla(nptr[nn]);
+      {
+        std::vector<int> f(nptr.begin(), nptr.end() - 1);
+        for (int e2 = 0; e2 < mesh->n_elems; ++e2)
+          for (int a = 0; a < 8; ++a) {
+            const int nd = en[size_t(e2) * 8 + a];
+            nel[f[nd]] = e2;
+            nla[f[nd]++] = a;
+          }
+      }
+      const int nf = c->plan0.in.n_dof;
+      std::vector<int> rowptr(nf + 1, 0), cols;
+      std::vector<int64_t> incp(nf + 1, 0);
+      std::vector<int> ie, ia;
+      std::vector<int> row_of_free(nf);
+      for (int nd = 0; nd < nn; ++nd)
+        for (int q = 0; q < d; ++q) {
+          const int fi = c->free_of_full[size_t(nd) * d + q];
+          if (fi < 0) continue;
+          std::vector<int> cc;
+          for (int k = nptr[nd]; k < nptr[nd + 1]; ++k) {
+            const int e2 = nel[k];
+            for (int b = 0; b < ne; ++b) {
+              const int cj = c->plan0.in.elem_dofs[size_t(e2) * ne + b];
+              if (cj >= 0) cc.push_back(cj);
+            }
+            ie.push_back(e2);
+            ia.push_back(nla[k] * d + q);
+          }
+          std::sort(cc.begin(), cc.end());
+          cc.erase(std::unique(cc.begin(), cc.end()), cc.end());
+          cols.insert(cols.end(), cc.begin(), cc.end());
+          rowptr[fi + 1] = int(cols.size());
+          incp[fi + 1] = int64_t(ie.size());
+        }
+      c->csr.n = nf;
+      c->csr.rowptr.upload(rowptr, st);
+      c->csr.cols.upload(cols, st);
+      c->csr.inc_ptr.upload(incp, st);
+      c->csr.inc_e.upload(ie, st);
+      c->csr.inc_a.upload(ia, st);
+      c->csr_vals.alloc(cols.size());
+    }
+    // level-1 structures that do not depend on the coefficients or constraints
+    auto L0 = std::make_unique<Level>();
+    L0->plan = c->plan0;
+    std::vector<int64_t> eoff(mesh->n_elems);
+    for (int e2 = 0; e2 < mesh->n_elems; ++e2) eoff[e2] = int64_t(e2) * ne * ne;
+    build_level_maps(*c, *L0, c->Ke.p, eoff);
+    L0->rigid.alloc(size_t(L0->ndof) * L0->nrb);
+    {
+      DBuf<int> fof;
+      fof.upload(c->free_of_full, st);
+      launch_rigid_level1(mesh->n_nodes, c->dof, c->coords.p, fof.p, L0->ndof, L0->rigid.p, st);
+      AMB_HIP(hipStreamSynchronize(st));
+    }
+    c->L.push_back(std::move(L0));
+    *out = c.release();
+  }));
+}
+
+ambddc_status ambddc_setup(ambddc_handle h, const double* coeff, const double* nu) {
+  return ambddc_status(guard([&] {
+    if (!h || !coeff) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (h->dof == 3 && !nu) throw Error(AMBDDC_E_INVALID_ARG, "elasticity needs nu");
+    setup_impl(*h, coeff, nu);
+  }));
+}
+
+ambddc_status ambddc_solve(ambddc_handle h, const double* rhs, int32_t nrhs, double rtol,
+                           int32_t maxit, double* x, int32_t* iterations, double* cond) {
+  int code = guard([&] {
+    if (!h || !rhs || !x) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (!h->ready) throw Error(AMBDDC_E_STATE, "solve called before a successful setup");
+    if (nrhs < 1 || nrhs > 16) throw Error(AMBDDC_E_INVALID_ARG, "nrhs must be in 1..16");
+    if (maxit < 1 || !(rtol > 0.0)) throw Error(AMBDDC_E_INVALID_ARG, "bad rtol or maxit");
+    std::vector<int> its(nrhs, 0);
+    std::vector<double> cd(nrhs, 0.0);
+    const int left = pcg_impl(*h, rhs, nrhs, rtol, maxit, x, its.data(), cd.data());
+    if (iterations) std::copy(its.begin(), its.end(), iterations);
+    if (cond) std::copy(cd.begin(), cd.end(), cond);
+    if (left > 0)
+      throw Error(AMBDDC_E_NO_CONVERGENCE,
+                  std::to_string(left) + " right-hand side(s) did not reach rtol in maxit");
+  });
+  return ambddc_status(code);
+}
+
+ambddc_status ambddc_element_gradient(ambddc_handle h, const double* X, const double* Lam,
+                                      int32_t nrhs, double* grad) {
+  return ambddc_status(guard([&] {
+    if (!h || !X || !Lam || !grad) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (!h->ready) throw Error(AMBDDC_E_STATE, "gradient needs a setup");
+    launch_element_gradient(h->n_elems, 8 * h->dof, h->L[0]->ndof, nrhs, h->edofs.p, h->Ke.p, X, Lam,
+                            grad, h->st);
+    AMB_HIP(hipStreamSynchronize(h->st));
+  }));
+}
+
+ambddc_status ambddc_get_stats(ambddc_handle h, ambddc_stats* out) {
+  return ambddc_status(guard([&] {
+    if (!h || !out) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    *out = h->stats;
+  }));
+}
+
+ambddc_status ambddc_level_info(ambddc_handle h, int32_t level, int32_t* n_dof, int32_t* n_sub,
+                                int32_t* n_pairs, int32_t* n_coarse) {
+  return ambddc_status(guard([&] {
+    if (!h || level < 0 || level >= int(h->L.size()))
+      throw Error(AMBDDC_E_INVALID_ARG, "bad handle or level");
+    const Level& L = *h->L[level];
+    if (n_dof) *n_dof = L.ndof;
+    if (n_sub) *n_sub = L.nsub;
+    if (n_pairs) *n_pairs = int(L.plan.pairs.size());
+    if (n_coarse) *n_coarse = L.ncoarse;
+  }));
+}
+
+ambddc_status ambddc_sub_dofs(ambddc_handle h, int32_t level, int32_t sub, int32_t* dofs,
+                              int32_t* n_I, int32_t* n_G) {
+  return ambddc_status(guard([&] {
+    if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
+    const Level& L = *h->L[level];
+    if (sub < 0 || sub >= L.nsub) throw Error(AMBDDC_E_INVALID_ARG, "bad subdomain");
+    const Sub& S = L.plan.subs[sub];
+    if (n_I) *n_I = S.nI;
+    if (n_G) *n_G = S.nG;
+    if (dofs) std::copy(S.dofs.begin(), S.dofs.end(), dofs);
+  }));
+}
+
+ambddc_status ambddc_get_schur(ambddc_handle h, int32_t level, int32_t sub, double* S) {
+  return ambddc_status(guard([&] {
+    if (!h || !S || level < 0 || level >= int(h->L.size()))
+      throw Error(AMBDDC_E_INVALID_ARG, "bad argument");
+    const Level& L = *h->L[level];
+    if (sub < 0 || sub >= L.nsub || !L.aug.p) throw Error(AMBDDC_E_INVALID_ARG, "bad subdomain");
+    const int nG = L.nG[sub], nI = L.nI[sub], N = L.augN[sub];
+    AMB_HIP(hipMemcpy2DAsync(S, sizeof(double) * nG,
+                             L.aug.p + L.aug_off[sub] + nI + int64_t(nI) * N, sizeof(double) * N,
+                             sizeof(double) * nG, nG, hipMemcpyDeviceToHost, h->st));
+    AMB_HIP(hipStreamSynchronize(h->st));
+  }));
+}
+
+ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int32_t* s, int32_t* t,
+                               int32_t* n_face) {
+  return ambddc_status(guard([&] {
+    if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
+    const Level& L = *h->L[level];
+    if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
+    const Pair& P = L.plan.pairs[pair];
+    if (s) *s = P.s;
+    if (t) *t = P.t;
+    if (n_face) *n_face = int(P.face_dofs.size());
+  }));
+}
+
+ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, double* lam,
+                                     double* resid, int32_t* k, double* lam_next, int32_t* iters,
+                                     int32_t* converged) {
+  return ambddc_status(guard([&] {
+    if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
+    const Level& L = *h->L[level];
+    if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
+    if (L.pair_k.empty()) throw Error(AMBDDC_E_STATE, "no adaptive results on this level");
+    if (lam) std::copy(L.pair_lam.begin() + size_t(pair) * L.m,
+                       L.pair_lam.begin() + size_t(pair + 1) * L.m, lam);
+    if (resid) std::copy(L.pair_res.begin() + size_t(pair) * L.m,
+                         L.pair_res.begin() + size_t(pair + 1) * L.m, resid);
+    if (k) *k = L.pair_k[pair];
+    if (lam_next) *lam_next = L.pair_lnext[pair];
+    if (iters) *iters = L.lobpcg_its;
+    if (converged) *converged = L.pair_conv[pair];
+  }));
+}
+
+ambddc_status ambddc_get_face_constraints(ambddc_handle h, int32_t level, int32_t pair, double* rows,
+                                          int32_t* face_dofs) {
+  return ambddc_status(guard([&] {
+    if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
+    const Level& L = *h->L[level];
+    if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
+    const Pair& P = L.plan.pairs[pair];
+    if (face_dofs) std::copy(P.face_dofs.begin(), P.face_dofs.end(), face_dofs);
+    if (rows && !L.pair_k.empty() && L.pair_k[pair] > 0) {
+      const size_t cnt = size_t(L.pair_k[pair]) * P.face_dofs.size();
+      AMB_HIP(hipMemcpyAsync(rows, L.fc.p + L.fc_off[pair], sizeof(double) * cnt,
+                             hipMemcpyDeviceToHost, h->st));
+      AMB_HIP(hipStreamSynchronize(h->st));
+    }
+  }));
+}
+
+ambddc_status ambddc_get_coarse_element(ambddc_handle h, int32_t level, int32_t sub, double* Kc,
+                                        int32_t* nc) {
+  return ambddc_status(guard([&] {
+    if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
+    const Level& L = *h->L[level];
+    if (sub < 0 || sub >= L.nsub || L.nc.empty()) throw Error(AMBDDC_E_INVALID_ARG, "bad subdomain");
+    if (nc) *nc = L.nc[sub];
+    if (Kc && L.nc[sub] > 0) {
+      AMB_HIP(hipMemcpyAsync(Kc, L.kc.p + L.kc_off[sub], sizeof(double) * L.nc[sub] * L.nc[sub],
+                             hipMemcpyDeviceToHost, h->st));
+      AMB_HIP(hipStreamSynchronize(h->st));
+    }
+  }));
+}
+
+ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc, int32_t* n) {
+  return ambddc_status(guard([&] {
+    if (!h) throw Error(AMBDDC_E_INVALID_ARG, "null handle");
+    if (n) *n = h->top.n;
+    if (Kc && h->top.n > 0) {
+      if (!h->top.Kc.p) throw Error(AMBDDC_E_STATE, "coarse matrix too large to keep a copy");
+      AMB_HIP(hipMemcpyAsync(Kc, h->top.Kc.p, sizeof(double) * h->top.Kc.n, hipMemcpyDeviceToHost,
+                             h->st));
+      AMB_HIP(hipStreamSynchronize(h->st));
+    }
+  }));
+}
+
+void ambddc_destroy(ambddc_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->st);
+  delete h;
+}
+
+}  // extern "C"

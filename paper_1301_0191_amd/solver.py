@@ -1,0 +1,225 @@
+"""Python surface of the HIP library: a handle with the C ABI's calls.
+
+PyTorch provides device memory and the stream; every numeric step runs in
+libambddc.so (see include/ambddc.h for the semantics of each call).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on the GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def analyze(coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, face_averages=False):
+    """Host-only level-1 structure counts and per-subdomain (n_I, n_Gamma)."""
+    lib = _lib.load()
+    co = np.ascontiguousarray(coords, dtype=np.float64)
+    en = np.ascontiguousarray(elem_nodes, dtype=np.int32)
+    di = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    e2s = np.ascontiguousarray(elem_to_sub, dtype=np.int32)
+    mesh = _lib.Mesh(co.shape[0], en.shape[0], dof_per_node, _ptr(co, C.c_double),
+                     _ptr(en, C.c_int32), _ptr(di, C.c_uint8))
+    dec = _lib.Decomp(2, _ptr(e2s, C.c_int32), None)
+    out = _lib.Analysis()
+    nsub = int(e2s.max()) + 1
+    sizes = np.zeros(2 * nsub, dtype=np.int32)
+    _lib.check(lib.ambddc_analyze(C.byref(mesh), C.byref(dec), int(bool(face_averages)),
+                                  C.byref(out), sizes.ctypes.data_as(C.c_void_p), nsub))
+    d = {f: getattr(out, f) for f, _ in _lib.Analysis._fields_}
+    d["sub_sizes"] = sizes.reshape(nsub, 2)
+    return d
+
+
+@dataclass
+class SolveResult:
+    x: object
+    iterations: list
+    cond: list
+
+
+class Handle:
+    """One problem: mesh + decomposition (create), coefficients (setup), solves."""
+
+    def __init__(self, coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, parents=(),
+                 levels=2, tau=10.0, nev_max=10, lobpcg_maxit=100, lobpcg_block=16,
+                 lobpcg_tol=1e-7, face_averages=False, seed=12345, stream=None):
+        lib = _lib.load()
+        self._lib = lib
+        self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self._en = np.ascontiguousarray(elem_nodes, dtype=np.int32)
+        self._dir = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        self._e2s = np.ascontiguousarray(elem_to_sub, dtype=np.int32)
+        self._par = [np.ascontiguousarray(p, dtype=np.int32) for p in parents]
+        mesh = _lib.Mesh(self._coords.shape[0], self._en.shape[0], dof_per_node,
+                         _ptr(self._coords, C.c_double), _ptr(self._en, C.c_int32),
+                         _ptr(self._dir, C.c_uint8))
+        par_arr = (C.POINTER(C.c_int32) * max(1, len(self._par)))(
+            *[_ptr(p, C.c_int32) for p in self._par])
+        dec = _lib.Decomp(levels, _ptr(self._e2s, C.c_int32), par_arr)
+        opt = _lib.Options()
+        lib.ambddc_default_options(C.byref(opt))
+        opt.tau = float(tau)
+        opt.nev_max = int(nev_max)
+        opt.lobpcg_maxit = int(lobpcg_maxit)
+        opt.lobpcg_block = int(lobpcg_block)
+        opt.lobpcg_tol = float(lobpcg_tol)
+        opt.face_averages = int(bool(face_averages))
+        opt.seed = int(seed)
+        if stream is None:
+            torch = _torch()
+            stream = torch.cuda.current_stream().cuda_stream
+        opt.stream = C.c_void_p(stream)
+        h = C.c_void_p()
+        _lib.check(lib.ambddc_create(C.byref(mesh), C.byref(dec), C.byref(opt), C.byref(h)))
+        self._h = h
+        self.dof_per_node = dof_per_node
+        self.n_elems = int(self._en.shape[0])
+        self.n_free = int(np.count_nonzero(self._dir == 0))
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        kw.setdefault("tau", prob.tau)
+        kw.setdefault("nev_max", prob.nev_max)
+        return cls(prob.coords, prob.elem_nodes, prob.dirichlet, prob.dof_per_node,
+                   prob.elem_to_sub, prob.parents, levels=prob.levels, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ambddc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- numeric calls --------------------------------------------------
+    def setup(self, coeff, nu=None, check=True):
+        """coeff, nu: float64 GPU tensors of length n_elems."""
+        code = self._lib.ambddc_setup(self._h, _dev_ptr(coeff), None if nu is None else _dev_ptr(nu))
+        if check:
+            _lib.check(code)
+        return code
+
+    def solve(self, rhs, rtol=1e-10, maxit=1000, x=None, raise_on_noconv=True):
+        """rhs: float64 GPU tensor (n_free,) or (nrhs, n_free) (row r = column r)."""
+        torch = _torch()
+        r2 = rhs if rhs.dim() == 2 else rhs.view(1, -1)
+        nrhs = r2.shape[0]
+        if x is None:
+            x = torch.empty_like(r2)
+        its = (C.c_int32 * nrhs)()
+        cond = (C.c_double * nrhs)()
+        code = self._lib.ambddc_solve(self._h, _dev_ptr(r2), nrhs, float(rtol), int(maxit),
+                                      _dev_ptr(x), its, cond)
+        if code != 0 and (raise_on_noconv or code != 4):
+            _lib.check(code)
+        xs = x if rhs.dim() == 2 else x.view(-1)
+        return SolveResult(xs, list(its), list(cond))
+
+    def element_gradient(self, X, Lam):
+        torch = _torch()
+        X2 = X if X.dim() == 2 else X.view(1, -1)
+        L2 = Lam if Lam.dim() == 2 else Lam.view(1, -1)
+        g = torch.empty(self.n_elems, dtype=torch.float64, device=X.device)
+        _lib.check(self._lib.ambddc_element_gradient(self._h, _dev_ptr(X2), _dev_ptr(L2),
+                                                     X2.shape[0], _dev_ptr(g)))
+        return g
+
+    # --- introspection --------------------------------------------------
+    def stats(self):
+        s = _lib.Stats()
+        _lib.check(self._lib.ambddc_get_stats(self._h, C.byref(s)))
+        L = s.levels
+        return dict(levels=L, n_free=s.n_free, n_sub=list(s.n_sub[:L]),
+                    n_pairs=list(s.n_pairs[:L]), n_coarse=list(s.n_coarse[:L]),
+                    n_adaptive=list(s.n_adaptive[:L]), lobpcg_iters=list(s.lobpcg_iters[:L]),
+                    n_unconverged=list(s.n_unconverged[:L]),
+                    omega_tilde=list(s.omega_tilde[:L]), t_phase=list(s.t_phase[:8]))
+
+    def level_info(self, level):
+        a = [C.c_int32() for _ in range(4)]
+        _lib.check(self._lib.ambddc_level_info(self._h, level, *[C.byref(x) for x in a]))
+        return dict(n_dof=a[0].value, n_sub=a[1].value, n_pairs=a[2].value,
+                    n_coarse=a[3].value)
+
+    def sub_dofs(self, level, sub):
+        nI, nG = C.c_int32(), C.c_int32()
+        _lib.check(self._lib.ambddc_sub_dofs(self._h, level, sub, None, C.byref(nI),
+                                             C.byref(nG)))
+        d = np.empty(nI.value + nG.value, dtype=np.int32)
+        _lib.check(self._lib.ambddc_sub_dofs(self._h, level, sub, d.ctypes.data_as(C.c_void_p),
+                                             C.byref(nI), C.byref(nG)))
+        return d, nI.value, nG.value
+
+    def schur(self, level, sub):
+        _, nI, nG = self.sub_dofs(level, sub)
+        S = np.empty((nG, nG), dtype=np.float64, order="F")
+        _lib.check(self._lib.ambddc_get_schur(self._h, level, sub, S.ctypes.data_as(C.c_void_p)))
+        return S
+
+    def pair_info(self, level, pair):
+        s, t, nf = C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(self._lib.ambddc_pair_info(self._h, level, pair, C.byref(s), C.byref(t),
+                                              C.byref(nf)))
+        return s.value, t.value, nf.value
+
+    def pair_result(self, level, pair, block=16):
+        lam = np.zeros(block, dtype=np.float64)
+        res = np.zeros(block, dtype=np.float64)
+        k, it, cv = C.c_int32(), C.c_int32(), C.c_int32()
+        ln = C.c_double()
+        _lib.check(self._lib.ambddc_get_pair_result(self._h, level, pair,
+                                                    lam.ctypes.data_as(C.c_void_p),
+                                                    res.ctypes.data_as(C.c_void_p), C.byref(k),
+                                                    C.byref(ln), C.byref(it), C.byref(cv)))
+        return dict(lam=lam, resid=res, k=k.value, lam_next=ln.value, iters=it.value,
+                    converged=bool(cv.value))
+
+    def face_constraints(self, level, pair, k):
+        _, _, nf = self.pair_info(level, pair)
+        rows = np.zeros((max(k, 0), nf), dtype=np.float64)
+        fd = np.zeros(nf, dtype=np.int32)
+        _lib.check(self._lib.ambddc_get_face_constraints(
+            self._h, level, pair, rows.ctypes.data_as(C.c_void_p), fd.ctypes.data_as(C.c_void_p)))
+        return rows, fd
+
+    def coarse_element(self, level, sub):
+        nc = C.c_int32()
+        _lib.check(self._lib.ambddc_get_coarse_element(self._h, level, sub, None, C.byref(nc)))
+        K = np.zeros((nc.value, nc.value), dtype=np.float64, order="F")
+        if nc.value:
+            _lib.check(self._lib.ambddc_get_coarse_element(
+                self._h, level, sub, K.ctypes.data_as(C.c_void_p), C.byref(nc)))
+        return K
+
+    def top_coarse(self):
+        n = C.c_int32()
+        _lib.check(self._lib.ambddc_get_top_coarse(self._h, None, C.byref(n)))
+        K = np.zeros((n.value, n.value), dtype=np.float64, order="F")
+        if n.value:
+            _lib.check(self._lib.ambddc_get_top_coarse(self._h, K.ctypes.data_as(C.c_void_p),
+                                                       C.byref(n)))
+        return K
