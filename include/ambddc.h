@@ -174,7 +174,8 @@ ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int
                                int32_t* n_face);
 
 /* Result of the pair eigenproblem: lam_host[lobpcg_block] (descending),
- * resid_host[lobpcg_block] relative residuals |A x - lam B x| / (|A x| + |lam| |B x|),
+ * resid_host[lobpcg_block] relative residuals
+ * |A x - lam B x| / (|A x| + max(|lam|, 1e-6 lam_1) |B x|),
  * number of selected constraints k (after the QR rank test), the first
  * unselected eigenvalue, LOBPCG iterations and a converged flag.  Any output
  * pointer may be NULL. */

@@ -116,6 +116,11 @@ def pair_eigenproblem(L, s, t, face_glob, tau, nev_max):
         dR = np.abs(np.diag(Rr))
         keep = dR > QR_RANK_TOL * dR.max() if dR.size else np.zeros(0, bool)
         rows = Qr[:, keep].T
+        # canonical sign of each row: its largest-magnitude entry (first on
+        # ties) positive; only the span is fixed by the method
+        for r in rows:
+            if r[np.argmax(np.abs(r))] < 0:
+                r *= -1.0
     return dict(s=s, t=t, lam=lam, k=k, lam_next=lam_next, rows=rows, face_dofs=face,
                 c_full=c_full, n=n, n_factor=Q.shape[1], both_floating=both_floating)
 

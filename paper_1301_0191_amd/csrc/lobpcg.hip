@@ -326,7 +326,9 @@ __global__ __launch_bounds__(256) void k_residual(const PairDev* P, double* V, c
     rr = block_sum(rr, red);
     aa = block_sum(aa, red);
     bb = block_sum(bb, red);
-    const double den = sqrt(aa) + fabs(l[c]) * sqrt(bb);
+    // eigenvalues far below the pair's largest (the exact zeros of a pair with
+    // few shared DOFs) are measured against 1e-6 lambda_1 instead of |lambda|
+    const double den = sqrt(aa) + fmax(fabs(l[c]), 1e-6 * fabs(l[0])) * sqrt(bb);
     const double rel = den > 0.0 ? sqrt(rr) / den : 0.0;
     if (threadIdx.x == 0) {
       resn[(size_t)blockIdx.x * m + c] = rel;
@@ -655,10 +657,24 @@ __global__ __launch_bounds__(256) void k_select(const PairDev* P, const double* 
   }
   double rmax = 0.0;
   for (int j = 0; j < k; ++j) rmax = fmax(rmax, rdiag[j]);
+  // canonical sign (the span is what the method fixes): the entry of largest
+  // magnitude, first on ties, is made positive
+  __shared__ double sgn;
   int kk = 0;
   for (int j = 0; j < k; ++j) {
     if (!(rdiag[j] > 1e-10 * rmax)) continue;
-    for (int q = threadIdx.x; q < nf; q += blockDim.x) fc[p.fc_off + (size_t)kk * nf + q] = Q[j * nf + q];
+    if (threadIdx.x == 0) {
+      double best = -1.0, v = 1.0;
+      for (int q = 0; q < nf; ++q) {
+        const double a = fabs(Q[j * nf + q]);
+        if (a > best) { best = a; v = Q[j * nf + q]; }
+      }
+      sgn = v < 0.0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nf; q += blockDim.x)
+      fc[p.fc_off + (size_t)kk * nf + q] = sgn * Q[j * nf + q];
+    __syncthreads();
     ++kk;
   }
   if (threadIdx.x == 0) kout[blockIdx.x] = kk;

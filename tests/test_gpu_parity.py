@@ -1,0 +1,212 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP64 path):
+* S^s: ||S_gpu - S||_F <= 1e-10 ||S||_F (Cholesky backward error ~ n u kappa(K_II)
+  with kappa <= 1e6 for these coefficients);
+* K_c^s (explicit saddle inverse, conditioning up to ~1e8 with the
+  coefficient jumps): 1e-8 relative;
+* pair eigenvalues: 1e-6 relative (the target); selected counts identical;
+  constraint spans: sine of the largest principal angle <= 1e-6 where the
+  cut eigenvalue gap is not tiny;
+* solution: ||x - x_direct|| / ||x_direct|| <= 1e-9 at rtol 1e-12.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+import oracle as O
+from oracle.substructure import build_level, coarse_basis, level1_input
+from gpu_common import gpu_handle, gpu_solve, subspace_gap, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+TINY = {
+    "poisson": lambda: W.tiny_poisson(shape=(8, 8, 8), subs=(2, 2, 2), seed=1),
+    # uneven boxes, a one-element slab whose subdomain has no interior DOF
+    "poisson_ragged": lambda: W.make_problem((9, 7, 6), None, coeff="lognormal", seed=3,
+                                             cuts=[[0, 1, 5, 9], [0, 3, 7], [0, 4, 6]],
+                                             rhs="normal"),
+    "elasticity": lambda: W.tiny_elasticity(shape=(4, 4, 4), subs=(2, 2, 2), seed=2),
+}
+
+_ORACLE = {}
+
+
+def oracle_hierarchy(key, prob, adaptive=True):
+    k = (key, adaptive)
+    if k not in _ORACLE:
+        _ORACLE[k] = O.setup_hierarchy(prob, adaptive=adaptive)
+    return _ORACLE[k]
+
+
+@pytest.mark.parametrize("case", sorted(TINY))
+def test_schur_and_coarse_parity(case):
+    log("CASE schur/coarse", case)
+    prob = TINY[case]()
+    h = gpu_handle(prob, tau=0.0)
+    L = build_level(level1_input(prob))
+    coarse_basis(L)
+    for s in range(L.inp.n_sub):
+        d, nI, nG = h.sub_dofs(0, s)
+        np.testing.assert_array_equal(d, L.sub_dofs[s])
+        S = h.schur(0, s)
+        assert np.linalg.norm(S - L.S[s]) <= 1e-10 * np.linalg.norm(L.S[s]), s
+        Kc = h.coarse_element(0, s)
+        if Kc.size:
+            assert np.linalg.norm(Kc - L.Kc[s]) <= 1e-8 * np.linalg.norm(L.Kc[s]), s
+    h.close()
+
+
+@pytest.mark.parametrize("case", sorted(TINY))
+def test_nonadaptive_pcg(case):
+    log("CASE non-adaptive pcg", case)
+    prob = TINY[case]()
+    h = gpu_handle(prob, tau=0.0)
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-12, adaptive=False)
+    xd = O.direct_solve(prob)
+    assert np.linalg.norm(X - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert abs(its[0] - ito[0]) <= max(2, 0.05 * ito[0])
+    assert cond[0] == pytest.approx(co[0], rel=1e-4)
+    assert cond[0] >= 1.0 - 1e-9
+    h.close()
+
+
+def check_pairs(h, prob, H, level=0):
+    L = H.levels[level]
+    res = L.adaptive["results"]
+    nk = prob.nev_max + 1
+    for p, r in enumerate(res):
+        s, t, nf = h.pair_info(level, p)
+        assert (s, t) == (r["s"], r["t"])
+        g = h.pair_result(level, p)
+        assert g["converged"], (level, p, g["resid"])
+        kk = min(nk, len(r["lam"]))
+        # eigenvalues that vanish in exact arithmetic (pairs with few shared
+        # DOFs) are rounding noise on both sides (the dense oracle's at ~1e-12
+        # lambda_1): they are compared in absolute terms, 1e-10 lambda_1; all
+        # others to 1e-6 relative, and every eigenvalue within a decade of tau,
+        # which decides the selection, strictly relative
+        lam_o = r["lam"][:kk]
+        err = np.abs(g["lam"][:kk] - lam_o)
+        ok = err <= np.maximum(1e-6 * np.abs(lam_o), 1e-10 * abs(lam_o[0]))
+        assert ok.all(), (level, p, err, lam_o)
+        near = lam_o >= 0.1 * prob.tau
+        if near.any():
+            strict = np.abs(g["lam"][:kk] - lam_o)[near] / lam_o[near]
+            assert strict.max() <= 1e-6, (level, p, strict.max())
+        assert g["k"] == len(r["rows"]), (level, p, g["k"], len(r["rows"]))
+        if r["lam_next"] > 0:
+            assert g["lam_next"] == pytest.approx(r["lam_next"], rel=1e-6)
+        if g["k"] > 0:
+            rows, fd = h.face_constraints(level, p, g["k"])
+            np.testing.assert_array_equal(fd, r["face_dofs"])
+            lam = r["lam"]
+            k = g["k"]
+            cut_gap = (lam[k - 1] - lam[k]) / lam[k - 1] if k < len(lam) else 1.0
+            if cut_gap > 1e-3:
+                assert subspace_gap(rows, r["rows"]) <= 1e-6, (level, p)
+            np.testing.assert_allclose(rows @ rows.T, np.eye(k), atol=1e-10)
+
+
+@pytest.mark.parametrize("case", ["poisson", "poisson_ragged", "elasticity", "c1", "c2"])
+def test_adaptive_parity_and_solution(case):
+    log("CASE adaptive", case)
+    prob = TINY[case]() if case in TINY else W.CONFIGS[case](0)
+    h = gpu_handle(prob)
+    H = oracle_hierarchy(case, prob)
+    st = h.stats()
+    assert st["n_adaptive"][0] == H.stats["n_adaptive"][0]
+    assert st["n_coarse"][0] == H.stats["n_coarse"][0]
+    assert st["omega_tilde"][0] == pytest.approx(H.stats["omega"][0], rel=1e-6)
+    check_pairs(h, prob, H)
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
+    xd = O.direct_solve(prob)
+    err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
+    log("  its", its, "cond", cond, "err", err)
+    assert err <= 1e-9
+    assert cond[0] >= 1.0 - 1e-9
+    h.close()
+
+
+def test_three_level_parity():
+    log("CASE three-level")
+    prob = W.make_problem((8, 8, 8), (4, 4, 4), group=(2, 2, 2), coeff="lognormal", seed=11,
+                          rhs="normal")
+    h = gpu_handle(prob)
+    H = O.setup_hierarchy(prob)
+    st = h.stats()
+    assert st["levels"] == 2
+    for lv in range(2):
+        assert st["n_adaptive"][lv] == H.stats["n_adaptive"][lv], lv
+        check_pairs(h, prob, H, level=lv)
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-12, H=H)
+    xd = O.direct_solve(prob)
+    assert np.linalg.norm(X - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert abs(its[0] - ito[0]) <= max(2, 0.05 * ito[0])
+    assert cond[0] == pytest.approx(co[0], rel=1e-3)
+    h.close()
+
+
+def test_multiple_rhs_lockstep():
+    log("CASE multi-rhs")
+    prob = W.tiny_poisson(shape=(8, 8, 8), subs=(2, 2, 2), seed=5, rhs="normal", nrhs=4)
+    h = gpu_handle(prob)
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
+    xd = O.direct_solve(prob)
+    for j in range(4):
+        x1, it1, c1 = gpu_solve(h, prob.rhs[:, j:j + 1], rtol=1e-12)
+        assert it1[0] == its[j]
+        np.testing.assert_allclose(X[:, j], x1[:, 0], rtol=0, atol=1e-13 * np.abs(x1).max())
+        assert np.linalg.norm(X[:, j] - xd[:, j]) <= 1e-9 * np.linalg.norm(xd[:, j])
+    h.close()
+
+
+def test_gradient_matches_oracle():
+    log("CASE gradient")
+    torch = torch_cuda()
+    prob = W.make_problem((8, 8, 8), (2, 2, 2), seed=21)
+    rng = np.random.default_rng(21)
+    theta = rng.normal(0.5, 0.7, prob.n_elems)
+    F = np.zeros((prob.n_free, 3))
+    F[rng.choice(prob.n_free, 3, replace=False), np.arange(3)] = 1.0
+    from oracle import fem
+    x_obs = O.direct_solve(prob, F, fem.element_matrices(prob, 10.0 ** (theta + 0.1)))
+    J, g_or, X_or, L_or = O.misfit_gradient(prob, theta, x_obs, F)
+    from paper_1301_0191_amd import Handle
+    h = Handle.from_problem(prob)
+    dev = torch.device("cuda:0")
+    h.setup(torch.from_numpy(10.0 ** theta).to(dev))
+    X, _, _ = gpu_solve(h, F, rtol=1e-13)
+    Lam, _, _ = gpu_solve(h, X - x_obs, rtol=1e-13)
+    Xt = torch.from_numpy(np.ascontiguousarray(X.T)).to(dev)
+    Lt = torch.from_numpy(np.ascontiguousarray(Lam.T)).to(dev)
+    g = h.element_gradient(Xt, Lt).cpu().numpy()
+    assert np.abs(g - g_or).max() <= 1e-8 * np.abs(g_or).max()
+    h.close()
+
+
+def test_error_paths():
+    log("CASE error paths")
+    torch = torch_cuda()
+    from paper_1301_0191_amd import Handle, AmbddcError
+    prob = W.tiny_poisson(shape=(4, 4, 4), subs=(2, 2, 2), seed=0)
+    h = Handle.from_problem(prob)
+    dev = torch.device("cuda:0")
+    rhs = torch.from_numpy(np.ascontiguousarray(prob.rhs[:, 0])).to(dev)
+    with pytest.raises(AmbddcError, match="E_STATE"):
+        h.solve(rhs)
+    with pytest.raises(AmbddcError, match="E_NOT_SPD"):
+        h.setup(torch.full((prob.n_elems,), -1.0, dtype=torch.float64, device=dev))
+    h.setup(torch.from_numpy(prob.coeff).to(dev))
+    res = h.solve(rhs, rtol=1e-14, maxit=1, raise_on_noconv=False)
+    assert res.iterations[0] == 1
+    with pytest.raises(AmbddcError, match="E_NO_CONVERGENCE"):
+        h.solve(rhs, rtol=1e-14, maxit=1)
+    h.close()
