@@ -383,53 +383,77 @@ __device__ inline int sturm_count(const double* d, const double* e2, int k, doub
   return cnt;
 }
 
-__global__ void k_lanczos(int nrhs, const int* nalpha, const double* alpha, const double* beta,
-                          int maxit, double* out, double* work) {
+// Extreme eigenvalues by parallel multisection: every thread evaluates the
+// Sturm count at one point of the current bracket, which shrinks by the
+// block size per pass.
+__device__ inline double multisect(const double* d, const double* e2, int k, double lo, double hi,
+                                   int target, int* cnt) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int pass = 0; pass < 12; ++pass) {
+    const double h = (hi - lo) / (nt + 1);
+    cnt[tid] = sturm_count(d, e2, k, lo + (tid + 1) * h);
+    __syncthreads();
+    int first = nt;
+    for (int t = 0; t < nt; ++t)
+      if (cnt[t] >= target) { first = t; break; }
+    __syncthreads();
+    const double nlo = lo + first * h;
+    hi = lo + (first + 1) * h;
+    lo = nlo;
+  }
+  return 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(256) void k_lanczos(int nrhs, const int* nalpha, const double* alpha,
+                                                 const double* beta, int maxit, double* out,
+                                                 double* work) {
+  __shared__ int cnt[256];
+  __shared__ double bounds[2];
   const int c = blockIdx.x;
-  if (threadIdx.x != 0) return;
   const int k = nalpha[c];
-  if (k <= 0) { out[c] = 1.0; out[nrhs + c] = 1.0; out[2 * nrhs + c] = 1.0; return; }
+  if (k <= 0) {
+    if (threadIdx.x == 0) { out[c] = 1.0; out[nrhs + c] = 1.0; out[2 * nrhs + c] = 1.0; }
+    return;
+  }
   const double* a = alpha + (size_t)c * maxit;
   const double* b = beta + (size_t)c * maxit;
   double* d = work + (size_t)c * 2 * maxit;
   double* e2 = d + maxit;
-  d[0] = 1.0 / a[0];
-  for (int j = 1; j < k; ++j) {
-    d[j] = 1.0 / a[j] + b[j - 1] / a[j - 1];
-    const double e = sqrt(b[j - 1]) / a[j - 1];
-    e2[j - 1] = e * e;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    d[j] = (j == 0) ? 1.0 / a[0] : 1.0 / a[j] + b[j - 1] / a[j - 1];
+    if (j > 0) {
+      const double e = sqrt(b[j - 1]) / a[j - 1];
+      e2[j - 1] = e * e;
+    }
   }
-  double lo = 1e300, hi = -1e300;
-  for (int j = 0; j < k; ++j) {
-    double rr = 0.0;
-    if (j > 0) rr += sqrt(e2[j - 1]);
-    if (j < k - 1) rr += sqrt(e2[j]);
-    lo = fmin(lo, d[j] - rr);
-    hi = fmax(hi, d[j] + rr);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lo = 1e300, hi = -1e300;
+    for (int j = 0; j < k; ++j) {
+      double rr = 0.0;
+      if (j > 0) rr += sqrt(e2[j - 1]);
+      if (j < k - 1) rr += sqrt(e2[j]);
+      lo = fmin(lo, d[j] - rr);
+      hi = fmax(hi, d[j] + rr);
+    }
+    bounds[0] = lo;
+    bounds[1] = hi;
   }
-  // smallest: count(x) >= 1
-  double l = lo, h = hi;
-  for (int it = 0; it < 200; ++it) {
-    const double m = 0.5 * (l + h);
-    if (sturm_count(d, e2, k, m) >= 1) h = m; else l = m;
+  __syncthreads();
+  const double lmin = multisect(d, e2, k, bounds[0], bounds[1], 1, cnt);
+  const double lmax = multisect(d, e2, k, bounds[0], bounds[1], k, cnt);
+  if (threadIdx.x == 0) {
+    out[c] = lmax / lmin;
+    out[nrhs + c] = lmin;
+    out[2 * nrhs + c] = lmax;
   }
-  const double lmin = 0.5 * (l + h);
-  l = lo; h = hi;
-  for (int it = 0; it < 200; ++it) {
-    const double m = 0.5 * (l + h);
-    if (sturm_count(d, e2, k, m) >= k) h = m; else l = m;
-  }
-  const double lmax = 0.5 * (l + h);
-  out[c] = lmax / lmin;
-  out[nrhs + c] = lmin;
-  out[2 * nrhs + c] = lmax;
 }
 
 // out[0:nrhs] = cond, out[nrhs:2nrhs] = lambda_min, out[2nrhs:3nrhs] = lambda_max.
 // `out` must hold 3*nrhs + 2*maxit*nrhs doubles (the tail is scratch).
 void launch_lanczos_cond(int nrhs, const int* nalpha, const double* alpha, const double* beta,
                          int maxit, double* out, hipStream_t st) {
-  k_lanczos<<<nrhs, 64, 0, st>>>(nrhs, nalpha, alpha, beta, maxit, out, out + 3 * nrhs);
+  k_lanczos<<<nrhs, 256, 0, st>>>(nrhs, nalpha, alpha, beta, maxit, out, out + 3 * nrhs);
   AMB_LAUNCH_CHECK();
 }
 

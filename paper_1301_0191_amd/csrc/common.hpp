@@ -58,8 +58,10 @@ struct DBuf {
   void zero(hipStream_t st) {
     if (n) AMB_HIP(hipMemsetAsync(p, 0, n * sizeof(T), st));
   }
+  // Same-size uploads keep the allocation, so device pointers taken into the
+  // buffer (e.g. per-pair flags referenced by GEMM descriptors) stay valid.
   void upload(const std::vector<T>& v, hipStream_t st) {
-    alloc(v.size());
+    if (v.size() != n || !p) alloc(v.size());
     if (n) {
       AMB_HIP(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
       AMB_HIP(hipStreamSynchronize(st));   // the host vector may be a temporary

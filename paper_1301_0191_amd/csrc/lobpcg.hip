@@ -52,58 +52,53 @@ void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStr
 }
 
 // v <- Pi v (and, when deflating, remove the orthonormal pair rigid modes).
+// Each row of D = [C^s_sh, -C^t_sh] is supported on the DOFs of one shared
+// corner or edge only; its entries are listed in dr (pair-vector index and
+// position of the coefficient in the constraint buffer; t-side entries carry
+// the minus sign).  Rows have disjoint supports, so Pi subtracts each row's
+// component independently.
 __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, const double* C,
-                             const int* dr_s, const int* dr_t, const double* rb, bool deflate,
-                             double* sm) {
+                             const DRows dr, const double* rb, bool deflate, double* sm) {
   const int n = p.nGs + p.nGt;
   const int nd = p.dr1 - p.dr0;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // coefficients coef[r * ncol + c] = (d_r . v_c) / |d_r|^2
-  double* coef = sm;
+  double* coef = sm;   // [nd * ncol] then [nrb * ncol]
   for (int idx = tid; idx < nd * ncol; idx += nt) {
     const int r = idx / ncol, c = idx % ncol;
-    const double* cs = C + p.cs_off + dr_s[p.dr0 + r];
-    const double* ct = C + p.ct_off + dr_t[p.dr0 + r];
     const double* vc = v + (size_t)c * ldv;
     double dot = 0.0, nrm = 0.0;
-    for (int i = 0; i < p.nGs; ++i) {
-      const double a = cs[(size_t)i * p.ncs];
+    for (int q = dr.ptr[p.dr0 + r]; q < dr.ptr[p.dr0 + r + 1]; ++q) {
+      const int i = dr.idx[q];
+      const double a = (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
       dot += a * vc[i];
-      nrm += a * a;
-    }
-    for (int i = 0; i < p.nGt; ++i) {
-      const double a = ct[(size_t)i * p.nct];
-      dot -= a * vc[p.nGs + i];
       nrm += a * a;
     }
     coef[idx] = nrm > 0.0 ? dot / nrm : 0.0;
   }
   __syncthreads();
   if (nd > 0) {
-    for (int idx = tid; idx < n * ncol; idx += nt) {
-      const int i = idx % n, c = idx / n;
-      double corr = 0.0;
-      if (i < p.nGs) {
-        for (int r = 0; r < nd; ++r)
-          corr += coef[r * ncol + c] * C[p.cs_off + dr_s[p.dr0 + r] + (size_t)i * p.ncs];
-      } else {
-        const int it = i - p.nGs;
-        for (int r = 0; r < nd; ++r)
-          corr -= coef[r * ncol + c] * C[p.ct_off + dr_t[p.dr0 + r] + (size_t)it * p.nct];
-      }
-      v[i + (size_t)c * ldv] -= corr;
+    const int q0 = dr.ptr[p.dr0], q1 = dr.ptr[p.dr1];
+    for (int idx = tid; idx < (q1 - q0) * ncol; idx += nt) {
+      const int q = q0 + idx % (q1 - q0), c = idx / (q1 - q0);
+      int r = 0;
+      while (dr.ptr[p.dr0 + r + 1] <= q) ++r;
+      const int i = dr.idx[q];
+      const double a = (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
+      v[i + (size_t)c * ldv] -= coef[r * ncol + c] * a;
     }
   }
   __syncthreads();
   if (deflate && p.nrb > 0) {
     const double* R = rb + p.rb_off;
-    for (int idx = tid; idx < p.nrb * ncol; idx += nt) {
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    for (int idx = wave; idx < p.nrb * ncol; idx += nw) {
       const int r = idx / ncol, c = idx % ncol;
       const double* vc = v + (size_t)c * ldv;
       const double* rr = R + (size_t)r * n;
       double dot = 0.0;
-      for (int i = 0; i < n; ++i) dot += rr[i] * vc[i];
-      coef[idx] = dot;
+      for (int i = lane; i < n; i += 64) dot += rr[i] * vc[i];
+      for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+      if (lane == 0) coef[idx] = dot;
     }
     __syncthreads();
     for (int idx = tid; idx < n * ncol; idx += nt) {
@@ -117,20 +112,20 @@ __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, con
 }
 
 __global__ __launch_bounds__(256) void k_project(const PairDev* P, double* V, int m, int col,
-                                                 const double* C, const int* dr_s, const int* dr_t,
+                                                 const double* C, const DRows dr,
                                                  const double* rb, const int* active, bool deflate) {
   __shared__ double sm[64 * 16];
   if (active && !active[blockIdx.x]) return;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
-  pair_project(p, V + p.v_off + (size_t)col * m * n, n, m, C, dr_s, dr_t, rb, deflate, sm);
+  pair_project(p, V + p.v_off + (size_t)col * m * n, n, m, C, dr, rb, deflate, sm);
 }
 
 void lp_project(const PairDev* P, int np, double* V, int m, int col, const double* C,
-                const int* dr_s, const int* dr_t, const double* rb, const int* active, bool deflate,
+                const DRows dr, const double* rb, const int* active, bool deflate,
                 hipStream_t st) {
   if (np == 0) return;
-  k_project<<<np, 256, 0, st>>>(P, V, m, col, C, dr_s, dr_t, rb, active, deflate);
+  k_project<<<np, 256, 0, st>>>(P, V, m, col, C, dr, rb, active, deflate);
   AMB_LAUNCH_CHECK();
 }
 
@@ -186,8 +181,7 @@ __global__ __launch_bounds__(256) void k_from_slab_ab(const PairDev* P, const do
                                                       int col, double* AV, double* BV,
                                                       const double* diagG, const int* sh_s,
                                                       const int* sh_t, const double* C,
-                                                      const int* dr_s, const int* dr_t,
-                                                      const int* active) {
+                                                      const DRows dr, const int* active) {
   __shared__ double sm[64 * 16];
   if (active && !active[blockIdx.x]) return;
   const PairDev p = P[blockIdx.x];
@@ -213,17 +207,15 @@ __global__ __launch_bounds__(256) void k_from_slab_ab(const PairDev* P, const do
     av[p.nGs + it + (size_t)c * n] = -dt * a + ds * b;
   }
   __syncthreads();
-  pair_project(p, bv, n, m, C, dr_s, dr_t, nullptr, false, sm);
-  pair_project(p, av, n, m, C, dr_s, dr_t, nullptr, false, sm);
+  pair_project(p, bv, n, m, C, dr, nullptr, false, sm);
+  pair_project(p, av, n, m, C, dr, nullptr, false, sm);
 }
 
 void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, double* AV,
                      double* BV, const double* diagG, const int* sh_s, const int* sh_t,
-                     const double* C, const int* dr_s, const int* dr_t, const int* active,
-                     hipStream_t st) {
+                     const double* C, const DRows dr, const int* active, hipStream_t st) {
   if (np == 0) return;
-  k_from_slab_ab<<<np, 256, 0, st>>>(P, Y, m, col, AV, BV, diagG, sh_s, sh_t, C, dr_s, dr_t,
-                                     active);
+  k_from_slab_ab<<<np, 256, 0, st>>>(P, Y, m, col, AV, BV, diagG, sh_s, sh_t, C, dr, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -350,11 +342,14 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
   AMB_LAUNCH_CHECK();
 }
 
-// Rayleigh-Ritz on span(V) with SVQB orthonormalisation in the B inner
-// product: D = diag(GB)^{-1/2}, D GB D = U Theta U^T, keep theta > 1e-10
-// theta_max, T = D U Theta^{-1/2}; eig(T^T GA T) = Y Lambda Y^T, descending;
-// coefficients Cf = T Y[:, :m] (columns 0..m-1 of Cf2) and the same with the
-// X rows zeroed (columns m..2m-1, giving the new P).  Cf2 has ld 3m.
+// Rayleigh-Ritz on span(V).  The basis is made B-orthonormal with a
+// diagonally pivoted Cholesky factorisation of the scaled Gram matrix:
+// D = diag(GB)^{-1/2}, P^T (D GB D) P = L L^T, stopping at the first pivot
+// below 1e-12 (numerically dependent directions are dropped); then
+// T = D P[:, :r] L^{-T} gives V T with (V T)^T B (V T) = I.  The projected
+// matrix T^T GA T is diagonalised by Jacobi, eigenvalues descending, and the
+// coefficients are Cf = T Y[:, :m] (columns 0..m-1 of Cf2) and the same with
+// the X rows zeroed (columns m..2m-1, giving the new P).  Cf2 has ld 3m.
 __global__ __launch_bounds__(256) void k_rr(const PairDev* P, const double* GA, const double* GB,
                                             int nb, int m, double* Cf2, double* lam,
                                             const int* active) {
@@ -369,39 +364,81 @@ __global__ __launch_bounds__(256) void k_rr(const PairDev* P, const double* GA, 
   double* dsc = Cb + nb * nb;     // nb
   double* rot = dsc + nb;         // 4*(nb/2+1)
   double* red = rot + 4 * (nb / 2 + 1);
-  int* keep = reinterpret_cast<int*>(red + 16);   // nb
-  int* perm = keep + nb;                          // nb
-  __shared__ int r_s;
+  int* piv = reinterpret_cast<int*>(red + 16);   // nb
+  int* perm = piv + nb;                          // nb
+  __shared__ int r_s, jp_s;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < nb; i += nt) {
     const double d = gb[i + (size_t)i * nb];
     dsc[i] = d > 1e-300 ? 1.0 / sqrt(d) : 0.0;
+    piv[i] = i;
   }
   __syncthreads();
   for (int idx = tid; idx < nb * nb; idx += nt) {
     const int i = idx % nb, j = idx / nb;
     A[idx] = 0.5 * (gb[i + (size_t)j * nb] + gb[j + (size_t)i * nb]) * dsc[i] * dsc[j];
   }
+  if (tid == 0) r_s = nb;
   __syncthreads();
-  jacobi_lds(A, B, nb, rot, red);
-  if (tid == 0) {
-    double tmax = 0.0;
-    for (int j = 0; j < nb; ++j) tmax = fmax(tmax, A[j + j * nb]);
-    int r = 0;
-    for (int j = 0; j < nb; ++j)
-      if (A[j + j * nb] > 1e-10 * tmax) keep[r++] = j;
-    r_s = r;
+  // pivoted Cholesky, lower triangle of A, symmetric row/column swaps
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      int best = j;
+      for (int i = j + 1; i < nb; ++i)
+        if (A[i + i * nb] > A[best + best * nb]) best = i;
+      jp_s = best;
+      if (!(A[best + best * nb] > 1e-12)) r_s = j;
+    }
+    __syncthreads();
+    if (r_s <= j) break;
+    const int jp = jp_s;
+    if (jp != j) {
+      for (int k = tid; k < nb; k += nt) {          // swap rows j, jp
+        const double t = A[j + k * nb];
+        A[j + k * nb] = A[jp + k * nb];
+        A[jp + k * nb] = t;
+      }
+      __syncthreads();
+      for (int k = tid; k < nb; k += nt) {          // swap columns j, jp
+        const double t = A[k + j * nb];
+        A[k + j * nb] = A[k + jp * nb];
+        A[k + jp * nb] = t;
+      }
+      if (tid == 0) { const int t = piv[j]; piv[j] = piv[jp]; piv[jp] = t; }
+      __syncthreads();
+    }
+    const double ljj = sqrt(A[j + j * nb]);
+    for (int i = j + 1 + tid; i < nb; i += nt) A[i + j * nb] /= ljj;
+    __syncthreads();
+    if (tid == 0) A[j + j * nb] = ljj;
+    const int rem = nb - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += nt) {
+      const int i = j + 1 + idx % rem, k = j + 1 + idx / rem;
+      if (k <= i) {
+        A[i + k * nb] -= A[i + j * nb] * A[k + j * nb];
+        A[k + i * nb] = A[i + k * nb];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int r = r_s;
-  // T (nb x r) into Cb, ld nb
-  for (int idx = tid; idx < nb * r; idx += nt) {
-    const int i = idx % nb, c = idx / nb;
-    const int j = keep[c];
-    Cb[i + c * nb] = dsc[i] * B[i + j * nb] / sqrt(A[j + j * nb]);
+  // Linv = L^{-1} (r x r, lower), one column per thread, into B (ld nb)
+  for (int c = tid; c < r; c += nt) {
+    for (int i = 0; i < r; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= A[i + k * nb] * B[k + c * nb];
+      B[i + c * nb] = (i < c) ? 0.0 : v / A[i + i * nb];
+    }
   }
   __syncthreads();
-  // B <- GA T (nb x r), ld nb
+  // T (nb x r) into Cb: T[piv[c'], j] = dsc[piv[c']] * Linv[j, c']
+  for (int idx = tid; idx < nb * r; idx += nt) {
+    const int cp = idx % nb, j = idx / nb;
+    const int row = piv[cp];
+    Cb[row + j * nb] = (cp < r) ? dsc[row] * B[j + cp * nb] : 0.0;
+  }
+  __syncthreads();
+  // B <- GA T (nb x r)
   for (int idx = tid; idx < nb * r; idx += nt) {
     const int i = idx % nb, c = idx / nb;
     double v = 0.0;
@@ -410,21 +447,15 @@ __global__ __launch_bounds__(256) void k_rr(const PairDev* P, const double* GA, 
     B[idx] = v;
   }
   __syncthreads();
-  // A <- T^T (GA T) (r x r), ld r
+  // A <- T^T (GA T) (r x r, ld r), symmetrised
   for (int idx = tid; idx < r * r; idx += nt) {
     const int i = idx % r, c = idx / r;
-    double v = 0.0;
-    for (int l = 0; l < nb; ++l) v += Cb[l + i * nb] * B[l + c * nb];
-    A[idx] = v;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < r * r; idx += nt) {
-    const int i = idx % r, c = idx / r;
-    if (i < c) {
-      const double s = 0.5 * (A[i + c * r] + A[c + i * r]);
-      A[i + c * r] = s;
-      A[c + i * r] = s;
+    double v = 0.0, w = 0.0;
+    for (int l = 0; l < nb; ++l) {
+      v += Cb[l + i * nb] * B[l + c * nb];
+      w += Cb[l + c * nb] * B[l + i * nb];
     }
+    A[idx] = 0.5 * (v + w);
   }
   __syncthreads();
   jacobi_lds(A, B, r, rot, red);   // eigenvectors Y in B (ld r)

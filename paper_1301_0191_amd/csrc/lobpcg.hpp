@@ -28,22 +28,29 @@ struct PairDev {
 };
 
 struct PairIdx {               // flat index arrays referenced by PairDev ranges
-  DBuf<int> sh_s, sh_t, dr_s, dr_t, pc_s, pc_t, face_s;
+  DBuf<int> sh_s, sh_t, pc_s, pc_t, face_s;
+  DBuf<int> dptr, didx;        // entries of the rows of D (global row ids dr0..dr1 per pair)
+  DBuf<int64_t> dcpos;
+};
+
+struct DRows {                 // device view of the sparse rows of D
+  const int* ptr;
+  const int* idx;
+  const int64_t* cpos;
 };
 
 // Launchers (lobpcg.hip).  `m` is the block size, `col` selects a column
 // block of V (0 = X, 1 = W, 2 = P), ncol columns.
 void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStream_t st);
 void lp_project(const PairDev* P, int np, double* V, int m, int col, const double* C,
-                const int* dr_s, const int* dr_t, const double* rb, const int* active, bool deflate,
+                const DRows dr, const double* rb, const int* active, bool deflate,
                 hipStream_t st);
 void lp_to_slab(const PairDev* P, int np, const double* V, int m, int col, bool with_ie,
                 const double* diagG, const int* sh_s, const int* sh_t, double* U, const int* active,
                 hipStream_t st);
 void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, double* AV,
                      double* BV, const double* diagG, const int* sh_s, const int* sh_t,
-                     const double* C, const int* dr_s, const int* dr_t, const int* active,
-                     hipStream_t st);
+                     const double* C, const DRows dr, const int* active, hipStream_t st);
 void lp_coarse(const PairDev* P, int np, const double* Y, int m, const double* Kp,
                const int* pc_s, const int* pc_t, double* Zc, const int* active, hipStream_t st);
 void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V, const int* active,

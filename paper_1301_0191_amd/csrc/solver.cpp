@@ -448,7 +448,13 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
     Yoff[s + 1] = Yoff[s] + cols * L.nl[s];
     Zoff[s + 1] = Zoff[s] + cols * L.nc[s];
   }
-  std::vector<int> sh_s, sh_t, dr_s, dr_t, pc_s, pc_t, face_s;
+  std::vector<int> sh_s, sh_t, pc_s, pc_t, face_s, dptr{0}, didx;
+  std::vector<int64_t> dcpos;
+  std::vector<LocalIndex> gl(L.nsub);
+  for (int s = 0; s < L.nsub; ++s) {
+    std::vector<int> G(P.subs[s].dofs.begin() + L.nI[s], P.subs[s].dofs.end());
+    gl[s].build(G);
+  }
   int64_t voff = 0, kpoff = 0, rboff = 0, fcoff = 0;
   W.hp.resize(W.np);
   L.fc_off.assign(W.np, 0);
@@ -479,10 +485,21 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
     sh_s.insert(sh_s.end(), Q.sh_s.begin(), Q.sh_s.end());
     sh_t.insert(sh_t.end(), Q.sh_t.begin(), Q.sh_t.end());
     d.sh1 = int(sh_s.size());
-    d.dr0 = int(dr_s.size());
-    dr_s.insert(dr_s.end(), Q.dr_s.begin(), Q.dr_s.end());
-    dr_t.insert(dr_t.end(), Q.dr_t.begin(), Q.dr_t.end());
-    d.dr1 = int(dr_s.size());
+    // rows of D: one per shared initial coarse DOF, supported on its glob's DOFs
+    d.dr0 = int(dptr.size()) - 1;
+    for (size_t r = 0; r < Q.dr_s.size(); ++r) {
+      const Constraint& K = P.cons[P.subs[Q.s].cons[Q.dr_s[r]]];
+      for (int j : K.dofs) {
+        const int is = gl[Q.s].find(j), it = gl[Q.t].find(j);
+        if (is < 0 || it < 0) throw Error(AMBDDC_E_INVALID_ARG, "shared constraint outside a pair");
+        didx.push_back(is);
+        dcpos.push_back(L.c_off[Q.s] + Q.dr_s[r] + int64_t(is) * L.nc[Q.s]);
+        didx.push_back(d.nGs + it);
+        dcpos.push_back(L.c_off[Q.t] + Q.dr_t[r] + int64_t(it) * L.nc[Q.t]);
+      }
+      dptr.push_back(int(didx.size()));
+    }
+    d.dr1 = int(dptr.size()) - 1;
     d.cs_off = L.c_off[Q.s];
     d.ct_off = L.c_off[Q.t];
     d.pcs0 = int(pc_s.size());
@@ -511,8 +528,9 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
   W.dp.upload(W.hp, st);
   W.idx.sh_s.upload(sh_s, st);
   W.idx.sh_t.upload(sh_t, st);
-  W.idx.dr_s.upload(dr_s, st);
-  W.idx.dr_t.upload(dr_t, st);
+  W.idx.dptr.upload(dptr, st);
+  W.idx.didx.upload(didx, st);
+  W.idx.dcpos.upload(dcpos, st);
   W.idx.pc_s.upload(pc_s, st);
   W.idx.pc_t.upload(pc_t, st);
   W.idx.face_s.upload(face_s, st);
@@ -613,7 +631,8 @@ void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
              W.active.p, st);
   W.gS.run(1.0, 0.0, st);
   lp_from_slab_ab(W.dp.p, W.np, W.Y.p, W.m, col, W.AV.p, W.BV.p, L.diagG.p, W.idx.sh_s.p,
-                  W.idx.sh_t.p, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.active.p, st);
+                  W.idx.sh_t.p, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.active.p,
+                  st);
 }
 
 // Rayleigh-Ritz on span(V) and the new X, P (the products AV, BV are always
@@ -626,10 +645,10 @@ void rayleigh_ritz(Level& L, PairWork& W, int v, bool with_p, hipStream_t st) {
   lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
   W.upd_v[v].run(1.0, 0.0, st);
   lp_commit(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.T.p, W.m, with_p, true, W.active.p, st);
-  lp_project(W.dp.p, W.np, W.V.p, W.m, 0, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p, W.active.p,
+  lp_project(W.dp.p, W.np, W.V.p, W.m, 0, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, W.active.p,
              true, st);
   if (with_p)
-    lp_project(W.dp.p, W.np, W.V.p, W.m, 2, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p,
+    lp_project(W.dp.p, W.np, W.V.p, W.m, 2, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p,
                W.active.p, true, st);
 }
 
@@ -675,7 +694,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   W.active.upload(ones, st);
   // start block, projected; first Rayleigh-Ritz on X alone
   lp_random(W.dp.p, W.np, W.V.p, m, c.opt.seed + uint64_t(li) * 7919u, st);
-  lp_project(W.dp.p, W.np, W.V.p, m, 0, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p, nullptr, true, st);
+  lp_project(W.dp.p, W.np, W.V.p, m, 0, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, nullptr, true, st);
   apply_ab(L, W, 0, st);
   rayleigh_ritz(L, W, 0, false, st);
   int it = 0;
@@ -696,7 +715,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
     lp_coarse(W.dp.p, W.np, W.Y.p, m, W.Kp.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Zc.p, W.active.p, st);
     W.gM2.run(1.0, 1.0, st);
     lp_from_slab_w(W.dp.p, W.np, W.Y.p, m, W.V.p, W.active.p, st);
-    lp_project(W.dp.p, W.np, W.V.p, m, 1, L.C.p, W.idx.dr_s.p, W.idx.dr_t.p, W.rb.p, W.active.p,
+    lp_project(W.dp.p, W.np, W.V.p, m, 1, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, W.active.p,
                true, st);
     W.orth_c.run(1.0, 0.0, st);
     W.orth_u.run(-1.0, 1.0, st);

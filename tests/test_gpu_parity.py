@@ -210,3 +210,28 @@ def test_error_paths():
     with pytest.raises(AmbddcError, match="E_NO_CONVERGENCE"):
         h.solve(rhs, rtol=1e-14, maxit=1)
     h.close()
+
+
+def test_repeated_setup_and_solve_on_one_handle():
+    """Regression: set-up after a solve on the same handle must reproduce the
+    first set-up exactly (per-pair flag buffers were once re-allocated under
+    live GEMM descriptors)."""
+    log("CASE repeated setup")
+    torch = torch_cuda()
+    prob = W.CONFIGS["c1"](0)
+    h = gpu_handle(prob)
+    coeff = torch.from_numpy(prob.coeff).to("cuda:0")
+    ref = None
+    for rep in range(3):
+        if rep:
+            h.setup(coeff)
+        st = h.stats()
+        X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-10)
+        lam = np.concatenate([h.pair_result(0, p)["lam"] for p in range(st["n_pairs"][0])])
+        cur = (st["lobpcg_iters"], st["n_adaptive"], its, lam)
+        if ref is None:
+            ref = cur
+        else:
+            assert cur[0] == ref[0] and cur[1] == ref[1] and cur[2] == ref[2]
+            np.testing.assert_array_equal(cur[3], ref[3])
+    h.close()
