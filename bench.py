@@ -24,6 +24,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "setup+solve time to rel. residual 1e-10 & pair eigenproblems/s, FP32+batched vs FP64"
 
+# MI355X peaks (published): FP64 vector and FP64 MFMA 78.6 TFLOP/s, HBM3E 8 TB/s.
+PEAK_F64 = 78.6e12
+PEAK_HBM = 8.0e12
+# Kernel classes timed with HIP events inside the library during the timed
+# steps.  The roofline is reported for the single-kernel class with the most
+# time; the others are listed for context.
+TIMED = ["pair_rr", "pair_apply", "pair_gram", "schur", "bddc_apply"]
+SINGLE_KERNEL = {
+    # class: (kernel, bound, peak, unit)
+    "pair_rr": ("k_rr (batched pair Rayleigh-Ritz)", "alu", PEAK_F64, "TFLOP/s"),
+    "pair_apply": ("k_gemm, grouped S^s products of the pair LOBPCG", "mfma", PEAK_F64, "TFLOP/s"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -34,22 +48,74 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=16,
-                    help="pair eigenproblems the oracle solves for the CPU baseline sample")
+    ap.add_argument("--cpu-pairs", type=int, default=0,
+                    help="pair eigenproblems the oracle solves for a sampled CPU baseline "
+                         "(0 = run the whole method in the oracle)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the steps, copy a device buffer of this size once (a plain "
+                         "copy kernel of known traffic, for calibrating HBM counters)")
     return ap.parse_args()
 
 
+def traffic_for(kernel_key):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE +
+    WRITE_SIZE, calibrated by a plain copy), if the kernel sources are
+    unchanged since the measurement; else None."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for rel in rec["sources"]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"]
+        return max(n) if n else 1
+    except Exception:
+        return 1
+
+
 def cpu_baseline(prob, npairs_sample, rtol):
-    """The FP64 oracle on the host cores: full level set-up and PCG, with the
-    dense pair eigenproblems solved for a sample of the pairs and their cost
-    scaled to all pairs."""
+    """The FP64 oracle on the host cores, on the same workload.
+
+    npairs_sample <= 0: the whole method (hierarchy set-up with every dense
+    pair eigenproblem, then PCG to rtol), timed as it runs.  Otherwise only
+    that many pair eigenproblems are solved and their time is scaled to all
+    pairs; the PCG then runs with the partially enriched preconditioner, so
+    that leg is an upper bound."""
     import numpy as np
     import oracle as O
+    cores = blas_threads()
+    if npairs_sample <= 0:
+        t0 = time.perf_counter()
+        H = O.setup_hierarchy(prob)
+        t1 = time.perf_counter()
+        X, its, cond, _ = O.solve_problem(prob, rtol=rtol, H=H)
+        t2 = time.perf_counter()
+        n_pairs = sum(len(L.pairs) for L in H.levels)
+        return dict(value=t2 - t0, unit="s", cores=cores, kind="oracle",
+                    setup_s=t1 - t0, solve_s=t2 - t1,
+                    sample=(f"{prob.name}: the whole method in the FP64 oracle (dense Schur "
+                            f"complements, {n_pairs} dense pair eigensolves, enriched BDDC, "
+                            f"PCG to {rtol:g} in {int(its[0])} its), {cores} BLAS threads; "
+                            f"nothing scaled"))
     from oracle.substructure import build_level, coarse_basis, level1_input
     from oracle.adaptive import enrich_level
     from oracle.bddc import _prepare_full_space, Hierarchy, bddc_apply, pcg
     from oracle import fem
-    cores = len(os.sched_getaffinity(0))
+    import scipy.linalg as sla
     t0 = time.perf_counter()
     inp = level1_input(prob)
     L = build_level(inp)
@@ -61,7 +127,6 @@ def cpu_baseline(prob, npairs_sample, rtol):
     t2 = time.perf_counter()
     coarse_basis(L)
     _prepare_full_space(L)
-    import scipy.linalg as sla
     H = Hierarchy(levels=[L])
     nC = L.n_coarse
     Kt = np.zeros((nC, nC))
@@ -71,16 +136,14 @@ def cpu_baseline(prob, npairs_sample, rtol):
     t3 = time.perf_counter()
     x, its, *_ = pcg(L.Kglob, prob.rhs[:, 0], lambda v: bddc_apply(H, v), rtol, 1000)
     t4 = time.perf_counter()
-    t_pairs = t2 - t1
-    per_pair = t_pairs / max(1, len(sample))
+    per_pair = (t2 - t1) / max(1, len(sample))
     total_est = (t1 - t0) + per_pair * n_pairs + (t3 - t2) + (t4 - t3)
     return dict(value=total_est, unit="s", cores=cores, kind="oracle",
-                pair_eigenproblems_per_s=len(sample) / t_pairs,
                 measured_s=t4 - t0,
                 sample=(f"{prob.name}: oracle level set-up, dense pair eigensolves for "
                         f"{len(sample)} of {n_pairs} pairs (time scaled to all pairs), "
-                        f"enriched BDDC with the sampled constraints, PCG to {rtol:g} "
-                        f"({its} its); BLAS threads = numpy default"))
+                        f"enriched BDDC with the sampled constraints only, PCG to {rtol:g} "
+                        f"({its} its, an upper bound); {cores} BLAS threads"))
 
 
 def main():
@@ -108,18 +171,54 @@ def main():
         h.setup(coeff, nu)
         return h.solve(rhs, rtol=args.rtol, maxit=2000, x=x)
 
-    for _ in range(args.warmup):
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr)
+        del src, dst
+    for i in range(args.warmup):
         step()
+        print(f"warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    h.timing_enable(TIMED)
     setup_s, solve_s = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         res = step()
         st = h.stats()
         setup_s.append(st["t_phase"][6])
         solve_s.append(st["t_phase"][7])
+        print(f"step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    timed = {c: h.timing_read(c) for c in TIMED}
+    h.timing_enable(None)
+    kernels = {}
+    for c, t in timed.items():
+        if t["launches"] == 0 or t["ms"] <= 0:
+            continue
+        sec = t["ms"] * 1e-3
+        kernels[c] = {"launches": t["launches"], "avg_launch_us": 1e3 * t["ms"] / t["launches"],
+                      "share_of_step": sec / T,
+                      "alg_flops_per_launch": t["flops"] / t["launches"],
+                      "alg_bytes_per_launch": t["bytes"] / t["launches"],
+                      "tflops": t["flops"] / sec / 1e12, "gbps": t["bytes"] / sec / 1e9}
+    dom = max((c for c in SINGLE_KERNEL if c in kernels), key=lambda c: timed[c]["ms"],
+              default=None)
+    roofline = None
+    if dom is not None:
+        name, bound, peak, unit = SINGLE_KERNEL[dom]
+        t = timed[dom]
+        achieved = t["flops"] / (t["ms"] * 1e-3)
+        roofline = {"kernel": name, "class": dom, "bound": bound,
+                    "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
+                    "frac": achieved / peak, "traffic": traffic_for(dom),
+                    "launches": t["launches"], "avg_launch_us": 1e3 * t["ms"] / t["launches"],
+                    "alg_flops_per_launch": t["flops"] / t["launches"],
+                    "alg_bytes_per_launch": t["bytes"] / t["launches"]}
     st = h.stats()
     ms = 1e3 * T / args.steps
     n_pairs = sum(st["n_pairs"])
@@ -152,6 +251,8 @@ def main():
         "phase_s": {"schur": st["t_phase"][0], "bddc_init": st["t_phase"][1],
                     "lobpcg_select": st["t_phase"][2], "enriched_bddc": st["t_phase"][4],
                     "coarse": st["t_phase"][5]},
+        "roofline": roofline,
+        "kernels": kernels,
     }
     h.close()
     if not args.no_cpu_baseline:

@@ -199,6 +199,40 @@ ambddc_status ambddc_get_coarse_element(ambddc_handle h, int32_t level, int32_t 
  * substructured level), host, column-major. */
 ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc_host, int32_t* n);
 
+/* ---- kernel timing (measurement) ----
+ * ambddc_timing_enable selects classes of kernel launches (comma-separated
+ * names; NULL or "" switches timing off) and clears their counters.  Each
+ * launch of a selected class is then bracketed by two HIP events recorded on
+ * the handle's stream, and the library adds to the class the algorithmic
+ * work of that launch (the count the roofline is taken against):
+ *   "pair_rr"      batched Rayleigh-Ritz of the pair LOBPCG (one workgroup
+ *                  per active pair, order nb = 3m): flops 9 nb^3 + 4/3 nb^3
+ *                  + 2 nb^2 m per pair (reduction to a standard problem and a
+ *                  symmetric eigendecomposition with vectors, LAPACK-style
+ *                  counts), bytes 8 (2 nb^2 + 2 nb m) per pair;
+ *   "pair_apply"   grouped S^s products of the pair LOBPCG: per subdomain
+ *                  2 nG^2 c flops and 8 (nG^2 + 2 nG c) bytes, c = columns of
+ *                  all its pair slots;
+ *   "pair_gram"    Gram matrices V^T (A V), V^T (B V): 2 n nb^2 flops and
+ *                  8 (2 n nb + nb^2) bytes per active pair and matrix;
+ *   "schur"        batched partial LDL^T of the augmented subdomain matrices
+ *                  (interior factorisation and Schur complement): per
+ *                  subdomain nI^3/3 + nI^2 nG + nI nG^2 flops and
+ *                  8 (nI + nG)^2 bytes;
+ *   "bddc_apply"   one application of the multilevel preconditioner
+ *                  (Alg. 1, all levels): the dense operators it reads, per
+ *                  subdomain nI^2 + 2 nI nG + nG^2 + 2 nG nc entries, plus
+ *                  the n_top^2 coarsest inverse; bytes 8 x entries + 8 x 6
+ *                  vector entries per DOF and right-hand side, flops
+ *                  2 x entries x nrhs.
+ * ambddc_timing_read returns, for one class, the launches, the summed event
+ * time in milliseconds and the summed algorithmic flops and bytes since the
+ * last enable (any pointer may be NULL; it waits for the recorded events).
+ * Errors: E_INVALID_ARG for an unknown class name. */
+ambddc_status ambddc_timing_enable(ambddc_handle h, const char* classes);
+ambddc_status ambddc_timing_read(ambddc_handle h, const char* cls, int32_t* launches,
+                                 double* total_ms, double* flops, double* bytes);
+
 const char* ambddc_last_error(void);
 void ambddc_destroy(ambddc_handle h);
 

@@ -79,4 +79,90 @@ struct DBuf {
 
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
+// Timing of selected classes of kernel launches with HIP events recorded on
+// the launch stream, with the algorithmic flops and bytes the caller
+// attributes to each timed launch.
+struct KTimer {
+  struct Acc {
+    int launches = 0;
+    double flops = 0.0, bytes = 0.0, ms = 0.0;
+  };
+  struct Pending {
+    int cls;
+    hipEvent_t e0, e1;
+  };
+  std::vector<std::string> names;
+  std::vector<Acc> acc;
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pend;
+  int cur = -1;
+  hipEvent_t cur_e = nullptr;
+
+  int find(const char* cls) const {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == cls) return int(i);
+    return -1;
+  }
+  void enable(const std::string& list) {
+    collect();
+    names.clear();
+    size_t a = 0;
+    while (a < list.size()) {
+      size_t b = list.find(',', a);
+      if (b == std::string::npos) b = list.size();
+      if (b > a) names.push_back(list.substr(a, b - a));
+      a = b + 1;
+    }
+    acc.assign(names.size(), Acc());
+  }
+  bool any() const { return !names.empty(); }
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    AMB_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void begin(const char* cls, hipStream_t st) {
+    if (names.empty()) return;
+    const int i = find(cls);
+    if (i < 0) return;
+    cur = i;
+    cur_e = get();
+    AMB_HIP(hipEventRecord(cur_e, st));
+  }
+  void end(const char* cls, hipStream_t st, double f, double b) {
+    if (cur < 0 || names[cur] != cls) return;
+    hipEvent_t e = get();
+    AMB_HIP(hipEventRecord(e, st));
+    pend.push_back({cur, cur_e, e});
+    acc[cur].launches += 1;
+    acc[cur].flops += f;
+    acc[cur].bytes += b;
+    cur = -1;
+    cur_e = nullptr;
+  }
+  void collect() {
+    for (auto& q : pend) {
+      AMB_HIP(hipEventSynchronize(q.e1));
+      float t = 0.f;
+      AMB_HIP(hipEventElapsedTime(&t, q.e0, q.e1));
+      if (q.cls < int(acc.size())) acc[q.cls].ms += t;
+      pool.push_back(q.e0);
+      pool.push_back(q.e1);
+    }
+    pend.clear();
+  }
+  ~KTimer() {
+    for (auto& q : pend) {
+      (void)hipEventDestroy(q.e0);
+      (void)hipEventDestroy(q.e1);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace ambddc

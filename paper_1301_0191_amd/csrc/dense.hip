@@ -3,7 +3,6 @@
 #include <cmath>
 
 #include "dense.hpp"
-#include "jacobi_dev.hpp"
 #include "mfma_tile.hpp"
 
 namespace ambddc {
@@ -340,41 +339,6 @@ void SymOp::finalize(hipStream_t st) {
 void SymOp::run(hipStream_t st) const {
   if (h.empty() || tiles == 0) return;
   k_sym<<<tiles, 256, 0, st>>>(d.p, int(h.size()));
-  AMB_LAUNCH_CHECK();
-}
-
-// --------------------------------------------------------------------------
-// batched Jacobi eigensolver (n <= 64 in LDS)
-// --------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_jacobi(double* const* A, const int* n, double* const* W,
-                                                double* const* V) {
-  extern __shared__ double smem[];
-  const int b = blockIdx.x;
-  const int nb = n[b];
-  if (nb <= 0) return;
-  double* a = smem;
-  double* v = a + nb * nb;
-  double* rot = v + nb * nb;
-  double* red = rot + 4 * ((nb + 2) / 2);
-  int* perm = reinterpret_cast<int*>(red + 16);
-  for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) a[i] = A[b][i];
-  __syncthreads();
-  jacobi_lds(a, v, nb, rot, red);
-  sort_desc_lds(a, nb, perm);
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) W[b][i] = a[perm[i] + perm[i] * nb];
-  for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) {
-    const int r = i % nb, c = i / nb;
-    V[b][r + c * nb] = v[r + perm[c] * nb];
-  }
-}
-
-void jacobi_eig_batched(double* const* A, const int* n, double* const* W, double* const* V,
-                        int batch, int nmax, hipStream_t st) {
-  if (batch == 0) return;
-  const size_t sm = sizeof(double) * (2 * nmax * nmax + 4 * ((nmax + 2) / 2) + 16) +
-                    sizeof(int) * (nmax + 1);
-  k_jacobi<<<batch, 256, sm, st>>>(A, n, W, V);
   AMB_LAUNCH_CHECK();
 }
 

@@ -95,10 +95,4 @@ class SymOp {
   void run(hipStream_t st) const;
 };
 
-// Batched symmetric eigensolver for small matrices (cyclic Jacobi in LDS).
-// A_b (n_b x n_b, ld = ldA) is overwritten; eigenvalues (descending) in
-// W_b, eigenvectors in V_b (ld = n_b).
-void jacobi_eig_batched(double* const* A, const int* n, double* const* W, double* const* V,
-                        int batch, int nmax, hipStream_t st);
-
 }  // namespace ambddc

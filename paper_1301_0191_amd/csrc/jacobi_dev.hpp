@@ -1,107 +1,177 @@
 // Cyclic two-sided Jacobi eigensolver for one small symmetric matrix held
-// in LDS, run by a whole workgroup.  Parallel round-robin ordering: in every
-// round the n indices form n/2 disjoint pairs (p, q); their rotations commute,
-// so A <- J^T A J is applied as independent 2x2-block updates
-// [A_pp' A_pq'; A_qp' A_qq'] <- R_k1^T [..] R_k2 for every pair of pairs
-// (k1, k2), with one barrier per round.
+// in LDS, run by a workgroup of 256 threads.
+//
+// Parallel round-robin ordering: in every round the n indices form n/2
+// disjoint pairs (p, q) whose rotations commute.  Thread t works for pair
+// k = t / 8 and block b = t % 8 of rows (columns) b, b + 8, ..., so the
+// eight threads of a pair are neighbouring lanes of one wave.  A round is:
+// each thread computes its pair's rotation from A_pp, A_qq, A_pq; the column
+// rotations of A and of the eigenvector matrix V on its rows (a wave reads
+// those three entries before it writes the columns, and no other wave
+// touches them); a barrier; the row rotations of A on its columns, which set
+// the annihilated entries to zero; a barrier.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace ambddc {
 
-// A: n x n (ld = n) symmetric, overwritten (diagonal -> eigenvalues).
-// V: n x n (ld = n) receives the eigenvectors (columns).
-// rot: scratch of 4 * (n/2 + 1) doubles; red: 16 doubles.  n <= 128.
-__device__ inline void jacobi_lds(double* A, double* V, int n, double* rot, double* red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < n * n; i += nt) V[i] = (i % (n + 1) == 0) ? 1.0 : 0.0;
+constexpr int JAC_MAXN = 64;
+constexpr int JAC_WORK = 8;   // doubles
+
+// pair k of round rr (np even player count, mm = np - 1 rounds per sweep);
+// q = -1 when the partner is the dummy player of an odd n
+__device__ inline void jac_pair(int k, int rr, int np, int mm, int n, int& p, int& q) {
+  if (k == 0) {
+    p = rr;
+    q = np - 1;
+  } else {
+    p = rr + k;
+    if (p >= mm) p -= mm;
+    q = rr - k;
+    if (q < 0) q += mm;
+  }
+  if (p > q) { const int t = p; p = q; q = t; }
+  if (q >= n) q = -1;
+}
+
+// A: n x n (ld lda) symmetric, overwritten (diagonal -> eigenvalues).
+// V: n x n (ld ldv) receives the eigenvectors (columns).  Odd lda and ldv
+// keep the LDS accesses free of bank conflicts.  work: JAC_WORK doubles.
+// n <= JAC_MAXN, blockDim = 256.
+__device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n, double* work) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = tid >> 3, blk = tid & 7;
+  double* red = work;   // [2 * 4]: (off, diag) partial sums per wave
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int i = idx % n, j = idx / n;
+    V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
+  }
   __syncthreads();
   if (n <= 1) return;
-  const int np = (n + 1) & ~1;   // even player count (a dummy when n is odd)
-  const int half = np / 2;
-  const int m = np - 1;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  const int np = (n + 1) & ~1, half = np / 2, mm = np - 1;
+  for (int g = 0;; ++g) {
+    const int rr = g % mm, sweep = g / mm;
+    if (sweep >= 40) break;
+    const bool acc = (rr == 0);
+    int p = -1, q = -1;
+    if (k < half) jac_pair(k, rr, np, mm, n, p, q);
+    double c = 1.0, s = 0.0;
     double off = 0.0, dia = 0.0;
-    for (int i = tid; i < n * n; i += nt) {
-      const int r = i % n, c = i / n;
-      const double v = A[i] * A[i];
-      if (r == c) dia += v; else off += v;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o);
-      dia += __shfl_xor(dia, o);
-    }
-    if ((tid & 63) == 0) { red[2 * (tid >> 6)] = off; red[2 * (tid >> 6) + 1] = dia; }
-    __syncthreads();
-    off = 0.0; dia = 0.0;
-    for (int w = 0; w < (nt + 63) / 64; ++w) { off += red[2 * w]; dia += red[2 * w + 1]; }
-    __syncthreads();
-    if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int r = 0; r < m; ++r) {
-      if (tid < half) {
-        int p, q;
-        if (tid == 0) { p = r; q = np - 1; }
-        else { p = (r + tid) % m; q = (r - tid + m) % m; }
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p + q * n];
-          if (apq != 0.0) {
-            const double app = A[p + p * n], aqq = A[q + q * n];
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+    if (q >= 0) {
+      const double apq = A[p + q * lda];
+      if (apq != 0.0) {
+        const double tau = (A[q + q * lda] - A[p + p * lda]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + t * t);
+        s = t * c;
+      }
+      // column pass: new col p = c col_p - s col_q, new col q = s col_p + c col_q
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = blk + 8 * u;
+        if (i < n) {
+          a[u] = A[i + p * lda];
+          b[u] = A[i + q * lda];
+        }
+      }
+      if (acc) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = blk + 8 * u;
+          if (i < n) {
+            const double a2 = a[u] * a[u], b2 = b[u] * b[u];
+            dia += (i == p ? a2 : 0.0) + (i == q ? b2 : 0.0);
+            off += (i == p ? 0.0 : a2) + (i == q ? 0.0 : b2);
           }
         }
-        rot[4 * tid] = c;
-        rot[4 * tid + 1] = s;
-        rot[4 * tid + 2] = p;
-        rot[4 * tid + 3] = (q < n) ? q : -1;
       }
-      __syncthreads();
-      for (int i = tid; i < half * half; i += nt) {
-        const int k1 = i % half, k2 = i / half;
-        const double c1 = rot[4 * k1], s1 = rot[4 * k1 + 1];
-        const double c2 = rot[4 * k2], s2 = rot[4 * k2 + 1];
-        const int p1 = int(rot[4 * k1 + 2]), q1 = int(rot[4 * k1 + 3]);
-        const int p2 = int(rot[4 * k2 + 2]), q2 = int(rot[4 * k2 + 3]);
-        const double a = A[p1 + p2 * n];
-        const double b = q2 >= 0 ? A[p1 + q2 * n] : 0.0;
-        const double cc = q1 >= 0 ? A[q1 + p2 * n] : 0.0;
-        const double d = (q1 >= 0 && q2 >= 0) ? A[q1 + q2 * n] : 0.0;
-        // rows: p' = c1 p - s1 q, q' = s1 p + c1 q; columns the same with (c2, s2)
-        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;
-        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
-        A[p1 + p2 * n] = c2 * ra - s2 * rb;
-        if (q2 >= 0) A[p1 + q2 * n] = s2 * ra + c2 * rb;
-        if (q1 >= 0) A[q1 + p2 * n] = c2 * rc - s2 * rd;
-        if (q1 >= 0 && q2 >= 0) A[q1 + q2 * n] = s2 * rc + c2 * rd;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = blk + 8 * u;
+        if (i < n) {
+          A[i + p * lda] = c * a[u] - s * b[u];
+          A[i + q * lda] = s * a[u] + c * b[u];
+        }
       }
-      for (int i = tid; i < half * n; i += nt) {
-        const int k = i / n, row = i % n;
-        const int q = int(rot[4 * k + 3]);
-        if (q < 0) continue;
-        const int p = int(rot[4 * k + 2]);
-        const double c = rot[4 * k], s = rot[4 * k + 1];
-        const double vp = V[row + p * n], vq = V[row + q * n];
-        V[row + p * n] = c * vp - s * vq;
-        V[row + q * n] = s * vp + c * vq;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = blk + 8 * u;
+        if (i < n) {
+          a[u] = V[i + p * ldv];
+          b[u] = V[i + q * ldv];
+        }
       }
-      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = blk + 8 * u;
+        if (i < n) {
+          V[i + p * ldv] = c * a[u] - s * b[u];
+          V[i + q * ldv] = s * a[u] + c * b[u];
+        }
+      }
+    } else if (acc && p >= 0) {
+      // paired with the dummy: column p is only read, for the norms
+      for (int u = 0; u < 8; ++u) {
+        const int i = blk + 8 * u;
+        if (i < n) {
+          const double a2 = A[i + p * lda] * A[i + p * lda];
+          dia += (i == p) ? a2 : 0.0;
+          off += (i == p) ? 0.0 : a2;
+        }
+      }
     }
+    if (acc) {
+      for (int o = 32; o > 0; o >>= 1) {
+        off += __shfl_xor(off, o);
+        dia += __shfl_xor(dia, o);
+      }
+      if (lane == 0) {
+        red[2 * wave] = off;
+        red[2 * wave + 1] = dia;
+      }
+    }
+    __syncthreads();
+    // row pass, with the annihilated entries set to zero
+    if (q >= 0) {
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = blk + 8 * u;
+        if (j < n) {
+          a[u] = A[p + j * lda];
+          b[u] = A[q + j * lda];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = blk + 8 * u;
+        if (j < n) {
+          A[p + j * lda] = (j == q) ? 0.0 : c * a[u] - s * b[u];
+          A[q + j * lda] = (j == p) ? 0.0 : s * a[u] + c * b[u];
+        }
+      }
+    }
+    bool stop = false;
+    if (acc) {
+      double to = 0.0, td = 0.0;
+      for (int w = 0; w < 4; ++w) { to += red[2 * w]; td += red[2 * w + 1]; }
+      stop = (to <= 1e-30 * td || to == 0.0);
+    }
+    __syncthreads();
+    if (stop) break;
   }
 }
 
-// Descending order of the diagonal of A (n <= 128): perm[r] = index of the
-// r-th largest eigenvalue.  Ties are broken by index.
-__device__ inline void sort_desc_lds(const double* A, int n, int* perm) {
+// Descending order of the diagonal of A (ld lda, n <= JAC_MAXN): perm[r] =
+// index of the r-th largest eigenvalue.  Ties are broken by index.
+__device__ inline void sort_desc_lds(const double* A, int lda, int n, int* perm) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < n; i += nt) {
-    const double v = A[i + i * n];
+    const double v = A[i + i * lda];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double w = A[j + j * n];
+      const double w = A[j + j * lda];
       rank += (w > v) || (w == v && j < i);
     }
     perm[rank] = i;

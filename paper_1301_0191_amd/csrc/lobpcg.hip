@@ -342,147 +342,236 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
   AMB_LAUNCH_CHECK();
 }
 
-// Rayleigh-Ritz on span(V).  The basis is made B-orthonormal with a
-// diagonally pivoted Cholesky factorisation of the scaled Gram matrix:
-// D = diag(GB)^{-1/2}, P^T (D GB D) P = L L^T, stopping at the first pivot
-// below 1e-12 (numerically dependent directions are dropped); then
-// T = D P[:, :r] L^{-T} gives V T with (V T)^T B (V T) = I.  The projected
-// matrix T^T GA T is diagonalised by Jacobi, eigenvalues descending, and the
-// coefficients are Cf = T Y[:, :m] (columns 0..m-1 of Cf2) and the same with
-// the X rows zeroed (columns m..2m-1, giving the new P).  Cf2 has ld 3m.
-__global__ __launch_bounds__(256) void k_rr(const PairDev* P, const double* GA, const double* GB,
-                                            int nb, int m, double* Cf2, double* lam,
-                                            const int* active) {
+// Rayleigh-Ritz on span(V).  With D = diag(GB)^{-1/2}, the scaled Gram
+// matrix B = D GB D is reduced by a diagonally pivoted elimination: step j
+// picks the remaining index p with the largest diagonal entry of the current
+// B (stopping below 1e-12: numerically dependent directions are dropped) and
+// eliminates column p from the remaining rows, B <- B - b_p b_p^T / b_pp,
+// while the same row operations are accumulated in F (F <- E F, starting
+// from I).  With the pivot rows of F scaled by b_pp^{-1/2} and by D,
+// Fc (r x nb) satisfies Fc GB Fc^T = I, and A_r = Fc GA Fc^T (two small
+// products) is diagonalised by Jacobi.  The Ritz coefficients are Fc^T Y,
+// eigenvalues descending; Cf2 (ld 3m) holds the first m of them (columns
+// 0..m-1) and the same with the X rows zeroed (columns m..2m-1, giving the
+// new P).
+//
+// Elimination: lanes are rows, each wave owns a fixed set of columns, one
+// barrier per step.  A row of F that is not yet a pivot is nonzero only in
+// the columns of earlier pivots and its own, so only those are updated;
+// pivot rows are never touched again (their scaling is applied at the end).
+// The next pivot is found with a 64-bit LDS max over keys (diagonal value
+// with its low 6 bits replaced by 63 - index), in a ring of three slots.
+constexpr int RR_COLS = 12;   // columns per wave (nb <= 48, 4 waves)
+
+__device__ inline unsigned long long rr_key(double v, int i) {
+  if (!(v > 0.0)) return 0ull;
+  return ((unsigned long long)__double_as_longlong(v) & ~63ull) | (unsigned long long)(63 - i);
+}
+
+__global__ __launch_bounds__(256) void k_rr(const double* GA, const double* GB, int nb, int m,
+                                            double* Cf2, double* lam, const int* active) {
   extern __shared__ double sm[];
   if (active && !active[blockIdx.x]) return;
   const int M3 = 3 * m;
+  const int ld = nb | 1;          // odd: row walks are free of bank conflicts
   const double* ga = GA + (size_t)blockIdx.x * M3 * M3;
   const double* gb = GB + (size_t)blockIdx.x * M3 * M3;
-  double* A = sm;                 // nb*nb
-  double* B = A + nb * nb;        // nb*nb
-  double* Cb = B + nb * nb;       // nb*nb
-  double* dsc = Cb + nb * nb;     // nb
-  double* rot = dsc + nb;         // 4*(nb/2+1)
-  double* red = rot + 4 * (nb / 2 + 1);
-  int* piv = reinterpret_cast<int*>(red + 16);   // nb
+  double* A = sm;                 // sym(GA), nb x nb (ld); later A_r (r x r, ld r|1)
+  double* B = A + nb * ld;        // scaled GB; later Fc (r x nb, ld)
+  double* F = B + nb * ld;        // F (nb x nb, ld); later GA Fc^T, then Y
+  double* dsc = F + nb * ld;      // nb
+  double* rs = dsc + nb;          // nb
+  double* work = rs + nb;         // JAC_WORK
+  unsigned long long* key = reinterpret_cast<unsigned long long*>(work + JAC_WORK);   // 3
+  int* piv = reinterpret_cast<int*>(key + 3);   // nb
   int* perm = piv + nb;                          // nb
-  __shared__ int r_s, jp_s;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nw = nt >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < nb; i += nt) {
     const double d = gb[i + (size_t)i * nb];
     dsc[i] = d > 1e-300 ? 1.0 / sqrt(d) : 0.0;
-    piv[i] = i;
   }
-  __syncthreads();
+  if (tid < 3) key[tid] = 0ull;
   for (int idx = tid; idx < nb * nb; idx += nt) {
-    const int i = idx % nb, j = idx / nb;
-    A[idx] = 0.5 * (gb[i + (size_t)j * nb] + gb[j + (size_t)i * nb]) * dsc[i] * dsc[j];
+    const int i = idx % nb, k = idx / nb;
+    A[i + k * ld] = ga[idx];
+    B[i + k * ld] = gb[idx];
+    F[i + k * ld] = (i == k) ? 1.0 : 0.0;
   }
-  if (tid == 0) r_s = nb;
   __syncthreads();
-  // pivoted Cholesky, lower triangle of A, symmetric row/column swaps
+  // symmetrise (A) and scale (B): columns owned by waves, lanes = rows; read
+  // into registers, then written after a barrier
+  double sa[12], sb[12];
+  {
+    int u = 0;
+    for (int k = wave; k < nb; k += nw, ++u) {
+      const int i = lane;
+      if (i < nb) {
+        sa[u] = 0.5 * (A[i + k * ld] + A[k + i * ld]);
+        sb[u] = 0.5 * (B[i + k * ld] + B[k + i * ld]) * dsc[i] * dsc[k];
+      }
+    }
+  }
+  __syncthreads();
+  {
+    int u = 0;
+    for (int k = wave; k < nb; k += nw, ++u) {
+      const int i = lane;
+      if (i < nb) {
+        A[i + k * ld] = sa[u];
+        B[i + k * ld] = sb[u];
+        if (i == k) atomicMax(&key[0], rr_key(sb[u], i));
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t done = 0;
+  int r = 0;
   for (int j = 0; j < nb; ++j) {
-    if (tid == 0) {
-      int best = j;
-      for (int i = j + 1; i < nb; ++i)
-        if (A[i + i * nb] > A[best + best * nb]) best = i;
-      jp_s = best;
-      if (!(A[best + best * nb] > 1e-12)) r_s = j;
-    }
-    __syncthreads();
-    if (r_s <= j) break;
-    const int jp = jp_s;
-    if (jp != j) {
-      for (int k = tid; k < nb; k += nt) {          // swap rows j, jp
-        const double t = A[j + k * nb];
-        A[j + k * nb] = A[jp + k * nb];
-        A[jp + k * nb] = t;
-      }
-      __syncthreads();
-      for (int k = tid; k < nb; k += nt) {          // swap columns j, jp
-        const double t = A[k + j * nb];
-        A[k + j * nb] = A[k + jp * nb];
-        A[k + jp * nb] = t;
-      }
-      if (tid == 0) { const int t = piv[j]; piv[j] = piv[jp]; piv[jp] = t; }
-      __syncthreads();
-    }
-    const double ljj = sqrt(A[j + j * nb]);
-    for (int i = j + 1 + tid; i < nb; i += nt) A[i + j * nb] /= ljj;
-    __syncthreads();
-    if (tid == 0) A[j + j * nb] = ljj;
-    const int rem = nb - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += nt) {
-      const int i = j + 1 + idx % rem, k = j + 1 + idx / rem;
-      if (k <= i) {
-        A[i + k * nb] -= A[i + j * nb] * A[k + j * nb];
-        A[k + i * nb] = A[i + k * nb];
+    const unsigned long long kv = key[j % 3];   // the same for every lane
+    const unsigned long long kj =
+        ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(kv >> 32)) << 32) |
+        (unsigned)__builtin_amdgcn_readfirstlane((int)(kv & 0xffffffffu));
+    const double vj = __longlong_as_double((long long)(kj & ~63ull));
+    if (kj == 0ull || !(vj > 1e-12)) break;
+    const int p = 63 - (int)(kj & 63ull);
+    const double inv = 1.0 / B[p + p * ld];
+    unsigned long long* kn = key + (j + 1) % 3;
+    if (tid == 0) key[(j + 2) % 3] = 0ull;
+    const int i = lane;
+    const bool row = i < nb && i != p && !((done >> i) & 1ull);
+    const double gi = row ? B[i + p * ld] * inv : 0.0;
+    // this wave's columns, batched: B columns not yet eliminated get the
+    // Schur update, F columns of earlier pivots and of p the row operation
+    double x[RR_COLS], y[RR_COLS];
+#pragma unroll
+    for (int u = 0; u < RR_COLS; ++u) {
+      const int k = wave + u * nw;
+      if (k < nb) {
+        const double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
+        y[u] = M[p + k * ld];
+        if (row) x[u] = M[i + k * ld];
       }
     }
+    if (row) {
+#pragma unroll
+      for (int u = 0; u < RR_COLS; ++u) {
+        const int k = wave + u * nw;
+        if (k < nb) {
+          double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
+          M[i + k * ld] = x[u] - gi * y[u];
+        }
+      }
+      if (i % nw == wave) atomicMax(kn, rr_key(B[i + i * ld], i));
+    }
+    if (tid == 0) { piv[j] = p; rs[p] = sqrt(inv); }
+    done |= 1ull << p;
+    r = j + 1;
     __syncthreads();
   }
-  const int r = r_s;
-  // Linv = L^{-1} (r x r, lower), one column per thread, into B (ld nb)
-  for (int c = tid; c < r; c += nt) {
-    for (int i = 0; i < r; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) v -= A[i + k * nb] * B[k + c * nb];
-      B[i + c * nb] = (i < c) ? 0.0 : v / A[i + i * nb];
+  // Fc[l, k] = rs_p dsc_k F[p, k], p = piv[l] (column-major, ld)
+  double* Fc = B;
+  for (int idx = tid; idx < r * nb; idx += nt) {
+    const int l = idx % r, k = idx / r;
+    const int pl = piv[l];
+    Fc[l + k * ld] = rs[pl] * dsc[k] * F[pl + k * ld];
+  }
+  __syncthreads();
+  // W = sym(GA) Fc^T (nb x r, ld) over F, 3 x 3 outputs per thread
+  double* Wt = F;
+  const int tx = tid & 15, ty = tid >> 4;
+  {
+    double acc[3][3] = {};
+    for (int k = 0; k < nb; ++k) {
+      double x[3], y[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int ii = tx + 16 * a, c = ty + 16 * a;
+        x[a] = ii < nb ? A[ii + k * ld] : 0.0;
+        y[a] = c < r ? Fc[c + k * ld] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] += x[a] * y[b];
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int ii = tx + 16 * a, c = ty + 16 * b;
+        if (ii < nb && c < r) Wt[ii + c * ld] = acc[a][b];
+      }
   }
   __syncthreads();
-  // T (nb x r) into Cb: T[piv[c'], j] = dsc[piv[c']] * Linv[j, c']
-  for (int idx = tid; idx < nb * r; idx += nt) {
-    const int cp = idx % nb, j = idx / nb;
-    const int row = piv[cp];
-    Cb[row + j * nb] = (cp < r) ? dsc[row] * B[j + cp * nb] : 0.0;
+  // A_r = Fc W (r x r, ld lr) over A
+  const int lr = r | 1;
+  double* J = A;
+  {
+    double acc[3][3] = {};
+    for (int k = 0; k < nb; ++k) {
+      double x[3], y[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int ii = tx + 16 * a, c = ty + 16 * a;
+        x[a] = ii < r ? Fc[ii + k * ld] : 0.0;
+        y[a] = c < r ? Wt[k + c * ld] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] += x[a] * y[b];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int ii = tx + 16 * a, c = ty + 16 * b;
+        if (ii < r && c < r) J[ii + c * lr] = acc[a][b];
+      }
   }
   __syncthreads();
-  // B <- GA T (nb x r)
-  for (int idx = tid; idx < nb * r; idx += nt) {
-    const int i = idx % nb, c = idx / nb;
-    double v = 0.0;
-    for (int l = 0; l < nb; ++l)
-      v += 0.5 * (ga[i + (size_t)l * nb] + ga[l + (size_t)i * nb]) * Cb[l + c * nb];
-    B[idx] = v;
-  }
-  __syncthreads();
-  // A <- T^T (GA T) (r x r, ld r), symmetrised
   for (int idx = tid; idx < r * r; idx += nt) {
-    const int i = idx % r, c = idx / r;
-    double v = 0.0, w = 0.0;
-    for (int l = 0; l < nb; ++l) {
-      v += Cb[l + i * nb] * B[l + c * nb];
-      w += Cb[l + c * nb] * B[l + i * nb];
+    const int ii = idx % r, c = idx / r;
+    if (ii > c) {
+      const double s = 0.5 * (J[ii + c * lr] + J[c + ii * lr]);
+      J[ii + c * lr] = s;
+      J[c + ii * lr] = s;
     }
-    A[idx] = 0.5 * (v + w);
   }
   __syncthreads();
-  jacobi_lds(A, B, r, rot, red);   // eigenvectors Y in B (ld r)
-  sort_desc_lds(A, r, perm);
+  double* Y = F;
+  const int ly = r | 1;
+  jacobi_lds(J, lr, Y, ly, r, work);
+  sort_desc_lds(J, lr, r, perm);
   const int mm = min(m, r);
   double* cf = Cf2 + (size_t)blockIdx.x * M3 * 2 * m;
-  for (int idx = tid; idx < nb * 2 * m; idx += nt) {
-    const int i = idx % nb, c = idx / nb;
-    const int cc = c % m;
+  for (int idx = tid; idx < nb * m; idx += nt) {
+    const int ii = idx % nb, c = idx / nb;
     double v = 0.0;
-    if (cc < mm) {
-      const int pc = perm[cc];
-      for (int l = 0; l < r; ++l) v += Cb[i + l * nb] * B[l + pc * r];
+    if (c < mm) {
+      const double* y = Y + perm[c] * ly;
+      for (int l = 0; l < r; ++l) v += Fc[l + ii * ld] * y[l];
     }
-    if (c >= m && i < m) v = 0.0;
-    cf[i + (size_t)c * M3] = v;
+    cf[ii + (size_t)c * M3] = v;
+    cf[ii + (size_t)(c + m) * M3] = (ii < m) ? 0.0 : v;
   }
   for (int c = tid; c < m; c += nt)
-    lam[(size_t)blockIdx.x * m + c] = c < mm ? A[perm[c] + perm[c] * r] : 0.0;
+    lam[(size_t)blockIdx.x * m + c] = c < mm ? J[perm[c] + perm[c] * lr] : 0.0;
+}
+
+size_t rr_smem(int nb) {
+  const int ld = nb | 1;
+  return sizeof(double) * (3 * nb * ld + 2 * nb + JAC_WORK + 3) + sizeof(int) * (2 * nb);
 }
 
 void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,
            double* Cf, double* lam, const int* active, hipStream_t st) {
+  (void)P;
   if (np == 0) return;
-  const size_t sm = sizeof(double) * (3 * nb * nb + nb + 4 * (nb / 2 + 1) + 16) +
-                    sizeof(int) * 2 * nb;
-  k_rr<<<np, 256, sm, st>>>(P, GA, GB, nb, m, Cf, lam, active);
+  if (nb > 48 || nb < 1) throw Error(1, "Rayleigh-Ritz block larger than 48");
+  k_rr<<<np, 256, rr_smem(nb), st>>>(GA, GB, nb, m, Cf, lam, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -555,11 +644,11 @@ __global__ __launch_bounds__(256) void k_pinv(const PairDev* P, double* Kp, doub
   extern __shared__ double sm[];
   const PairDev p = P[blockIdx.x];
   const int n = p.ncp;
-  double* A = sm;
-  double* V = A + n * n;
-  double* rot = V + n * n;
-  double* red = rot + 4 * (n / 2 + 1);
-  double* dsc = red + 16;
+  const int la = n | 1;
+  double* A = sm;                 // n x n, ld la
+  double* V = A + n * la;         // n x n, ld la
+  double* work = V + n * la;
+  double* dsc = work + JAC_WORK;
   int* perm = reinterpret_cast<int*>(dsc + n);
   double* K = Kp + p.kp_off;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -569,26 +658,26 @@ __global__ __launch_bounds__(256) void k_pinv(const PairDev* P, double* Kp, doub
   __syncthreads();
   for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
     const int r = i % n, c = i / n;
-    A[i] = 0.5 * (K[r + c * n] + K[c + r * n]) * dsc[r] * dsc[c];
+    A[r + c * la] = 0.5 * (K[r + c * n] + K[c + r * n]) * dsc[r] * dsc[c];
   }
   __syncthreads();
-  jacobi_lds(A, V, n, rot, red);
-  sort_desc_lds(A, n, perm);
-  const double lmax = A[perm[0] + perm[0] * n];
+  jacobi_lds(A, la, V, la, n, work);
+  sort_desc_lds(A, la, n, perm);
+  const double lmax = A[perm[0] + perm[0] * la];
   const int keep = n - p.nrb;   // drop the nrb smallest
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int r = idx % n, c = idx / n;
     double v = 0.0;
     for (int q = 0; q < keep; ++q) {
       const int j = perm[q];
-      const double l = A[j + j * n];
-      if (l > 0.0) v += V[r + j * n] * V[c + j * n] / l;
+      const double l = A[j + j * la];
+      if (l > 0.0) v += V[r + j * la] * V[c + j * la] / l;
     }
     K[idx] = v * dsc[r] * dsc[c];
   }
   if (threadIdx.x == 0) {
     int z = 0;
-    for (int j = 0; j < n; ++j) z += !(A[j + j * n] > tol * lmax);
+    for (int j = 0; j < n; ++j) z += !(A[j + j * la] > tol * lmax);
     nnull[blockIdx.x] = z;
   }
 }
@@ -596,8 +685,8 @@ __global__ __launch_bounds__(256) void k_pinv(const PairDev* P, double* Kp, doub
 void lp_pinv(const PairDev* P, int np, double* Kp, int ncp_max, double tol, int* nnull,
              hipStream_t st) {
   if (np == 0) return;
-  const size_t sm = sizeof(double) * (2 * ncp_max * ncp_max + 4 * (ncp_max / 2 + 1) + 16 + ncp_max) +
-                    sizeof(int) * (ncp_max + 1);
+  const size_t sm = sizeof(double) * (2 * ncp_max * (ncp_max | 1) + JAC_WORK + ncp_max) +
+                    sizeof(int) * ncp_max;
   k_pinv<<<np, 256, sm, st>>>(P, Kp, tol, nnull);
   AMB_LAUNCH_CHECK();
 }

@@ -104,6 +104,7 @@ struct ambddc_ctx {
   Top top;
   bool ready = false;
   ambddc_stats stats{};
+  KTimer kt;   // optional per-class kernel timing
   // PCG workspace
   int pcg_cap = 0, pcg_maxit = 0;
   DBuf<double> px, pr, pz, pp, pq, pdot, ppart, pah, pbh, plz;
@@ -383,7 +384,17 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
   }
   launch_diag_copy(int(L.nG_tot), L.diagpos.p, L.aug.p, L.diagG.p, st);
   launch_weights(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.diagG.p, L.delta.p, st);
-  L.ldl_aug.run(st);
+  {
+    double f = 0.0, b = 0.0;
+    for (int s = 0; s < L.nsub; ++s) {
+      const double nI = L.nI[s], nG = L.nG[s];
+      f += nI * nI * nI / 3.0 + nI * nI * nG + nI * nG * nG;
+      b += 8.0 * (nI + nG) * (nI + nG);
+    }
+    c.kt.begin("schur", st);
+    L.ldl_aug.run(st);
+    c.kt.end("schur", st, f, b);
+  }
   check_ldlt(L.ldl_aug, st, "interior factorisation", li);
   L.sym_aug.run(st);
   // rho_s = mean diag(S^s)
@@ -434,6 +445,9 @@ struct PairWork {
   DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw;
   DBuf<int> active, kout, nnull;
   GemmOp gS, gM1, gM2, gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
+  KTimer* kt = nullptr;
+  double apply_flops = 0.0, apply_bytes = 0.0;   // grouped S products, per launch
+  std::vector<int> act;                          // host copy of the active flags
 };
 
 void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
@@ -564,6 +578,8 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
     const double* S = L.aug.p + L.aug_off[s] + nI + int64_t(nI) * N;
     const double* Tn = L.naug.p + L.naug_off[s] + nl + int64_t(nl) * NN;
     W.gS.add(S, N, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nG, cols, nG);
+    W.apply_flops += 2.0 * nG * double(nG) * cols;
+    W.apply_bytes += 8.0 * (double(nG) * nG + 2.0 * double(nG) * cols);
     W.gM1.add(Tn, NN, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nl, cols, nG);
     if (L.nc[s] > 0)
       W.gM2.add(Tn + int64_t(nG) * NN, NN, W.Zc.p + Zoff[s], L.nc[s], W.Y.p + Yoff[s], nl, nG, cols,
@@ -629,7 +645,9 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
 void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
   lp_to_slab(W.dp.p, W.np, W.V.p, W.m, col, true, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
              W.active.p, st);
+  W.kt->begin("pair_apply", st);
   W.gS.run(1.0, 0.0, st);
+  W.kt->end("pair_apply", st, W.apply_flops, W.apply_bytes);
   lp_from_slab_ab(W.dp.p, W.np, W.Y.p, W.m, col, W.AV.p, W.BV.p, L.diagG.p, W.idx.sh_s.p,
                   W.idx.sh_t.p, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.active.p,
                   st);
@@ -640,9 +658,30 @@ void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
 // with coefficient jumps the implicit updates drift out of the factor space).
 void rayleigh_ritz(Level& L, PairWork& W, int v, bool with_p, hipStream_t st) {
   const int nb = (v + 1) * W.m;
-  W.gram_a[v].run(1.0, 0.0, st);
-  W.gram_b[v].run(1.0, 0.0, st);
-  lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
+  if (W.kt->any()) {
+    double fg = 0.0, bg = 0.0, nact = 0.0;
+    for (int p = 0; p < W.np; ++p) {
+      if (!W.act.empty() && !W.act[p]) continue;
+      const double n = W.hp[p].nGs + W.hp[p].nGt;
+      fg += 2.0 * 2.0 * n * nb * nb;
+      bg += 2.0 * 8.0 * (2.0 * n * nb + double(nb) * nb);
+      nact += 1.0;
+    }
+    const double b3 = double(nb) * nb * nb;
+    const double frr = nact * (9.0 * b3 + 4.0 / 3.0 * b3 + 2.0 * double(nb) * nb * W.m);
+    const double brr = nact * 8.0 * (2.0 * double(nb) * nb + 2.0 * double(nb) * W.m);
+    W.kt->begin("pair_gram", st);
+    W.gram_a[v].run(1.0, 0.0, st);
+    W.gram_b[v].run(1.0, 0.0, st);
+    W.kt->end("pair_gram", st, fg, bg);
+    W.kt->begin("pair_rr", st);
+    lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
+    W.kt->end("pair_rr", st, frr, brr);
+  } else {
+    W.gram_a[v].run(1.0, 0.0, st);
+    W.gram_b[v].run(1.0, 0.0, st);
+    lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
+  }
   W.upd_v[v].run(1.0, 0.0, st);
   lp_commit(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.T.p, W.m, with_p, true, W.active.p, st);
   lp_project(W.dp.p, W.np, W.V.p, W.m, 0, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, W.active.p,
@@ -653,9 +692,9 @@ void rayleigh_ritz(Level& L, PairWork& W, int v, bool with_p, hipStream_t st) {
 }
 
 int count_active(PairWork& W, hipStream_t st) {
-  std::vector<int> a = W.active.download(st);
+  W.act = W.active.download(st);
   int n = 0;
-  for (int x : a) n += x != 0;
+  for (int x : W.act) n += x != 0;
   return n;
 }
 
@@ -666,6 +705,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   W.m = std::max(c.opt.lobpcg_block, nev + 1);
   if (W.m > 16) throw Error(AMBDDC_E_INVALID_ARG, "lobpcg_block larger than 16 is not supported");
   L.m = W.m;
+  W.kt = &c.kt;
   build_pair_work(c, L, W);
   if (W.np == 0) {
     L.omega = 0.0;
@@ -692,6 +732,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   const int nconv = std::min(nev + 1, m);
   std::vector<int> ones(W.np, 1);
   W.active.upload(ones, st);
+  W.act = ones;
   // start block, projected; first Rayleigh-Ritz on X alone
   lp_random(W.dp.p, W.np, W.V.p, m, c.opt.seed + uint64_t(li) * 7919u, st);
   lp_project(W.dp.p, W.np, W.V.p, m, 0, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, nullptr, true, st);
@@ -999,7 +1040,27 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
   for (int k = 0; k < nrhs; ++k)
     if (hff[k] == 0.0) act[k] = 0;
   c.pact.upload(act, st);
-  apply_level(c, 0, c.pr.p, n, c.pz.p, n, nrhs);
+  // algorithmic work of one preconditioner application (timing only)
+  double apf = 0.0, apb = 0.0;
+  if (c.kt.any()) {
+    double ent = 0.0;
+    for (auto& lp : c.L) {
+      const Level& Lv = *lp;
+      for (int s = 0; s < Lv.nsub; ++s) {
+        const double nI = Lv.nI[s], nG = Lv.nG[s], ncs = Lv.nc[s];
+        ent += nI * nI + 2.0 * nI * nG + nG * nG + 2.0 * nG * ncs;
+      }
+    }
+    ent += double(c.top.n) * c.top.n;
+    apf = 2.0 * ent * nrhs;
+    apb = 8.0 * ent + 48.0 * double(n) * nrhs;
+  }
+  auto precondition = [&]() {
+    c.kt.begin("bddc_apply", st);
+    apply_level(c, 0, c.pr.p, n, c.pz.p, n, nrhs);
+    c.kt.end("bddc_apply", st, apf, apb);
+  };
+  precondition();
   launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rz, st);
   launch_copy(c.pp.p, c.pz.p, nn, st);
   int nact = 0;
@@ -1026,7 +1087,7 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
     }
     if (nact == 0) break;
     if (changed) c.pact.upload(act, st);
-    apply_level(c, 0, c.pr.p, n, c.pz.p, n, nrhs);
+    precondition();
     launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rzn, st);
     launch_pcg_update_p(n, nrhs, rzn, rz, c.pact.p, c.pp.p, c.pz.p, c.pbh.p, it, c.pcg_maxit, st);
   }
@@ -1273,6 +1334,48 @@ ambddc_status ambddc_get_stats(ambddc_handle h, ambddc_stats* out) {
   return ambddc_status(guard([&] {
     if (!h || !out) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     *out = h->stats;
+  }));
+}
+
+static const char* const kTimingClasses[] = {"pair_rr", "pair_apply", "pair_gram", "schur",
+                                             "bddc_apply"};
+
+static bool known_class(const std::string& name) {
+  for (const char* k : kTimingClasses)
+    if (name == k) return true;
+  return false;
+}
+
+ambddc_status ambddc_timing_enable(ambddc_handle h, const char* classes) {
+  return ambddc_status(guard([&] {
+    if (!h) throw Error(AMBDDC_E_INVALID_ARG, "null handle");
+    const std::string list = classes ? classes : "";
+    size_t a = 0;
+    while (a < list.size()) {
+      size_t b = list.find(',', a);
+      if (b == std::string::npos) b = list.size();
+      const std::string name = list.substr(a, b - a);
+      if (!name.empty() && !known_class(name))
+        throw Error(AMBDDC_E_INVALID_ARG, "unknown timing class '" + name + "'");
+      a = b + 1;
+    }
+    h->kt.enable(list);
+  }));
+}
+
+ambddc_status ambddc_timing_read(ambddc_handle h, const char* cls, int32_t* launches,
+                                 double* total_ms, double* flops, double* bytes) {
+  return ambddc_status(guard([&] {
+    if (!h || !cls) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (!known_class(cls)) throw Error(AMBDDC_E_INVALID_ARG, std::string("unknown timing class '") + cls + "'");
+    h->kt.collect();
+    const int i = h->kt.find(cls);
+    KTimer::Acc a;
+    if (i >= 0) a = h->kt.acc[i];
+    if (launches) *launches = a.launches;
+    if (total_ms) *total_ms = a.ms;
+    if (flops) *flops = a.flops;
+    if (bytes) *bytes = a.bytes;
   }));
 }
 

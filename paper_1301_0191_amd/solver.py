@@ -223,3 +223,21 @@ class Handle:
             _lib.check(self._lib.ambddc_get_top_coarse(self._h, K.ctypes.data_as(C.c_void_p),
                                                        C.byref(n)))
         return K
+
+    # ---- kernel timing ----
+    def timing_enable(self, classes):
+        """Time the listed kernel classes (list or comma-separated string)
+        with HIP events on the handle's stream; None switches timing off."""
+        if classes is None:
+            arg = None
+        else:
+            arg = (",".join(classes) if not isinstance(classes, str) else classes).encode()
+        _lib.check(self._lib.ambddc_timing_enable(self._h, arg))
+
+    def timing_read(self, cls):
+        """{'launches', 'ms', 'flops', 'bytes'} summed since timing_enable."""
+        n = C.c_int32()
+        ms, fl, by = C.c_double(), C.c_double(), C.c_double()
+        _lib.check(self._lib.ambddc_timing_read(self._h, cls.encode(), C.byref(n), C.byref(ms),
+                                                C.byref(fl), C.byref(by)))
+        return dict(launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
