@@ -1,9 +1,11 @@
 """Pins of the oracle's substructuring layer.
 
-* Glob counts against the paper's weak-scaling table (Tab. 1: elasticity
-  cube, H/h = 16, N = 8 and 64 cubic subdomains; n, n_Gamma and n_f are
-  printed rounded) and against the box-decomposition counts of the
-  workloads (3(B-1)B^2 faces, 3B(B-1)^2 edges, (B-1)^3 corners).
+* Glob counts against the paper's weak-scaling table (Tabs. 1-2: elasticity
+  cube, H/h = 16, N = 8, 64 and 512 cubic subdomains; n, n_Gamma and n_f
+  are printed rounded) and the first-level pair count of Tab. 5 (4096
+  subdomains), both from fixtures under tests/golden/, and against the
+  box-decomposition counts of the workloads (3(B-1)B^2 faces, 3B(B-1)^2
+  edges, (B-1)^3 corners).
 * Schur complements: symmetric PSD, constants (Poisson) or rigid modes
   (elasticity) in the null space of floating subdomains, minimal energy
   among interior extensions, and the assembled interface problem
@@ -12,6 +14,8 @@
   leaves continuous functions unchanged (Section 2).
 * Coarse basis: C Psi = I and Psi^T S Psi = -mu (Section 5).
 """
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -31,24 +35,67 @@ def _glob_counts(prob):
     return types.count("corner"), types.count("edge"), types.count("face"), n_iface_dofs
 
 
-@pytest.mark.parametrize("B,n_print,ng_print,nf_print", [
-    (2, (0.1, 1e6), (9.5, 1e3), 12),          # Tab. 1, N = 8: 0.1M, 9.5k, 12
-    (4, (0.8, 1e6), (0.1, 1e6), (0.1, 1e3)),  # Tab. 1, N = 64: 0.8M, 0.1M, 0.1k
-])
-def test_glob_counts_match_paper_weak_scaling_table(B, n_print, ng_print, nf_print):
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _printed(v):
+    """Parse a rounded figure as the paper prints it: '9.5k', '0.1M', '12'."""
+    scale = {"k": 1e3, "M": 1e6}.get(v[-1], 1.0)
+    digits = v[:-1] if v[-1] in "kM" else v
+    return float(digits), scale, (len(digits.split(".")[1]) if "." in digits else 0)
+
+
+def _matches_printed(x, v):
+    val, scale, nd = _printed(v)
+    return round(x / scale, nd) == val
+
+
+def _golden_rows(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_rows("cube_weak_scaling_counts.txt")[:2],
+                         ids=lambda r: "N" + r[0])
+def test_glob_counts_match_paper_weak_scaling_table(row):
+    N = int(row[0])
+    B = round(N ** (1.0 / 3.0))
     n = 16 * B
     prob = W.make_problem((n, n, n), (B, B, B), dof_per_node=3, dirichlet_axis=None)
     nc, ne, nf, n_gamma = _glob_counts(prob)
-    ndof = prob.n_dofs_total
-    assert round(ndof / n_print[1], 1) == n_print[0]
-    assert round(n_gamma / ng_print[1], 1) == ng_print[0]
-    if isinstance(nf_print, tuple):
-        assert round(nf / nf_print[1], 1) == nf_print[0]
-    else:
-        assert nf == nf_print
+    assert _matches_printed(prob.n_dofs_total, row[1])
+    assert _matches_printed(n_gamma, row[2])
+    assert _matches_printed(nf, row[3])
     # exact structural counts behind the rounded figures
     assert nf == 3 * (B - 1) * B * B
     assert n_gamma == 3 * ((n + 1) ** 3 - (n + 2 - B) ** 3)
+
+
+@pytest.mark.slow
+def test_glob_counts_match_paper_weak_scaling_table_n512():
+    row = _golden_rows("cube_weak_scaling_counts.txt")[2]
+    B = 8
+    n = 16 * B
+    prob = W.make_problem((n, n, n), (B, B, B), dof_per_node=3, dirichlet_axis=None)
+    nc, ne, nf, n_gamma = _glob_counts(prob)
+    assert _matches_printed(prob.n_dofs_total, row[1])
+    assert _matches_printed(n_gamma, row[2])
+    assert _matches_printed(nf, row[3])
+
+
+def test_first_level_pairs_of_the_4096_subdomain_cube():
+    g = dict((k, int(v)) for k, v in _golden_rows("cube_4096_pairs.txt"))
+    prob = W.make_problem((64, 64, 64), (16, 16, 16), dof_per_node=3, dirichlet_axis=None)
+    nc, ne, nf, _ = _glob_counts(prob)
+    assert nf == g["pairs_level1"]
+    # the second level groups 4^3 first-level subdomains: a 4 x 4 x 4 box of
+    # subdomains has 3 * 3 * 4^2 faces
+    assert 3 * 3 * 4 * 4 == g["pairs_level2"]
+    assert prob.n_dofs_total - g["unknowns_printed"] == 3
 
 
 @pytest.mark.parametrize("cfg,expect", [("c1", (1, 6, 12)), ("c2", (27, 108, 144))])
