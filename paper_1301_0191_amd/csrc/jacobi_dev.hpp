@@ -1,10 +1,10 @@
 // Cyclic two-sided Jacobi eigensolver for one small symmetric matrix held
-// in LDS, run by a workgroup of 256 threads.
+// in LDS, run by a workgroup of 32 * TPP threads.
 //
 // Parallel round-robin ordering: in every round the n indices form n/2
 // disjoint pairs (p, q) whose rotations commute.  Thread t works for pair
-// k = t / 8 and block b = t % 8 of rows (columns) b, b + 8, ..., so the
-// eight threads of a pair are neighbouring lanes of one wave.  A round is:
+// k = t / TPP and block b = t % TPP of rows (columns) b, b + TPP, ..., so
+// the TPP threads of a pair are neighbouring lanes of one wave.  A round is:
 // each thread computes its pair's rotation from A_pp, A_qq, A_pq; the column
 // rotations of A and of the eigenvector matrix V on its rows (a wave reads
 // those three entries before it writes the columns, and no other wave
@@ -16,7 +16,7 @@
 namespace ambddc {
 
 constexpr int JAC_MAXN = 64;
-constexpr int JAC_WORK = 8;   // doubles
+constexpr int JAC_WORK = 32;   // doubles
 
 // pair k of round rr (np even player count, mm = np - 1 rounds per sweep);
 // q = -1 when the partner is the dummy player of an odd n
@@ -37,12 +37,15 @@ __device__ inline void jac_pair(int k, int rr, int np, int mm, int n, int& p, in
 // A: n x n (ld lda) symmetric, overwritten (diagonal -> eigenvalues).
 // V: n x n (ld ldv) receives the eigenvectors (columns).  Odd lda and ldv
 // keep the LDS accesses free of bank conflicts.  work: JAC_WORK doubles.
-// n <= JAC_MAXN, blockDim = 256.
+// n <= JAC_MAXN, blockDim = 32 * TPP, TPP in {8, 16, 32}.
+template <int TPP>
 __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n, double* work) {
+  constexpr int RPT = JAC_MAXN / TPP;   // rows (columns) per thread
+  constexpr int NW = TPP / 2;           // waves
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = tid >> 3, blk = tid & 7;
-  double* red = work;   // [2 * 4]: (off, diag) partial sums per wave
-  for (int idx = tid; idx < n * n; idx += 256) {
+  const int k = tid / TPP, blk = tid % TPP;
+  double* red = work;   // [2 * NW]: (off, diag) partial sums per wave
+  for (int idx = tid; idx < n * n; idx += 32 * TPP) {
     const int i = idx % n, j = idx / n;
     V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
   }
@@ -60,16 +63,18 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
     if (q >= 0) {
       const double apq = A[p + q * lda];
       if (apq != 0.0) {
-        const double tau = (A[q + q * lda] - A[p + p * lda]) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        c = 1.0 / sqrt(1.0 + t * t);
+        // tangent of the smaller rotation angle annihilating A_pq:
+        // t = 2 A_pq sgn(d) / (|d| + sqrt(d^2 + 4 A_pq^2)), d = A_qq - A_pp
+        const double d = A[q + q * lda] - A[p + p * lda];
+        const double t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+        c = rsqrt(1.0 + t * t);
         s = t * c;
       }
       // column pass: new col p = c col_p - s col_q, new col q = s col_p + c col_q
-      double a[8], b[8];
+      double a[RPT], b[RPT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int i = blk + TPP * u;
         if (i < n) {
           a[u] = A[i + p * lda];
           b[u] = A[i + q * lda];
@@ -77,8 +82,8 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
       }
       if (acc) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = blk + 8 * u;
+        for (int u = 0; u < RPT; ++u) {
+          const int i = blk + TPP * u;
           if (i < n) {
             const double a2 = a[u] * a[u], b2 = b[u] * b[u];
             dia += (i == p ? a2 : 0.0) + (i == q ? b2 : 0.0);
@@ -87,24 +92,24 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int i = blk + TPP * u;
         if (i < n) {
           A[i + p * lda] = c * a[u] - s * b[u];
           A[i + q * lda] = s * a[u] + c * b[u];
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int i = blk + TPP * u;
         if (i < n) {
           a[u] = V[i + p * ldv];
           b[u] = V[i + q * ldv];
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int i = blk + TPP * u;
         if (i < n) {
           V[i + p * ldv] = c * a[u] - s * b[u];
           V[i + q * ldv] = s * a[u] + c * b[u];
@@ -112,8 +117,8 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
       }
     } else if (acc && p >= 0) {
       // paired with the dummy: column p is only read, for the norms
-      for (int u = 0; u < 8; ++u) {
-        const int i = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int i = blk + TPP * u;
         if (i < n) {
           const double a2 = A[i + p * lda] * A[i + p * lda];
           dia += (i == p) ? a2 : 0.0;
@@ -134,18 +139,18 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
     __syncthreads();
     // row pass, with the annihilated entries set to zero
     if (q >= 0) {
-      double a[8], b[8];
+      double a[RPT], b[RPT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int j = blk + TPP * u;
         if (j < n) {
           a[u] = A[p + j * lda];
           b[u] = A[q + j * lda];
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = blk + 8 * u;
+      for (int u = 0; u < RPT; ++u) {
+        const int j = blk + TPP * u;
         if (j < n) {
           A[p + j * lda] = (j == q) ? 0.0 : c * a[u] - s * b[u];
           A[q + j * lda] = (j == p) ? 0.0 : s * a[u] + c * b[u];
@@ -155,7 +160,7 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
     bool stop = false;
     if (acc) {
       double to = 0.0, td = 0.0;
-      for (int w = 0; w < 4; ++w) { to += red[2 * w]; td += red[2 * w + 1]; }
+      for (int w = 0; w < NW; ++w) { to += red[2 * w]; td += red[2 * w + 1]; }
       stop = (to <= 1e-30 * td || to == 0.0);
     }
     __syncthreads();

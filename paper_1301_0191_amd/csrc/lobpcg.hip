@@ -361,14 +361,15 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // pivot rows are never touched again (their scaling is applied at the end).
 // The next pivot is found with a 64-bit LDS max over keys (diagonal value
 // with its low 6 bits replaced by 63 - index), in a ring of three slots.
-constexpr int RR_COLS = 12;   // columns per wave (nb <= 48, 4 waves)
+constexpr int RR_THREADS = 1024;   // 16 waves; 32 threads per Jacobi pair
+constexpr int RR_COLS = 3;         // columns per wave (nb <= 48)
 
 __device__ inline unsigned long long rr_key(double v, int i) {
   if (!(v > 0.0)) return 0ull;
   return ((unsigned long long)__double_as_longlong(v) & ~63ull) | (unsigned long long)(63 - i);
 }
 
-__global__ __launch_bounds__(256) void k_rr(const double* GA, const double* GB, int nb, int m,
+__global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const double* GB, int nb, int m,
                                             double* Cf2, double* lam, const int* active) {
   extern __shared__ double sm[];
   if (active && !active[blockIdx.x]) return;
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(256) void k_rr(const double* GA, const double* GB, 
   __syncthreads();
   // symmetrise (A) and scale (B): columns owned by waves, lanes = rows; read
   // into registers, then written after a barrier
-  double sa[12], sb[12];
+  double sa[RR_COLS], sb[RR_COLS];
   {
     int u = 0;
     for (int k = wave; k < nb; k += nw, ++u) {
@@ -477,29 +478,29 @@ __global__ __launch_bounds__(256) void k_rr(const double* GA, const double* GB, 
     Fc[l + k * ld] = rs[pl] * dsc[k] * F[pl + k * ld];
   }
   __syncthreads();
-  // W = sym(GA) Fc^T (nb x r, ld) over F, 3 x 3 outputs per thread
+  // W = sym(GA) Fc^T (nb x r, ld) over F, 2 x 2 outputs per thread
   double* Wt = F;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int tx = tid & 31, ty = tid >> 5;
   {
-    double acc[3][3] = {};
+    double acc[2][2] = {};
     for (int k = 0; k < nb; ++k) {
-      double x[3], y[3];
+      double x[2], y[2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int ii = tx + 16 * a, c = ty + 16 * a;
+      for (int a = 0; a < 2; ++a) {
+        const int ii = tx + 32 * a, c = ty + 32 * a;
         x[a] = ii < nb ? A[ii + k * ld] : 0.0;
         y[a] = c < r ? Fc[c + k * ld] : 0.0;
       }
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) acc[a][b] += x[a] * y[b];
+        for (int b = 0; b < 2; ++b) acc[a][b] += x[a] * y[b];
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int ii = tx + 16 * a, c = ty + 16 * b;
+      for (int b = 0; b < 2; ++b) {
+        const int ii = tx + 32 * a, c = ty + 32 * b;
         if (ii < nb && c < r) Wt[ii + c * ld] = acc[a][b];
       }
   }
@@ -508,26 +509,25 @@ __global__ __launch_bounds__(256) void k_rr(const double* GA, const double* GB, 
   const int lr = r | 1;
   double* J = A;
   {
-    double acc[3][3] = {};
+    double acc[2][2] = {};
     for (int k = 0; k < nb; ++k) {
-      double x[3], y[3];
+      double x[2], y[2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int ii = tx + 16 * a, c = ty + 16 * a;
+      for (int a = 0; a < 2; ++a) {
+        const int ii = tx + 32 * a, c = ty + 32 * a;
         x[a] = ii < r ? Fc[ii + k * ld] : 0.0;
         y[a] = c < r ? Wt[k + c * ld] : 0.0;
       }
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) acc[a][b] += x[a] * y[b];
+        for (int b = 0; b < 2; ++b) acc[a][b] += x[a] * y[b];
     }
-    __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int ii = tx + 16 * a, c = ty + 16 * b;
+      for (int b = 0; b < 2; ++b) {
+        const int ii = tx + 32 * a, c = ty + 32 * b;
         if (ii < r && c < r) J[ii + c * lr] = acc[a][b];
       }
   }
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void k_rr(const double* GA, const double* GB, 
   __syncthreads();
   double* Y = F;
   const int ly = r | 1;
-  jacobi_lds(J, lr, Y, ly, r, work);
+  jacobi_lds<RR_THREADS / 32>(J, lr, Y, ly, r, work);
   sort_desc_lds(J, lr, r, perm);
   const int mm = min(m, r);
   double* cf = Cf2 + (size_t)blockIdx.x * M3 * 2 * m;
@@ -571,7 +571,7 @@ void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb,
   (void)P;
   if (np == 0) return;
   if (nb > 48 || nb < 1) throw Error(1, "Rayleigh-Ritz block larger than 48");
-  k_rr<<<np, 256, rr_smem(nb), st>>>(GA, GB, nb, m, Cf, lam, active);
+  k_rr<<<np, RR_THREADS, rr_smem(nb), st>>>(GA, GB, nb, m, Cf, lam, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -640,7 +640,7 @@ void lp_pair_coarse(const PairDev* P, int np, const double* kc, const int64_t* k
 // K G K = K, which is all the preconditioner needs (its input lies in
 // range(K) and null(K) maps onto the deflated rigid modes).  nnull[p] counts
 // the scaled eigenvalues below tol * max for the Assumption 1 check.
-__global__ __launch_bounds__(256) void k_pinv(const PairDev* P, double* Kp, double tol, int* nnull) {
+__global__ __launch_bounds__(1024) void k_pinv(const PairDev* P, double* Kp, double tol, int* nnull) {
   extern __shared__ double sm[];
   const PairDev p = P[blockIdx.x];
   const int n = p.ncp;
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(256) void k_pinv(const PairDev* P, double* Kp, doub
     A[r + c * la] = 0.5 * (K[r + c * n] + K[c + r * n]) * dsc[r] * dsc[c];
   }
   __syncthreads();
-  jacobi_lds(A, la, V, la, n, work);
+  jacobi_lds<32>(A, la, V, la, n, work);
   sort_desc_lds(A, la, n, perm);
   const double lmax = A[perm[0] + perm[0] * la];
   const int keep = n - p.nrb;   // drop the nrb smallest
@@ -687,7 +687,7 @@ void lp_pinv(const PairDev* P, int np, double* Kp, int ncp_max, double tol, int*
   if (np == 0) return;
   const size_t sm = sizeof(double) * (2 * ncp_max * (ncp_max | 1) + JAC_WORK + ncp_max) +
                     sizeof(int) * ncp_max;
-  k_pinv<<<np, 256, sm, st>>>(P, Kp, tol, nnull);
+  k_pinv<<<np, 1024, sm, st>>>(P, Kp, tol, nnull);
   AMB_LAUNCH_CHECK();
 }
 
