@@ -130,6 +130,18 @@ ambddc_status ambddc_solve(ambddc_handle h, const double* rhs_dev, int32_t nrhs,
                            int32_t maxit, double* x_dev, int32_t* iterations_host,
                            double* cond_host);
 
+/* Numeric set-up from element log10-coefficients: coeff_e = 10^theta_e is
+ * computed on the device, then as ambddc_setup.  theta_dev: device
+ * [n_elems]; nu_dev as in ambddc_setup.  Same errors as ambddc_setup. */
+ambddc_status ambddc_setup_log10(ambddc_handle h, const double* theta_dev, const double* nu_dev);
+
+/* Least-squares misfit of solutions against observations:
+ * R = X - X_obs (device [n_free*nrhs], may alias neither input) and, if
+ * J_host is not NULL, J = 1/2 ||R||_F^2 (host).  R is the right-hand side of
+ * the adjoint solve K Lam = R.  nrhs in 1..16.  Errors: E_INVALID_ARG. */
+ambddc_status ambddc_misfit(ambddc_handle h, const double* X_dev, const double* Xobs_dev,
+                            int32_t nrhs, double* R_dev, double* J_host);
+
 /* Element gradient of a misfit w.r.t. element log10-coefficients theta_e,
  * K = sum_e 10^theta_e Khat_e:  grad[e] = -ln(10) sum_k lam_k,e^T K_e x_k,e
  * with the element matrices of the last setup.  X_dev, Lam_dev: device

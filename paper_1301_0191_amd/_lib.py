@@ -84,6 +84,9 @@ _SIGS = {
     "ambddc_get_coarse_element": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                             C.POINTER(C.c_int32)]),
     "ambddc_get_top_coarse": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "ambddc_setup_log10": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ambddc_misfit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                C.POINTER(C.c_double)]),
     "ambddc_timing_enable": (C.c_int, [C.c_void_p, C.c_char_p]),
     "ambddc_timing_read": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_double),

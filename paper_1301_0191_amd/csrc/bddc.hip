@@ -479,6 +479,30 @@ void launch_copy(double* dst, const double* src, size_t n, hipStream_t st) {
   AMB_LAUNCH_CHECK();
 }
 
+// out = 10^theta elementwise (coefficients from log10-coefficients)
+__global__ void k_pow10(size_t n, const double* theta, double* out) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = exp10(theta[i]);
+}
+
+void launch_pow10(size_t n, const double* theta, double* out, hipStream_t st) {
+  if (n == 0) return;
+  k_pow10<<<ceil_div(int64_t(n), 256), 256, 0, st>>>(n, theta, out);
+  AMB_LAUNCH_CHECK();
+}
+
+// out = a - b elementwise
+__global__ void k_sub(size_t n, const double* a, const double* b, double* out) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+void launch_sub(size_t n, const double* a, const double* b, double* out, hipStream_t st) {
+  if (n == 0) return;
+  k_sub<<<ceil_div(int64_t(n), 256), 256, 0, st>>>(n, a, b, out);
+  AMB_LAUNCH_CHECK();
+}
+
 }  // namespace ambddc
 
 namespace ambddc {

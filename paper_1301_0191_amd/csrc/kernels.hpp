@@ -104,5 +104,7 @@ void launch_coarse_rigid(int n2, int nrb, const int* sub_of, const int* row_of, 
                          const double* C, const double* rigid1, int n1, double* rigid2,
                          hipStream_t st);
 void launch_copy(double* dst, const double* src, size_t n, hipStream_t st);
+void launch_pow10(size_t n, const double* theta, double* out, hipStream_t st);
+void launch_sub(size_t n, const double* a, const double* b, double* out, hipStream_t st);
 
 }  // namespace ambddc

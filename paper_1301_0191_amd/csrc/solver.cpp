@@ -105,6 +105,7 @@ struct ambddc_ctx {
   bool ready = false;
   ambddc_stats stats{};
   KTimer kt;   // optional per-class kernel timing
+  DBuf<double> coeff_buf, mis_part, mis_out;   // log10 set-up and misfit workspace
   // PCG workspace
   int pcg_cap = 0, pcg_maxit = 0;
   DBuf<double> px, pr, pz, pp, pq, pdot, ppart, pah, pbh, plz;
@@ -1297,6 +1298,38 @@ ambddc_status ambddc_setup(ambddc_handle h, const double* coeff, const double* n
     if (!h || !coeff) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (h->dof == 3 && !nu) throw Error(AMBDDC_E_INVALID_ARG, "elasticity needs nu");
     setup_impl(*h, coeff, nu);
+  }));
+}
+
+ambddc_status ambddc_setup_log10(ambddc_handle h, const double* theta, const double* nu) {
+  return ambddc_status(guard([&] {
+    if (!h || !theta) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (h->dof == 3 && !nu) throw Error(AMBDDC_E_INVALID_ARG, "elasticity needs nu");
+    if (h->coeff_buf.n != size_t(h->n_elems)) h->coeff_buf.alloc(h->n_elems);
+    launch_pow10(size_t(h->n_elems), theta, h->coeff_buf.p, h->st);
+    setup_impl(*h, h->coeff_buf.p, nu);
+  }));
+}
+
+ambddc_status ambddc_misfit(ambddc_handle h, const double* X, const double* Xobs, int32_t nrhs,
+                            double* R, double* J) {
+  return ambddc_status(guard([&] {
+    if (!h || !X || !Xobs || !R) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (h->L.empty()) throw Error(AMBDDC_E_STATE, "misfit needs a created handle");
+    if (nrhs < 1 || nrhs > 16) throw Error(AMBDDC_E_INVALID_ARG, "nrhs must be in 1..16");
+    const int n = h->L[0]->ndof;
+    launch_sub(size_t(n) * nrhs, X, Xobs, R, h->st);
+    if (J) {
+      if (h->mis_part.n < size_t(256) * 16) h->mis_part.alloc(size_t(256) * 16);
+      if (h->mis_out.n < 16) h->mis_out.alloc(16);
+      launch_dot_cols(n, nrhs, R, R, h->mis_part.p, h->mis_out.p, h->st);
+      std::vector<double> v = h->mis_out.download(h->st);
+      double s = 0.0;
+      for (int k = 0; k < nrhs; ++k) s += v[k];
+      *J = 0.5 * s;
+    } else {
+      AMB_HIP(hipStreamSynchronize(h->st));
+    }
   }));
 }
 

@@ -139,6 +139,26 @@ class Handle:
         xs = x if rhs.dim() == 2 else x.view(-1)
         return SolveResult(xs, list(its), list(cond))
 
+    def setup_log10(self, theta, nu=None, check=True):
+        """Set-up with coefficients 10^theta computed on the device."""
+        code = self._lib.ambddc_setup_log10(self._h, _dev_ptr(theta),
+                                            None if nu is None else _dev_ptr(nu))
+        if check:
+            _lib.check(code)
+        return code
+
+    def misfit(self, X, Xobs, R=None):
+        """R = X - Xobs on the device and J = 1/2 ||R||_F^2; returns (J, R)."""
+        torch = _torch()
+        X2 = X if X.dim() == 2 else X.view(1, -1)
+        O2 = Xobs if Xobs.dim() == 2 else Xobs.view(1, -1)
+        if R is None:
+            R = torch.empty_like(X2)
+        J = C.c_double()
+        _lib.check(self._lib.ambddc_misfit(self._h, _dev_ptr(X2), _dev_ptr(O2), X2.shape[0],
+                                           _dev_ptr(R), C.byref(J)))
+        return J.value, R
+
     def element_gradient(self, X, Lam):
         torch = _torch()
         X2 = X if X.dim() == 2 else X.view(1, -1)
