@@ -115,6 +115,19 @@ void GemvOp::finalize(hipStream_t st) {
 
 void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
   if (h.empty() || wgs == 0) return;
+  if (nrhs >= GEMM_FROM && nrhs <= 16) {
+    if (by_nrhs.size() < 17) by_nrhs.resize(17);
+    if (!by_nrhs[nrhs]) {
+      auto g = std::make_unique<GemmOp>();
+      g->ta = true;
+      g->narrow = true;
+      for (const auto& v : h) g->add(v.A, v.lda, v.X, v.ldx, v.Y, v.ldy, v.M, nrhs, v.K);
+      g->finalize(st);
+      by_nrhs[nrhs] = std::move(g);
+    }
+    by_nrhs[nrhs]->run(alpha, beta, st);
+    return;
+  }
   const int nd = int(h.size());
   switch (nrhs) {
 #define AMB_CASE(R) case R: k_gemv_t<R><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;

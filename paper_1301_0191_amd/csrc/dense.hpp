@@ -5,6 +5,8 @@
 //            trailing block becomes the Schur complement
 //   SymOp  : copy the lower triangle of a square block to the upper one
 #pragma once
+#include <memory>
+
 #include "common.hpp"
 
 namespace ambddc {
@@ -47,9 +49,13 @@ struct GemvDesc {
 
 class GemvOp {
  public:
+  // from this many right-hand sides on, the product runs as an MFMA GEMM
+  // (the operator is read once and the right-hand sides are staged in LDS)
+  static constexpr int GEMM_FROM = 4;
   std::vector<GemvDesc> h;
   DBuf<GemvDesc> d;
   int wgs = 0;
+  mutable std::vector<std::unique_ptr<GemmOp>> by_nrhs;   // built on first use
   void add(const double* A, int lda, int K, int M, const double* X, int ldx, double* Y, int ldy) {
     if (M <= 0) return;
     h.push_back(GemvDesc{A, lda, K, M, X, ldx, Y, ldy, 0});
