@@ -225,11 +225,12 @@ void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, 
 __global__ __launch_bounds__(256) void k_coarse(const PairDev* P, const double* Y, int m,
                                                 const double* Kp, const int* pc_s, const int* pc_t,
                                                 double* Zc, const int* active) {
-  __shared__ double yc[64 * 16];
-  __shared__ double zc[64 * 16];
+  extern __shared__ double sm[];   // yc, zc: ncp_max x m each
   if (active && !active[blockIdx.x]) return;
   const PairDev p = P[blockIdx.x];
   const int ncp = p.ncp;
+  double* yc = sm;
+  double* zc = sm + (size_t)ncp * m;
   for (int i = threadIdx.x; i < ncp * m; i += blockDim.x) yc[i] = 0.0;
   __syncthreads();
   for (int idx = threadIdx.x; idx < p.ncs * m; idx += blockDim.x) {
@@ -261,9 +262,11 @@ __global__ __launch_bounds__(256) void k_coarse(const PairDev* P, const double* 
 }
 
 void lp_coarse(const PairDev* P, int np, const double* Y, int m, const double* Kp,
-               const int* pc_s, const int* pc_t, double* Zc, const int* active, hipStream_t st) {
+               const int* pc_s, const int* pc_t, double* Zc, int ncp_max, const int* active,
+               hipStream_t st) {
   if (np == 0) return;
-  k_coarse<<<np, 256, 0, st>>>(P, Y, m, Kp, pc_s, pc_t, Zc, active);
+  const size_t sm = sizeof(double) * 2 * size_t(std::max(ncp_max, 1)) * m;
+  k_coarse<<<np, 256, sm, st>>>(P, Y, m, Kp, pc_s, pc_t, Zc, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -631,63 +634,148 @@ void lp_pair_coarse(const PairDev* P, int np, const double* kc, const int64_t* k
   AMB_LAUNCH_CHECK();
 }
 
-// Generalised inverse of the pair coarse matrix K (Section 5 uses a dense
-// eigendecomposition that drops the smallest eigenvalues).  K is first scaled
-// to unit diagonal, D^{-1/2} K D^{-1/2} = V L V^T (Jacobi, accurate for the
-// small eigenvalues of a well-scaled SPD matrix), and exactly the expected
-// null space is dropped: the nrb pair rigid modes when both subdomains
-// float, nothing otherwise.  G = D^{-1/2} V L'^{-1} V^T D^{-1/2} satisfies
-// K G K = K, which is all the preconditioner needs (its input lies in
-// range(K) and null(K) maps onto the deflated rigid modes).  nnull[p] counts
-// the scaled eigenvalues below tol * max for the Assumption 1 check.
-__global__ __launch_bounds__(1024) void k_pinv(const PairDev* P, double* Kp, double tol, int* nnull) {
-  extern __shared__ double sm[];
+// Generalised inverse of the pair coarse matrix K = Psi^T S^st Psi (Section 5
+// drops the near-null part of its eigendecomposition).  K is scaled to unit
+// diagonal, Kt = D^{-1/2} K D^{-1/2}; when both subdomains float, its null
+// space is spanned by the coarse values of the nrb pair rigid modes
+// (N = C^s, C^t applied to them), so with Nt = orthonormal basis of
+// D^{1/2} N the pseudo-inverse is Kt^+ = (Kt + Nt Nt^T)^{-1} - Nt Nt^T, and
+// G = D^{-1/2} Kt^+ D^{-1/2} satisfies K G K = K; otherwise K is
+// nonsingular (Assumption 1) and G = K^{-1}.  The inverse comes from a
+// batched signed LDL^T of [[Kt + Nt Nt^T, I], [I, 0]]: a non-positive pivot
+// means K has more null vectors than rigid modes, i.e. Assumption 1 fails.
+//
+// Step 1: Nt (ncp x nrb, stored at kp_off of Nb) for every pair with nrb > 0.
+__global__ __launch_bounds__(256) void k_pair_null(const PairDev* P, const double* C,
+                                                   const int* pc_s, const int* pc_t,
+                                                   const double* Kp, const double* rb,
+                                                   double* Nb) {
+  __shared__ double red[8];
   const PairDev p = P[blockIdx.x];
-  const int n = p.ncp;
-  const int la = n | 1;
-  double* A = sm;                 // n x n, ld la
-  double* V = A + n * la;         // n x n, ld la
-  double* work = V + n * la;
-  double* dsc = work + JAC_WORK;
-  int* perm = reinterpret_cast<int*>(dsc + n);
-  double* K = Kp + p.kp_off;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double d = K[i + i * n];
-    dsc[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-    const int r = i % n, c = i / n;
-    A[r + c * la] = 0.5 * (K[r + c * n] + K[c + r * n]) * dsc[r] * dsc[c];
-  }
-  __syncthreads();
-  jacobi_lds<32>(A, la, V, la, n, work);
-  sort_desc_lds(A, la, n, perm);
-  const double lmax = A[perm[0] + perm[0] * la];
-  const int keep = n - p.nrb;   // drop the nrb smallest
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int r = idx % n, c = idx / n;
+  if (p.nrb == 0) return;
+  const int ncp = p.ncp, n = p.nGs + p.nGt;
+  double* N = Nb + p.kp_off;
+  const double* K = Kp + p.kp_off;
+  const double* R = rb + p.rb_off;
+  for (int idx = threadIdx.x; idx < p.ncs * p.nrb; idx += blockDim.x) {
+    const int r = idx % p.ncs, j = idx / p.ncs;
     double v = 0.0;
-    for (int q = 0; q < keep; ++q) {
-      const int j = perm[q];
-      const double l = A[j + j * la];
-      if (l > 0.0) v += V[r + j * la] * V[c + j * la] / l;
-    }
-    K[idx] = v * dsc[r] * dsc[c];
+    for (int i = 0; i < p.nGs; ++i) v += C[p.cs_off + r + (int64_t)i * p.ncs] * R[i + (size_t)j * n];
+    N[pc_s[p.pcs0 + r] + (size_t)j * ncp] = v;
   }
-  if (threadIdx.x == 0) {
-    int z = 0;
-    for (int j = 0; j < n; ++j) z += !(A[j + j * la] > tol * lmax);
-    nnull[blockIdx.x] = z;
+  __syncthreads();
+  // t writes its coarse DOFs afterwards (shared ones carry the same values)
+  for (int idx = threadIdx.x; idx < p.nct * p.nrb; idx += blockDim.x) {
+    const int r = idx % p.nct, j = idx / p.nct;
+    double v = 0.0;
+    for (int i = 0; i < p.nGt; ++i)
+      v += C[p.ct_off + r + (int64_t)i * p.nct] * R[p.nGs + i + (size_t)j * n];
+    N[pc_t[p.pct0 + r] + (size_t)j * ncp] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ncp * p.nrb; idx += blockDim.x) {
+    const int i = idx % ncp;
+    const double d = K[i + (size_t)i * ncp];
+    N[idx] *= d > 0.0 ? sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  // modified Gram-Schmidt, twice
+  for (int j = 0; j < p.nrb; ++j) {
+    double* nj = N + (size_t)j * ncp;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = 0; q < j; ++q) {
+        const double* nq = N + (size_t)q * ncp;
+        double dot = 0.0;
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) dot += nq[i] * nj[i];
+        dot = block_sum(dot, red);
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) nj[i] -= dot * nq[i];
+        __syncthreads();
+      }
+    }
+    double nrm = 0.0;
+    for (int i = threadIdx.x; i < ncp; i += blockDim.x) nrm += nj[i] * nj[i];
+    nrm = block_sum(nrm, red);
+    const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+    for (int i = threadIdx.x; i < ncp; i += blockDim.x) nj[i] *= inv;
+    __syncthreads();
   }
 }
 
-void lp_pinv(const PairDev* P, int np, double* Kp, int ncp_max, double tol, int* nnull,
-             hipStream_t st) {
+// Step 2: the augmented matrices [[Kt + Nt Nt^T, I], [I, 0]] (order 2 ncp,
+// at 4 kp_off of Aug).
+__global__ __launch_bounds__(256) void k_pinv_fill(const PairDev* P, const double* Kp,
+                                                   const double* Nb, double* Aug) {
+  const PairDev p = P[blockIdx.x];
+  const int ncp = p.ncp, N2 = 2 * ncp;
+  const double* K = Kp + p.kp_off;
+  const double* Nt = Nb + p.kp_off;
+  double* A = Aug + 4 * p.kp_off;
+  for (int idx = threadIdx.x; idx < N2 * N2; idx += blockDim.x) {
+    const int i = idx % N2, k = idx / N2;
+    double v = 0.0;
+    if (i < ncp && k < ncp) {
+      const double di = K[i + (size_t)i * ncp], dk = K[k + (size_t)k * ncp];
+      const double si = di > 0.0 ? 1.0 / sqrt(di) : 1.0, sk = dk > 0.0 ? 1.0 / sqrt(dk) : 1.0;
+      v = 0.5 * (K[i + (size_t)k * ncp] + K[k + (size_t)i * ncp]) * si * sk;
+      for (int j = 0; j < p.nrb; ++j) v += Nt[i + (size_t)j * ncp] * Nt[k + (size_t)j * ncp];
+    } else if (i == k + ncp || k == i + ncp) {
+      v = 1.0;
+    }
+    A[idx] = v;
+  }
+}
+
+// Step 3 (after the factorisation, whose trailing block is -(Kt + Nt Nt^T)^{-1}):
+// G = D^{-1/2} (-T - Nt Nt^T) D^{-1/2} over K.
+__global__ __launch_bounds__(256) void k_pinv_extract(const PairDev* P, const double* Aug,
+                                                      const double* Nb, double* Kp, int* nsmall) {
+  __shared__ double sc[PAIR_COARSE_MAX];
+  __shared__ int cnt;
+  const PairDev p = P[blockIdx.x];
+  const int ncp = p.ncp, N2 = 2 * ncp;
+  double* K = Kp + p.kp_off;
+  const double* Nt = Nb + p.kp_off;
+  const double* A = Aug + 4 * p.kp_off;
+  const double* T = A + ncp + (size_t)ncp * N2;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncp; i += blockDim.x) {
+    const double d = K[i + (size_t)i * ncp];
+    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+    // the factor's diagonal holds the square roots of the pivots of the
+    // unit-diagonal matrix Kt + Nt Nt^T; a tiny pivot is a null vector
+    // beyond the rigid modes
+    const double l = A[i + (size_t)i * N2];
+    if (!(l * l > 1e-10)) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) nsmall[blockIdx.x] = cnt;
+  for (int idx = threadIdx.x; idx < ncp * ncp; idx += blockDim.x) {
+    const int i = idx % ncp, k = idx / ncp;
+    double v = -0.5 * (T[i + (size_t)k * N2] + T[k + (size_t)i * N2]);
+    for (int j = 0; j < p.nrb; ++j) v -= Nt[i + (size_t)j * ncp] * Nt[k + (size_t)j * ncp];
+    K[idx] = v * sc[i] * sc[k];
+  }
+}
+
+void lp_pair_null(const PairDev* P, int np, const double* C, const int* pc_s, const int* pc_t,
+                  const double* Kp, const double* rb, double* Nb, hipStream_t st) {
   if (np == 0) return;
-  const size_t sm = sizeof(double) * (2 * ncp_max * (ncp_max | 1) + JAC_WORK + ncp_max) +
-                    sizeof(int) * ncp_max;
-  k_pinv<<<np, 1024, sm, st>>>(P, Kp, tol, nnull);
+  k_pair_null<<<np, 256, 0, st>>>(P, C, pc_s, pc_t, Kp, rb, Nb);
+  AMB_LAUNCH_CHECK();
+}
+
+void lp_pinv_fill(const PairDev* P, int np, const double* Kp, const double* Nb, double* Aug,
+                  hipStream_t st) {
+  if (np == 0) return;
+  k_pinv_fill<<<np, 256, 0, st>>>(P, Kp, Nb, Aug);
+  AMB_LAUNCH_CHECK();
+}
+
+void lp_pinv_extract(const PairDev* P, int np, const double* Aug, const double* Nb, double* Kp,
+                     int* nsmall, hipStream_t st) {
+  if (np == 0) return;
+  k_pinv_extract<<<np, 256, 0, st>>>(P, Aug, Nb, Kp, nsmall);
   AMB_LAUNCH_CHECK();
 }
 

@@ -6,6 +6,8 @@
 
 namespace ambddc {
 
+constexpr int PAIR_COARSE_MAX = 256;   // pair coarse DOFs (LDS of the coarse correction)
+
 struct PairDev {
   int s, t, nGs, nGt;
   int64_t gs_off, gt_off;      // stacked interface offsets of s and t
@@ -52,7 +54,8 @@ void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, 
                      double* BV, const double* diagG, const int* sh_s, const int* sh_t,
                      const double* C, const DRows dr, const int* active, hipStream_t st);
 void lp_coarse(const PairDev* P, int np, const double* Y, int m, const double* Kp,
-               const int* pc_s, const int* pc_t, double* Zc, const int* active, hipStream_t st);
+               const int* pc_s, const int* pc_t, double* Zc, int ncp_max, const int* active,
+               hipStream_t st);
 void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V, const int* active,
                     hipStream_t st);
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,
@@ -64,8 +67,15 @@ void lp_commit(const PairDev* P, int np, double* V, double* AV, double* BV, cons
                int m, bool with_p, bool only_v, const int* active, hipStream_t st);
 void lp_pair_coarse(const PairDev* P, int np, const double* kc, const int64_t* kc_off,
                     const int* pc_s, const int* pc_t, double* Kp, hipStream_t st);
-void lp_pinv(const PairDev* P, int np, double* Kp, int ncp_max, double tol, int* nnull,
-             hipStream_t st);
+// Pair coarse pseudo-inverse (at most PAIR_COARSE_MAX pair coarse DOFs):
+// null-space basis, augmented matrices, and the result after the batched
+// factorisation of the augmented matrices (see lobpcg.hip).
+void lp_pair_null(const PairDev* P, int np, const double* C, const int* pc_s, const int* pc_t,
+                  const double* Kp, const double* rb, double* Nb, hipStream_t st);
+void lp_pinv_fill(const PairDev* P, int np, const double* Kp, const double* Nb, double* Aug,
+                  hipStream_t st);
+void lp_pinv_extract(const PairDev* P, int np, const double* Aug, const double* Nb, double* Kp,
+                     int* nsmall, hipStream_t st);
 void lp_rigid(const PairDev* P, int np, const double* rigid, int ndof, const int* gdof,
               double* rb, hipStream_t st);
 void lp_select(const PairDev* P, int np, const double* AV, const double* lam, int m, int nev_max,

@@ -443,7 +443,7 @@ struct PairWork {
   std::vector<PairDev> hp;
   DBuf<PairDev> dp;
   PairIdx idx;
-  DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw;
+  DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw, Nb, Aug;
   DBuf<int> active, kout, nnull;
   GemmOp gS, gM1, gM2, gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
   KTimer* kt = nullptr;
@@ -538,8 +538,9 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
     fcoff += int64_t(c.opt.nev_max) * d.nface;
     W.hp[p] = d;
   }
-  if (W.ncp_max > 60)
-    throw Error(AMBDDC_E_INVALID_ARG, "pair coarse space larger than 60 is not supported yet");
+  if (W.ncp_max > PAIR_COARSE_MAX)
+    throw Error(AMBDDC_E_INVALID_ARG, "pair coarse space larger than " +
+                                          std::to_string(PAIR_COARSE_MAX) + " is not supported");
   W.dp.upload(W.hp, st);
   W.idx.sh_s.upload(sh_s, st);
   W.idx.sh_t.upload(sh_t, st);
@@ -643,6 +644,53 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
   AMB_HIP(hipStreamSynchronize(st));
 }
 
+// Pseudo-inverses of the pair coarse matrices (see lobpcg.hip): null-space
+// basis, augmented matrices, one batched factorisation, extraction.
+void pair_pinv(ambddc_ctx& c, Level& L, PairWork& W, int li) {
+  hipStream_t st = c.st;
+  const size_t kp = W.Kp.n;
+  W.Nb.alloc(kp);
+  W.Nb.zero(st);
+  W.Aug.alloc(4 * kp);
+  lp_pair_null(W.dp.p, W.np, L.C.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Kp.p, W.rb.p, W.Nb.p, st);
+  lp_pinv_fill(W.dp.p, W.np, W.Kp.p, W.Nb.p, W.Aug.p, st);
+  LdltOp ldl;
+  SymOp sym;
+  std::vector<int> of_desc;
+  for (int p = 0; p < W.np; ++p) {
+    const int n = W.hp[p].ncp;
+    if (n == 0) continue;
+    double* A = W.Aug.p + 4 * W.hp[p].kp_off;
+    ldl.add(A, 2 * n, 2 * n, n, n);
+    sym.add(A, 2 * n, n, n);
+    of_desc.push_back(p);
+  }
+  auto fail = [&](int p, const std::string& why) {
+    return Error(AMBDDC_E_ASSUMPTION, "Assumption 1 fails on level " + std::to_string(li + 1) +
+                                          " pair (" + std::to_string(W.hp[p].s) + "," +
+                                          std::to_string(W.hp[p].t) + "): " + why);
+  };
+  if (!of_desc.empty()) {
+    ldl.finalize(st);
+    sym.finalize(st);
+    ldl.run(st);
+    const int f = ldl.failed(st);
+    if (f >= 0) throw fail(of_desc[f], "the pair coarse matrix has null vectors beyond the " +
+                                           std::to_string(W.hp[of_desc[f]].nrb) + " rigid modes");
+    sym.run(st);
+  }
+  lp_pinv_extract(W.dp.p, W.np, W.Aug.p, W.Nb.p, W.Kp.p, W.nnull.p, st);
+  const std::vector<int> small = W.nnull.download(st);
+  L.pair_nnull.assign(W.np, 0);
+  for (int p = 0; p < W.np; ++p) {
+    if (small[p] > 0)
+      throw fail(p, std::to_string(small[p]) + " near-zero pivots beyond the " +
+                        std::to_string(W.hp[p].nrb) + " rigid modes");
+    L.pair_nnull[p] = W.hp[p].nrb;
+  }
+  W.Aug.release();
+}
+
 void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
   lp_to_slab(W.dp.p, W.np, W.V.p, W.m, col, true, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
              W.active.p, st);
@@ -712,23 +760,10 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
     L.omega = 0.0;
     return;
   }
-  // pair coarse pseudo-inverses and rigid modes
+  // pair rigid modes and pair coarse pseudo-inverses
   lp_pair_coarse(W.dp.p, W.np, L.kc.p, L.d_kc_off.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Kp.p, st);
-  lp_pinv(W.dp.p, W.np, W.Kp.p, W.ncp_max, 1e-10, W.nnull.p, st);
   lp_rigid(W.dp.p, W.np, L.rigid.p, L.ndof, L.Gdof.p, W.rb.p, st);
-  {
-    std::vector<int> nn = W.nnull.download(st);
-    L.pair_nnull = nn;
-    for (int p = 0; p < W.np; ++p) {
-      const int expect = W.hp[p].nrb;
-      if (nn[p] > expect)
-        throw Error(AMBDDC_E_ASSUMPTION,
-                    "Assumption 1 fails on level " + std::to_string(li + 1) + " pair (" +
-                        std::to_string(W.hp[p].s) + "," + std::to_string(W.hp[p].t) +
-                        "): pair coarse matrix has " + std::to_string(nn[p]) +
-                        " null vectors, rigid modes " + std::to_string(expect));
-    }
-  }
+  pair_pinv(c, L, W, li);
   const int m = W.m;
   const int nconv = std::min(nev + 1, m);
   std::vector<int> ones(W.np, 1);
@@ -754,7 +789,8 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
     lp_to_slab(W.dp.p, W.np, W.V.p, m, 1, false, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
                W.active.p, st);
     W.gM1.run(1.0, 0.0, st);
-    lp_coarse(W.dp.p, W.np, W.Y.p, m, W.Kp.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Zc.p, W.active.p, st);
+    lp_coarse(W.dp.p, W.np, W.Y.p, m, W.Kp.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Zc.p, W.ncp_max,
+              W.active.p, st);
     W.gM2.run(1.0, 1.0, st);
     lp_from_slab_w(W.dp.p, W.np, W.Y.p, m, W.V.p, W.active.p, st);
     lp_project(W.dp.p, W.np, W.V.p, m, 1, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, W.active.p,
