@@ -244,6 +244,7 @@ def main():
         "solve_s": float(np.mean(solve_s)),
         "analysis_s": analysis_s,
         "pcg_iterations": res.iterations,
+        "true_residual_max": max(res.true_residual) if res.true_residual else None,
         "cond": res.cond,
         "lobpcg_iterations": st["lobpcg_iters"],
         "adaptive_constraints": st["n_adaptive"],

@@ -130,6 +130,12 @@ ambddc_status ambddc_solve(ambddc_handle h, const double* rhs_dev, int32_t nrhs,
                            int32_t maxit, double* x_dev, int32_t* iterations_host,
                            double* cond_host);
 
+/* True relative residuals ||f_k - K x_k||_2 / ||f_k||_2 of the last
+ * ambddc_solve (recomputed with one product by K after the iteration, which
+ * itself tracks only the recursively updated residual): res_host[nrhs], host.
+ * Errors: E_STATE if nrhs differs from the last solve's. */
+ambddc_status ambddc_last_residual(ambddc_handle h, int32_t nrhs, double* res_host);
+
 /* Numeric set-up from element log10-coefficients: coeff_e = 10^theta_e is
  * computed on the device, then as ambddc_setup.  theta_dev: device
  * [n_elems]; nu_dev as in ambddc_setup.  Same errors as ambddc_setup. */

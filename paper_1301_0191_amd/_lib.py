@@ -84,6 +84,7 @@ _SIGS = {
     "ambddc_get_coarse_element": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                             C.POINTER(C.c_int32)]),
     "ambddc_get_top_coarse": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "ambddc_last_residual": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "ambddc_setup_log10": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ambddc_misfit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                 C.POINTER(C.c_double)]),

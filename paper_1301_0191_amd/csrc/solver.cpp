@@ -105,6 +105,7 @@ struct ambddc_ctx {
   bool ready = false;
   ambddc_stats stats{};
   KTimer kt;   // optional per-class kernel timing
+  std::vector<double> last_res;   // true relative residuals of the last solve
   DBuf<double> coeff_buf, mis_part, mis_out;   // log10 set-up and misfit workspace
   // PCG workspace
   int pcg_cap = 0, pcg_maxit = 0;
@@ -1128,6 +1129,16 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
     launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rzn, st);
     launch_pcg_update_p(n, nrhs, rzn, rz, c.pact.p, c.pp.p, c.pz.p, c.pbh.p, it, c.pcg_maxit, st);
   }
+  // true residual of every column, ||f - K x|| / ||f|| (the recursion above
+  // only tracks the updated residual)
+  launch_spmv(c.csr, c.csr_vals.p, x, c.pq.p, nrhs, st);
+  launch_sub(size_t(n) * nrhs, f, c.pq.p, c.pq.p, st);
+  launch_dot_cols(n, nrhs, c.pq.p, c.pq.p, c.ppart.p, rr, st);
+  AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  AMB_HIP(hipStreamSynchronize(st));
+  c.last_res.assign(nrhs, 0.0);
+  for (int k = 0; k < nrhs; ++k)
+    c.last_res[k] = hff[k] > 0.0 ? std::sqrt(hrr[k] / hff[k]) : 0.0;
   if (cond) {
     c.pnal.upload(nal, st);
     launch_lanczos_cond(nrhs, c.pnal.p, c.pah.p, c.pbh.p, c.pcg_maxit, c.plz.p, st);
@@ -1396,6 +1407,16 @@ ambddc_status ambddc_element_gradient(ambddc_handle h, const double* X, const do
     launch_element_gradient(h->n_elems, 8 * h->dof, h->L[0]->ndof, nrhs, h->edofs.p, h->Ke.p, X, Lam,
                             grad, h->st);
     AMB_HIP(hipStreamSynchronize(h->st));
+  }));
+}
+
+ambddc_status ambddc_last_residual(ambddc_handle h, int32_t nrhs, double* res) {
+  return ambddc_status(guard([&] {
+    if (!h || !res) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (nrhs != int(h->last_res.size()))
+      throw Error(AMBDDC_E_STATE, "nrhs differs from the last solve (" +
+                                      std::to_string(h->last_res.size()) + ")");
+    std::copy(h->last_res.begin(), h->last_res.end(), res);
   }));
 }
 

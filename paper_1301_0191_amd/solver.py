@@ -56,6 +56,7 @@ class SolveResult:
     x: object
     iterations: list
     cond: list
+    true_residual: list = None   # ||f - K x|| / ||f|| per column, recomputed after PCG
 
 
 class Handle:
@@ -137,7 +138,11 @@ class Handle:
         if code != 0 and (raise_on_noconv or code != 4):
             _lib.check(code)
         xs = x if rhs.dim() == 2 else x.view(-1)
-        return SolveResult(xs, list(its), list(cond))
+        res = (C.c_double * nrhs)()
+        tr = None
+        if self._lib.ambddc_last_residual(self._h, nrhs, res) == 0:
+            tr = list(res)
+        return SolveResult(xs, list(its), list(cond), tr)
 
     def setup_log10(self, theta, nu=None, check=True):
         """Set-up with coefficients 10^theta computed on the device."""
