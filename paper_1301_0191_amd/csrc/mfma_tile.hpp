@@ -2,7 +2,9 @@
 // CDNA MFMA (v_mfma_f64_16x16x4f64), FP64.  256 threads = 4 waves arranged
 // WM x WN; every wave owns a 32x32 sub-tile (2x2 MFMA blocks).  K is staged
 // through LDS in chunks of KC so that global reads are coalesced for either
-// operand orientation.
+// operand orientation; the staging is double-buffered: the next chunk is
+// loaded into registers while the current one feeds the MFMAs, then stored
+// to the other LDS buffer, with one barrier per chunk.
 //
 // MFMA 16x16x4 operand layout (per wave of 64 lanes):
 //   A (16x4):  lane l holds A[l % 16][l / 16]
@@ -25,8 +27,8 @@ struct TileShape {
 
 template <int WM, int WN>
 struct TileSmem {
-  double As[TileShape<WM, WN>::KC][TileShape<WM, WN>::TM + TileShape<WM, WN>::PAD];
-  double Bs[TileShape<WM, WN>::KC][TileShape<WM, WN>::TN + TileShape<WM, WN>::PAD];
+  double As[2][TileShape<WM, WN>::KC][TileShape<WM, WN>::TM + TileShape<WM, WN>::PAD];
+  double Bs[2][TileShape<WM, WN>::KC][TileShape<WM, WN>::TN + TileShape<WM, WN>::PAD];
 };
 
 // op(A)(m, k) = TA ? A[k + m*lda] : A[m + k*lda]
@@ -39,6 +41,7 @@ __device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int lda,
                                           double beta, int sign_split, TileSmem<WM, WN>& sm) {
   using S = TileShape<WM, WN>;
   constexpr int TM = S::TM, TN = S::TN, KC = S::KC;
+  constexpr int NA = KC * TM / 256, NB = KC * TN / 256;   // staged values per thread
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -48,11 +51,12 @@ __device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int lda,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    // stage op(A)[m0:m0+TM, k0:k0+KC] as As[k][m]
+  double ra[NA], rb[NB];
+  // global -> registers for the chunk starting at k0
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int idx = tid; idx < KC * TM; idx += 256) {
+    for (int u = 0; u < NA; ++u) {
+      const int idx = tid + u * 256;
       int m, k;
       if (!TA) { m = idx % TM; k = idx / TM; }
       else { k = idx % KC; m = idx / KC; }
@@ -60,34 +64,63 @@ __device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int lda,
       double v = 0.0;
       if (gm < M && gk < K) v = TA ? A[gk + (size_t)gm * lda] : A[gm + (size_t)gk * lda];
       if (sign_split >= 0 && gk >= sign_split) v = -v;
-      sm.As[k][m] = v;
+      ra[u] = v;
     }
 #pragma unroll
-    for (int idx = tid; idx < KC * TN; idx += 256) {
+    for (int u = 0; u < NB; ++u) {
+      const int idx = tid + u * 256;
       int n, k;
       if (TB) { n = idx % TN; k = idx / TN; }
       else { k = idx % KC; n = idx / KC; }
       const int gn = n0 + n, gk = k0 + k;
-      double v = 0.0;
-      if (gn < N && gk < K) v = TB ? B[gn + (size_t)gk * ldb] : B[gk + (size_t)gn * ldb];
-      sm.Bs[k][n] = v;
+      rb[u] = (gn < N && gk < K) ? (TB ? B[gn + (size_t)gk * ldb] : B[gk + (size_t)gn * ldb]) : 0.0;
     }
-    __syncthreads();
+  };
+  // registers -> LDS buffer
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int idx = tid + u * 256;
+      int m, k;
+      if (!TA) { m = idx % TM; k = idx / TM; }
+      else { k = idx % KC; m = idx / KC; }
+      sm.As[buf][k][m] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int idx = tid + u * 256;
+      int n, k;
+      if (TB) { n = idx % TN; k = idx / TN; }
+      else { k = idx % KC; n = idx / KC; }
+      sm.Bs[buf][k][n] = rb[u];
+    }
+  };
+  if (K > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    const bool more = k0 + KC < K;
+    if (more) gload(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int kr = kk + (lane >> 4);
       double a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = sm.As[kr][wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = sm.As[buf][kr][wm * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = sm.Bs[kr][wn * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = sm.Bs[buf][kr][wn * 32 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) sstore(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
