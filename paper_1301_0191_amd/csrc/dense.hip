@@ -230,10 +230,36 @@ __global__ __launch_bounds__(256) void k_ldlt_panel(const LdltDesc* __restrict__
     if (j < kb) g.A[row + (size_t)(k0 + j) * g.lda] = x[j];
 }
 
-// Trailing update: A_ij -= L_i D L_j^T on lower tiles of the trailing block.
+// Update of the rest of the outer block after the inner step at k0:
+// A[r, c] -= sum_p L[r, p] sigma_p L[c, p] (p = panel columns k0..k0+kb) for
+// columns c in [k0+kb, c1), c1 = end of the outer block, rows r >= c.
+__global__ __launch_bounds__(256) void k_ldlt_strip(const LdltDesc* __restrict__ d,
+                                                    const int* __restrict__ act,
+                                                    const int* __restrict__ pre, int nact, int k0,
+                                                    int outer) {
+  __shared__ TileSmem<2, 2> sm;
+  const int a = find_active(pre, nact, blockIdx.x);
+  const LdltDesc g = d[act[a]];
+  int l = blockIdx.x - pre[a];
+  const int kb = min(LdltOp::NB, g.p - k0);
+  const int r0 = k0 + kb;
+  const int c1 = min(outer + LdltOp::OB, g.p);
+  const int nrt = (g.N - r0 + LdltOp::TILE - 1) / LdltOp::TILE;
+  int tc = 0;
+  while (l >= nrt - tc) { l -= nrt - tc; ++tc; }
+  const int tr = tc + l;
+  const double* P = g.A + (size_t)k0 * g.lda;
+  mfma_tile<false, true, 2, 2>(P, g.lda, P, g.lda, g.A, g.lda, g.N, c1, kb, r0 + tr * LdltOp::TILE,
+                               r0 + tc * LdltOp::TILE, -1.0, 1.0, max(g.q - k0, 0), sm);
+}
+
+// Trailing update after the outer block starting at `outer`: lower tiles of
+// A[c1:, c1:] -= L D L^T over the block's columns outer..c1.  Panel column p
+// is a negative pivot when outer + p >= q (clamped: all negative when q <= outer).
 __global__ __launch_bounds__(256) void k_ldlt_update(const LdltDesc* __restrict__ d,
                                                      const int* __restrict__ act,
-                                                     const int* __restrict__ pre, int nact, int k0) {
+                                                     const int* __restrict__ pre, int nact,
+                                                     int outer) {
   __shared__ TileSmem<2, 2> sm;
   const int a = find_active(pre, nact, blockIdx.x);
   const LdltDesc g = d[act[a]];
@@ -242,46 +268,55 @@ __global__ __launch_bounds__(256) void k_ldlt_update(const LdltDesc* __restrict_
   while ((ti2 + 1) * (ti2 + 2) / 2 <= l) ++ti2;
   while (ti2 * (ti2 + 1) / 2 > l) --ti2;
   const int tj = l - ti2 * (ti2 + 1) / 2;
-  const int kb = min(LdltOp::NB, g.p - k0);
-  const int r0 = k0 + kb;
-  const int m0 = r0 + ti2 * LdltOp::TILE, n0 = r0 + tj * LdltOp::TILE;
-  const double* P = g.A + (size_t)k0 * g.lda;   // panel columns
-  // C[m0.., n0..] -= sum_p P[m, p] sigma_p P[n, p]
-  // panel column p is a negative pivot when k0 + p >= q (clamped: all negative when q <= k0)
-  mfma_tile<false, true, 2, 2>(P, g.lda, P, g.lda, g.A, g.lda, g.N, g.N, kb, m0, n0, -1.0, 1.0,
-                               max(g.q - k0, 0), sm);
+  const int c1 = min(outer + LdltOp::OB, g.p);
+  const int m0 = c1 + ti2 * LdltOp::TILE, n0 = c1 + tj * LdltOp::TILE;
+  const double* P = g.A + (size_t)outer * g.lda;
+  mfma_tile<false, true, 2, 2>(P, g.lda, P, g.lda, g.A, g.lda, g.N, g.N, c1 - outer, m0, n0, -1.0,
+                               1.0, max(g.q - outer, 0), sm);
 }
 
 void LdltOp::finalize(hipStream_t st) {
   int maxp = 0;
   for (auto& g : h) maxp = std::max(maxp, g.p);
-  steps = (maxp + NB - 1) / NB;
-  std::vector<int> a, pp, up;
-  step_off.assign(steps + 1, 0);
-  pan_total.assign(steps, 0);
-  upd_total.assign(steps, 0);
-  nact.assign(steps, 0);
-  std::vector<int> pp_all, up_all;
-  for (int s = 0; s < steps; ++s) {
-    const int k0 = s * NB;
-    int ptot = 0, utot = 0, na = 0;
+  ph.clear();
+  std::vector<int> a, pp_all, up_all;
+  for (int outer = 0; outer < maxp; outer += OB) {
+    for (int k0 = outer; k0 < std::min(outer + OB, maxp); k0 += NB) {
+      Phase f{0, k0, outer, int(a.size()), 0, 0, 0};
+      for (size_t i = 0; i < h.size(); ++i) {
+        const auto& g = h[i];
+        if (g.p <= k0) continue;
+        const int kb = std::min(NB, g.p - k0);
+        const int rows = g.N - k0 - kb;
+        const int c1 = std::min(outer + OB, g.p);
+        const int w = c1 - (k0 + kb);
+        a.push_back(int(i));
+        pp_all.push_back(f.pan_total);
+        up_all.push_back(f.upd_total);
+        f.pan_total += rows > 0 ? ceil_div(rows, ROWS) : 0;
+        if (w > 0 && rows > 0) {
+          const int nct = ceil_div(w, TILE), nrt = ceil_div(rows, TILE);
+          f.upd_total += nct * nrt - nct * (nct - 1) / 2;
+        }
+        ++f.nact;
+      }
+      ph.push_back(f);
+    }
+    Phase f{1, outer, outer, int(a.size()), 0, 0, 0};
     for (size_t i = 0; i < h.size(); ++i) {
       const auto& g = h[i];
-      if (g.p <= k0) continue;
-      const int kb = std::min(NB, g.p - k0);
-      const int rows = g.N - k0 - kb;
+      if (g.p <= outer) continue;
+      const int c1 = std::min(outer + OB, g.p);
+      const int rows = g.N - c1;
+      if (rows <= 0) continue;
       a.push_back(int(i));
-      pp_all.push_back(ptot);
-      up_all.push_back(utot);
-      ptot += rows > 0 ? ceil_div(rows, ROWS) : 0;
-      const int nt = rows > 0 ? ceil_div(rows, TILE) : 0;
-      utot += nt * (nt + 1) / 2;
-      ++na;
+      pp_all.push_back(0);
+      up_all.push_back(f.upd_total);
+      const int nt = ceil_div(rows, TILE);
+      f.upd_total += nt * (nt + 1) / 2;
+      ++f.nact;
     }
-    step_off[s + 1] = step_off[s] + na;
-    pan_total[s] = ptot;
-    upd_total[s] = utot;
-    nact[s] = na;
+    ph.push_back(f);
   }
   d.upload(h, st);
   act.upload(a, st);
@@ -294,15 +329,20 @@ void LdltOp::finalize(hipStream_t st) {
 void LdltOp::run(hipStream_t st) {
   if (h.empty()) return;
   info.zero(st);
-  for (int s = 0; s < steps; ++s) {
-    const int k0 = s * NB;
-    const int off = step_off[s];
-    if (nact[s] == 0) continue;
-    k_ldlt_diag<<<nact[s], 256, 0, st>>>(d.p, act.p + off, k0, info.p);
-    if (pan_total[s] > 0)
-      k_ldlt_panel<<<pan_total[s], 256, 0, st>>>(d.p, act.p + off, pan_pre.p + off, nact[s], k0);
-    if (upd_total[s] > 0)
-      k_ldlt_update<<<upd_total[s], 256, 0, st>>>(d.p, act.p + off, upd_pre.p + off, nact[s], k0);
+  for (const Phase& f : ph) {
+    if (f.nact == 0) continue;
+    if (!f.big) {
+      k_ldlt_diag<<<f.nact, 256, 0, st>>>(d.p, act.p + f.off, f.k0, info.p);
+      if (f.pan_total > 0)
+        k_ldlt_panel<<<f.pan_total, 256, 0, st>>>(d.p, act.p + f.off, pan_pre.p + f.off, f.nact,
+                                                  f.k0);
+      if (f.upd_total > 0)
+        k_ldlt_strip<<<f.upd_total, 256, 0, st>>>(d.p, act.p + f.off, upd_pre.p + f.off, f.nact,
+                                                  f.k0, f.outer);
+    } else if (f.upd_total > 0) {
+      k_ldlt_update<<<f.upd_total, 256, 0, st>>>(d.p, act.p + f.off, upd_pre.p + f.off, f.nact,
+                                                 f.outer);
+    }
   }
   AMB_LAUNCH_CHECK();
 }

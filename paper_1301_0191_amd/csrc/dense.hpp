@@ -74,16 +74,22 @@ struct LdltDesc {
 class LdltOp {
  public:
   static constexpr int NB = 32;     // panel width
+  static constexpr int OB = 128;    // outer block: columns per full trailing update
   static constexpr int TILE = 64;   // trailing update tile
   static constexpr int ROWS = 256;  // panel rows per workgroup
   std::vector<LdltDesc> h;
   DBuf<LdltDesc> d;
-  // per step: active matrices with work prefix (panel chunks / update tiles)
-  std::vector<int> step_off;        // into lists, size steps+1
-  DBuf<int> act, pan_pre, upd_pre;  // matrix ids, prefix sums
-  std::vector<int> pan_total, upd_total, nact;
+  // Phases in order: for every outer block of OB columns, its NB-wide inner
+  // steps (diagonal block, panel, update of the rest of the outer block),
+  // then one update of the whole trailing matrix with the OB panel columns.
+  struct Phase {
+    int big;       // 0: inner step at column k0; 1: trailing update of the block at k0
+    int k0, outer; // k0 and the outer block's first column
+    int off, nact, pan_total, upd_total;
+  };
+  std::vector<Phase> ph;
+  DBuf<int> act, pan_pre, upd_pre;  // per phase: matrix ids, prefix sums of work items
   DBuf<int> info;                   // first failing matrix + 1 (0 = ok)
-  int steps = 0;
   void add(double* A, int lda, int N, int p, int q) { h.push_back(LdltDesc{A, lda, N, p, q}); }
   void finalize(hipStream_t st);
   void run(hipStream_t st);
