@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1],
+                    help="mode of the timed headline steps: 0 = FP64 throughout, 1 = the PCG "
+                         "preconditioner's dense subdomain operators stored in FP32")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the steps in the other precision mode")
     ap.add_argument("--cpu-pairs", type=int, default=0,
                     help="pair eigenproblems the oracle solves for a sampled CPU baseline "
                          "(0 = run the whole method in the oracle)")
@@ -159,17 +164,10 @@ def main():
 
     dev = torch.device("cuda:0")
     prob = W.CONFIGS[args.config](args.seed)
-    t0 = time.perf_counter()
-    h = Handle.from_problem(prob)
-    analysis_s = time.perf_counter() - t0
     coeff = torch.from_numpy(prob.coeff).to(dev)
     nu = None if prob.nu is None else torch.from_numpy(prob.nu).to(dev)
     rhs = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to(dev)
     x = torch.empty_like(rhs)
-
-    def step():
-        h.setup(coeff, nu)
-        return h.solve(rhs, rtol=args.rtol, maxit=2000, x=x)
 
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -179,33 +177,58 @@ def main():
         torch.cuda.synchronize()
         print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr)
         del src, dst
-    for i in range(args.warmup):
-        step()
-        print(f"warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    h.timing_enable(TIMED)
-    setup_s, solve_s = [], []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        res = step()
+
+    def run(precision):
+        """Warm-up and timed steps with one handle; returns the measurements."""
+        t0 = time.perf_counter()
+        h = Handle.from_problem(prob, precision=precision)
+        analysis_s = time.perf_counter() - t0
+
+        def step():
+            h.setup(coeff, nu)
+            return h.solve(rhs, rtol=args.rtol, maxit=2000, x=x)
+
+        for i in range(args.warmup):
+            step()
+            print(f"precision {precision}: warmup step {i + 1}/{args.warmup} done",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        h.timing_enable(TIMED)
+        setup_s, solve_s = [], []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            res = step()
+            st = h.stats()
+            setup_s.append(st["t_phase"][6])
+            solve_s.append(st["t_phase"][7])
+            print(f"precision {precision}: step {i + 1}/{args.steps} done", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        timed = {c: h.timing_read(c) for c in TIMED}
+        h.timing_enable(None)
         st = h.stats()
-        setup_s.append(st["t_phase"][6])
-        solve_s.append(st["t_phase"][7])
-        print(f"step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    timed = {c: h.timing_read(c) for c in TIMED}
-    h.timing_enable(None)
-    kernels = {}
-    for c, t in timed.items():
-        if t["launches"] == 0 or t["ms"] <= 0:
-            continue
-        sec = t["ms"] * 1e-3
-        kernels[c] = {"launches": t["launches"], "avg_launch_us": 1e3 * t["ms"] / t["launches"],
-                      "share_of_step": sec / T,
-                      "alg_flops_per_launch": t["flops"] / t["launches"],
-                      "alg_bytes_per_launch": t["bytes"] / t["launches"],
-                      "tflops": t["flops"] / sec / 1e12, "gbps": t["bytes"] / sec / 1e9}
+        h.close()
+        return dict(T=T, res=res, st=st, timed=timed, setup_s=setup_s, solve_s=solve_s,
+                    analysis_s=analysis_s)
+
+    def kernel_table(m):
+        kernels = {}
+        for c, t in m["timed"].items():
+            if t["launches"] == 0 or t["ms"] <= 0:
+                continue
+            sec = t["ms"] * 1e-3
+            kernels[c] = {"launches": t["launches"], "avg_launch_us": 1e3 * t["ms"] / t["launches"],
+                          "share_of_step": sec / m["T"],
+                          "alg_flops_per_launch": t["flops"] / t["launches"],
+                          "alg_bytes_per_launch": t["bytes"] / t["launches"],
+                          "tflops": t["flops"] / sec / 1e12, "gbps": t["bytes"] / sec / 1e9}
+        return kernels
+
+    main_m = run(args.precision)
+    other_m = run(1 - args.precision) if not args.no_compare else None
+    timed, T, res, st = main_m["timed"], main_m["T"], main_m["res"], main_m["st"]
+    kernels = kernel_table(main_m)
     dom = max((c for c in SINGLE_KERNEL if c in kernels), key=lambda c: timed[c]["ms"],
               default=None)
     roofline = None
@@ -219,10 +242,28 @@ def main():
                     "launches": t["launches"], "avg_launch_us": 1e3 * t["ms"] / t["launches"],
                     "alg_flops_per_launch": t["flops"] / t["launches"],
                     "alg_bytes_per_launch": t["bytes"] / t["launches"]}
-    st = h.stats()
     ms = 1e3 * T / args.steps
     n_pairs = sum(st["n_pairs"])
     lob = st["t_phase"][2]
+
+    def mode_summary(m):
+        k = kernel_table(m)
+        r = m["res"]
+        return {"ms_per_step": 1e3 * m["T"] / args.steps,
+                "setup_s": float(np.mean(m["setup_s"])), "solve_s": float(np.mean(m["solve_s"])),
+                "pcg_iterations": r.iterations,
+                "true_residual_max": max(r.true_residual) if r.true_residual else None,
+                "adaptive_constraints": m["st"]["n_adaptive"],
+                "lobpcg_iterations": m["st"]["lobpcg_iters"],
+                "bddc_apply": {kk: k["bddc_apply"][kk] for kk in ("avg_launch_us", "gbps")}
+                if "bddc_apply" in k else None}
+
+    modes = None
+    if other_m is not None:
+        by_p = {args.precision: main_m, 1 - args.precision: other_m}
+        modes = {"fp64": mode_summary(by_p[0]), "fp32_stored_preconditioners": mode_summary(by_p[1])}
+        modes["speedup_fp32_stored_vs_fp64"] = (modes["fp64"]["ms_per_step"]
+                                                / modes["fp32_stored_preconditioners"]["ms_per_step"])
     out = {
         "metric": METRIC,
         "value": T / args.steps,
@@ -234,15 +275,15 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f64 (preconditioner operators stored f32)",
         "data": "synthetic",
         "config": {"workload": prob.name, "n_free": st["n_free"], "subdomains": st["n_sub"],
                    "pairs": st["n_pairs"], "levels": prob.levels, "tau": prob.tau,
-                   "nrhs": int(rhs.shape[0]), "rtol": args.rtol},
+                   "nrhs": int(rhs.shape[0]), "rtol": args.rtol, "precision": args.precision},
         "pair_eigenproblems_per_s": n_pairs / lob if lob > 0 else None,
-        "setup_s": float(np.mean(setup_s)),
-        "solve_s": float(np.mean(solve_s)),
-        "analysis_s": analysis_s,
+        "setup_s": float(np.mean(main_m["setup_s"])),
+        "solve_s": float(np.mean(main_m["solve_s"])),
+        "analysis_s": main_m["analysis_s"],
         "pcg_iterations": res.iterations,
         "true_residual_max": max(res.true_residual) if res.true_residual else None,
         "cond": res.cond,
@@ -254,8 +295,8 @@ def main():
                     "coarse": st["t_phase"][5]},
         "roofline": roofline,
         "kernels": kernels,
+        "precision_modes": modes,
     }
-    h.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_pairs, args.rtol)
     print(json.dumps(out), flush=True)

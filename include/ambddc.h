@@ -78,7 +78,15 @@ typedef struct {
   int32_t lobpcg_maxit;        /* LOBPCG iteration cap (e.g. 100) */
   int32_t lobpcg_block;        /* LOBPCG block size m >= nev_max+1 (e.g. 16) */
   double lobpcg_tol;           /* relative residual tolerance (e.g. 1e-8) */
-  int32_t precision;           /* 0 = FP64 everywhere (only value accepted so far) */
+  int32_t precision;           /* 0 = FP64 everywhere; 1 = the dense subdomain
+                                  operators of the PCG preconditioner (Alg. 1 on
+                                  every substructured level) stored in FP32 and
+                                  widened to FP64 on load.  Everything else (Schur
+                                  complements, the whole adaptive set-up, the
+                                  coarsest problem, PCG vectors and residuals) stays
+                                  FP64, so PCG, which iterates on FP64 residuals,
+                                  reaches the same FP64 accuracy; only iteration
+                                  counts can change. */
   int32_t face_averages;       /* 1 = add face averages to the initial constraints (c+e+f) */
   uint64_t seed;               /* LOBPCG start vectors */
   void* stream;                /* hipStream_t for all work (NULL = default stream) */
@@ -240,8 +248,9 @@ ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc_host, int32_t* n
  *   "bddc_apply"   one application of the multilevel preconditioner
  *                  (Alg. 1, all levels): the dense operators it reads, per
  *                  subdomain nI^2 + 2 nI nG + nG^2 + 2 nG nc entries, plus
- *                  the n_top^2 coarsest inverse; bytes 8 x entries + 8 x 6
- *                  vector entries per DOF and right-hand side, flops
+ *                  the n_top^2 coarsest inverse; bytes 8 x entries (4 x the
+ *                  subdomain entries with precision 1) + 8 x 6 vector
+ *                  entries per DOF and right-hand side, flops
  *                  2 x entries x nrhs.
  * ambddc_timing_read returns, for one class, the launches, the summed event
  * time in milliseconds and the summed algorithmic flops and bytes since the

@@ -13,7 +13,7 @@ __device__ __forceinline__ int ceil_div_dev(int a, int b) { return (a + b - 1) /
 // GEMM
 // --------------------------------------------------------------------------
 
-template <bool TA, bool TB, int WM, int WN>
+template <bool TA, bool TB, int WM, int WN, typename TAe>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, int nd, double alpha,
                                               double beta) {
   __shared__ TileSmem<WM, WN> sm;
@@ -27,9 +27,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, in
   if (g.flag && *g.flag == 0) return;
   const int lt = tile - g.tile_start;
   const int tm = lt % g.tiles_m, tn = lt / g.tiles_m;
-  mfma_tile<TA, TB, WM, WN>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N, g.K,
-                            tm * TileShape<WM, WN>::TM, tn * TileShape<WM, WN>::TN, alpha, beta,
-                            -1, sm);
+  mfma_tile<TA, TB, WM, WN>(static_cast<const TAe*>(g.A), g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N,
+                            g.K, tm * TileShape<WM, WN>::TM, tn * TileShape<WM, WN>::TN, alpha,
+                            beta, -1, sm);
 }
 
 void GemmOp::finalize(hipStream_t st) {
@@ -44,28 +44,98 @@ void GemmOp::finalize(hipStream_t st) {
   AMB_HIP(hipStreamSynchronize(st));
 }
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, typename TAe>
 static void gemm_dispatch(const GemmOp& op, double alpha, double beta, hipStream_t st) {
   if (op.narrow)
-    k_gemm<TA, TB, 4, 1><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+    k_gemm<TA, TB, 4, 1, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
   else
-    k_gemm<TA, TB, 2, 2><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+    k_gemm<TA, TB, 2, 2, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+}
+
+template <typename TAe>
+static void gemm_run(const GemmOp& op, double alpha, double beta, hipStream_t st) {
+  if (!op.ta && !op.tb) gemm_dispatch<false, false, TAe>(op, alpha, beta, st);
+  else if (op.ta && !op.tb) gemm_dispatch<true, false, TAe>(op, alpha, beta, st);
+  else if (!op.ta && op.tb) gemm_dispatch<false, true, TAe>(op, alpha, beta, st);
+  else gemm_dispatch<true, true, TAe>(op, alpha, beta, st);
 }
 
 void GemmOp::run(double alpha, double beta, hipStream_t st) const {
   if (h.empty() || tiles == 0) return;
-  if (!ta && !tb) gemm_dispatch<false, false>(*this, alpha, beta, st);
-  else if (ta && !tb) gemm_dispatch<true, false>(*this, alpha, beta, st);
-  else if (!ta && tb) gemm_dispatch<false, true>(*this, alpha, beta, st);
-  else gemm_dispatch<true, true>(*this, alpha, beta, st);
+  if (a32) gemm_run<float>(*this, alpha, beta, st);
+  else gemm_run<double>(*this, alpha, beta, st);
   AMB_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
+// FP32 operand copies: one workgroup row per block, columns strided over x
+// --------------------------------------------------------------------------
+
+struct PackDesc {
+  const double* src;
+  int64_t lds;
+  int rows, cols;
+  float* dst;
+  int64_t ldd;
+};
+
+__global__ __launch_bounds__(256) void k_pack_f32(const PackDesc* __restrict__ d) {
+  const PackDesc g = d[blockIdx.y];
+  for (int j = blockIdx.x; j < g.cols; j += gridDim.x) {
+    const double* s = g.src + (size_t)j * g.lds;
+    float* t = g.dst + (size_t)j * g.ldd;
+    for (int i = threadIdx.x; i < g.rows; i += blockDim.x) t[i] = static_cast<float>(s[i]);
+    // zero the padding rows so that vector loads read defined values
+    for (int i = g.rows + threadIdx.x; i < g.ldd; i += blockDim.x) t[i] = 0.0f;
+  }
+}
+
+// Packs every (rows x cols, leading dimension lds) FP64 block into `store`
+// with leading dimension rows rounded up to 4; returns the packed pointers
+// and leading dimensions in pd[].dst / pd[].ldd.
+static void pack_blocks(std::vector<PackDesc>& pd, DBuf<float>& store, hipStream_t st) {
+  int64_t total = 0;
+  int maxc = 1;
+  for (auto& p : pd) {
+    p.ldd = (p.rows + 3) / 4 * 4;
+    total += p.ldd * int64_t(p.cols);
+    maxc = std::max(maxc, p.cols);
+  }
+  store.alloc(size_t(std::max<int64_t>(total, 4)));
+  int64_t off = 0;
+  for (auto& p : pd) {
+    p.dst = store.p + off;
+    off += p.ldd * int64_t(p.cols);
+  }
+  if (pd.empty()) return;
+  if (pd.size() > 65535) throw Error(1, "pack_a_f32: too many blocks");
+  DBuf<PackDesc> dd;
+  dd.upload(pd, st);
+  k_pack_f32<<<dim3(std::min(maxc, 1024), unsigned(pd.size())), 256, 0, st>>>(dd.p);
+  AMB_LAUNCH_CHECK();
+  AMB_HIP(hipStreamSynchronize(st));
+}
+
+void GemmOp::pack_a_f32(DBuf<float>& store, hipStream_t st) {
+  if (a32) throw Error(1, "GemmOp::pack_a_f32 called twice");
+  std::vector<PackDesc> pd;
+  for (const auto& g : h) {
+    const int rows = ta ? g.K : g.M, cols = ta ? g.M : g.K;
+    pd.push_back(PackDesc{static_cast<const double*>(g.A), g.lda, rows, cols, nullptr, 0});
+  }
+  pack_blocks(pd, store, st);
+  for (size_t i = 0; i < h.size(); ++i) {
+    h[i].A = pd[i].dst;
+    h[i].lda = int(pd[i].ldd);
+  }
+  a32 = true;
 }
 
 // --------------------------------------------------------------------------
 // GEMV (transposed, several right-hand sides): one wave per output column
 // --------------------------------------------------------------------------
 
-template <int R>
+template <int R, typename T>
 __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, int nd, double alpha,
                                                 double beta) {
   const int wg = blockIdx.x;
@@ -78,14 +148,31 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
   const int col = (wg - g.wg_start) * 4 + (threadIdx.x >> 6);
   if (col >= g.M) return;
   const int lane = threadIdx.x & 63;
-  const double* a = g.A + (size_t)col * g.lda;
+  const T* a = static_cast<const T*>(g.A) + (size_t)col * g.lda;
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  for (int i = lane; i < g.K; i += 64) {
-    const double av = a[i];
+  if constexpr (sizeof(T) == 4) {
+    // packed FP32 columns: 16-byte aligned, padded with zeros to a multiple of 4
+    for (int i0 = 4 * lane; i0 < g.K; i0 += 256) {
+      const float4 av = *reinterpret_cast<const float4*>(a + i0);
+      const float as[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u;
+        if (i < g.K) {
+          const double w = as[u];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] += w * g.X[i + (size_t)r * g.ldx];
+        }
+      }
+    }
+  } else {
+    for (int i = lane; i < g.K; i += 64) {
+      const double av = a[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
+    }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -101,6 +188,20 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
     double* y = g.Y + col + (size_t)lane * g.ldy;
     *y = alpha * v + (beta != 0.0 ? beta * (*y) : 0.0);
   }
+}
+
+void GemvOp::pack_a_f32(DBuf<float>& store, hipStream_t st) {
+  if (a32) throw Error(1, "GemvOp::pack_a_f32 called twice");
+  if (!by_nrhs.empty()) throw Error(1, "GemvOp::pack_a_f32 after run");
+  std::vector<PackDesc> pd;
+  for (const auto& g : h)
+    pd.push_back(PackDesc{static_cast<const double*>(g.A), g.lda, g.K, g.M, nullptr, 0});
+  pack_blocks(pd, store, st);
+  for (size_t i = 0; i < h.size(); ++i) {
+    h[i].A = pd[i].dst;
+    h[i].lda = int(pd[i].ldd);
+  }
+  a32 = true;
 }
 
 void GemvOp::finalize(hipStream_t st) {
@@ -121,7 +222,9 @@ void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
       auto g = std::make_unique<GemmOp>();
       g->ta = true;
       g->narrow = true;
-      for (const auto& v : h) g->add(v.A, v.lda, v.X, v.ldx, v.Y, v.ldy, v.M, nrhs, v.K);
+      g->a32 = a32;
+      for (const auto& v : h)
+        g->h.push_back(GemmDesc{v.A, v.X, v.Y, v.lda, v.ldx, v.ldy, v.M, nrhs, v.K, 0, 0, nullptr});
       g->finalize(st);
       by_nrhs[nrhs] = std::move(g);
     }
@@ -130,7 +233,11 @@ void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
   }
   const int nd = int(h.size());
   switch (nrhs) {
-#define AMB_CASE(R) case R: k_gemv_t<R><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+#define AMB_CASE(R)                                                     \
+  case R:                                                               \
+    if (a32) k_gemv_t<R, float><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); \
+    else k_gemv_t<R, double><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta);   \
+    break;
     AMB_CASE(1) AMB_CASE(2) AMB_CASE(3) AMB_CASE(4) AMB_CASE(5) AMB_CASE(6) AMB_CASE(7)
     AMB_CASE(8) AMB_CASE(9) AMB_CASE(10) AMB_CASE(11) AMB_CASE(12) AMB_CASE(13) AMB_CASE(14)
     AMB_CASE(15) AMB_CASE(16)

@@ -4,6 +4,9 @@
 //   LdltOp : signed partial LDL^T (Cholesky with fixed pivot signs), the
 //            trailing block becomes the Schur complement
 //   SymOp  : copy the lower triangle of a square block to the upper one
+// GemmOp and GemvOp can keep their A operands as FP32 copies (pack_a_f32):
+// the operands are rounded once and widened to FP64 as they are loaded, so
+// the products still accumulate in FP64 while HBM traffic for A halves.
 #pragma once
 #include <memory>
 
@@ -12,7 +15,7 @@
 namespace ambddc {
 
 struct GemmDesc {
-  const double* A;
+  const void* A;    // const double*, or const float* after pack_a_f32
   const double* B;
   double* C;
   int lda, ldb, ldc;
@@ -24,6 +27,7 @@ struct GemmDesc {
 class GemmOp {
  public:
   bool ta = false, tb = false, narrow = false;  // narrow: 128x32 tiles (N <= 32)
+  bool a32 = false;                             // A operands are FP32 (pack_a_f32)
   std::vector<GemmDesc> h;
   DBuf<GemmDesc> d;
   int tiles = 0;
@@ -33,12 +37,16 @@ class GemmOp {
     h.push_back(GemmDesc{A, B, C, lda, ldb, ldc, M, N, K, 0, 0, flag});
   }
   void finalize(hipStream_t st);
+  // Round every A block (op(A) is M x K) to FP32 into one packed buffer owned
+  // by `store`, and point the descriptors at it.  Call after the last add()
+  // and before finalize(); the FP64 source must hold its final values.
+  void pack_a_f32(DBuf<float>& store, hipStream_t st);
   void run(double alpha, double beta, hipStream_t st) const;
   bool empty() const { return h.empty(); }
 };
 
 struct GemvDesc {
-  const double* A;  // K x M block, column-major
+  const void* A;    // K x M block, column-major; double, or float after pack_a_f32
   int lda, K, M;
   const double* X;  // K x nrhs
   int ldx;
@@ -52,6 +60,7 @@ class GemvOp {
   // from this many right-hand sides on, the product runs as an MFMA GEMM
   // (the operator is read once and the right-hand sides are staged in LDS)
   static constexpr int GEMM_FROM = 4;
+  bool a32 = false;                 // A blocks are FP32 (pack_a_f32)
   std::vector<GemvDesc> h;
   DBuf<GemvDesc> d;
   int wgs = 0;
@@ -61,6 +70,9 @@ class GemvOp {
     h.push_back(GemvDesc{A, lda, K, M, X, ldx, Y, ldy, 0});
   }
   void finalize(hipStream_t st);
+  // FP32 copies of the A blocks (see GemmOp::pack_a_f32); columns are padded
+  // to a multiple of 4 floats so that the GEMV reads them as float4.
+  void pack_a_f32(DBuf<float>& store, hipStream_t st);
   // Y = alpha A^T X + beta Y, nrhs in 1..16
   void run(double alpha, double beta, int nrhs, hipStream_t st) const;
   bool empty() const { return h.empty(); }

@@ -38,6 +38,9 @@ struct Level {
   SymOp sym_naug;
   GemvOp g2, g3;
 
+  // FP32 copies of the g1..g4 operators (precision 1)
+  DBuf<float> g1_32, g2_32, g3_32, g4_32;
+
   // workspace of the preconditioner application
   int nrhs_cap = 0;
   DBuf<double> w_xI, w_y1, w_rBs, w_y2, w_rc, w_uc, w_ucl, w_uBs;

@@ -34,8 +34,9 @@ struct TileSmem {
 // op(A)(m, k) = TA ? A[k + m*lda] : A[m + k*lda]
 // op(B)(k, n) = TB ? B[n + k*ldb] : B[k + n*ldb]
 // sign_split >= 0: column k of op(A) is scaled by +1 if k < sign_split, else -1.
-template <bool TA, bool TB, int WM, int WN>
-__device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int lda,
+// TAe is the element type of A in memory (double, or float widened on load).
+template <bool TA, bool TB, int WM, int WN, typename TAe>
+__device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
                                           const double* __restrict__ B, int ldb, double* C, int ldc,
                                           int M, int N, int K, int m0, int n0, double alpha,
                                           double beta, int sign_split, TileSmem<WM, WN>& sm) {
@@ -62,7 +63,8 @@ __device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int lda,
       else { k = idx % KC; m = idx / KC; }
       const int gm = m0 + m, gk = k0 + k;
       double v = 0.0;
-      if (gm < M && gk < K) v = TA ? A[gk + (size_t)gm * lda] : A[gm + (size_t)gk * lda];
+      if (gm < M && gk < K)
+        v = static_cast<double>(TA ? A[gk + (size_t)gm * lda] : A[gm + (size_t)gk * lda]);
       if (sign_split >= 0 && gk >= sign_split) v = -v;
       ra[u] = v;
     }

@@ -249,6 +249,14 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
     L.g3.add(B + nl + nG + int64_t(nl) * NN, NN, L.nc[s], nG, L.w_ucl.p + L.cloff[s],
              int(std::max<int64_t>(L.cl_tot, 1)), L.w_y2.p + L.y2off[s], int(L.y2_tot));
   }
+  if (c.opt.precision == 1) {
+    // Alg. 1's dense operators are only read by the preconditioner: keep them
+    // in FP32 (the FP64 blocks stay for the Schur complements and set-up)
+    L.g1.pack_a_f32(L.g1_32, st);
+    L.g2.pack_a_f32(L.g2_32, st);
+    L.g3.pack_a_f32(L.g3_32, st);
+    L.g4.pack_a_f32(L.g4_32, st);
+  }
   L.g1.finalize(st);
   L.g2.finalize(st);
   L.g3.finalize(st);
@@ -1089,9 +1097,9 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
         ent += nI * nI + 2.0 * nI * nG + nG * nG + 2.0 * nG * ncs;
       }
     }
-    ent += double(c.top.n) * c.top.n;
-    apf = 2.0 * ent * nrhs;
-    apb = 8.0 * ent + 48.0 * double(n) * nrhs;
+    const double top = double(c.top.n) * c.top.n;   // the coarsest inverse stays FP64
+    apf = 2.0 * (ent + top) * nrhs;
+    apb = (c.opt.precision == 1 ? 4.0 : 8.0) * ent + 8.0 * top + 48.0 * double(n) * nrhs;
   }
   auto precondition = [&]() {
     c.kt.begin("bddc_apply", st);
@@ -1236,7 +1244,8 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     if (dec->levels < 2 || dec->levels > 8 || !dec->elem_to_sub)
       throw Error(AMBDDC_E_INVALID_ARG, "levels must be in 2..8 with an element map");
     if (dec->levels > 2 && !dec->parents) throw Error(AMBDDC_E_INVALID_ARG, "missing parent maps");
-    if (opt->precision != 0) throw Error(AMBDDC_E_INVALID_ARG, "only precision 0 (FP64) is built");
+    if (opt->precision != 0 && opt->precision != 1)
+      throw Error(AMBDDC_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (FP32-stored preconditioners)");
     if (opt->nev_max < 0 || opt->lobpcg_maxit < 1 || opt->lobpcg_tol <= 0.0)
       throw Error(AMBDDC_E_INVALID_ARG, "bad LOBPCG options");
     auto c = std::make_unique<ambddc_ctx>();

@@ -64,7 +64,12 @@ class Handle:
 
     def __init__(self, coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, parents=(),
                  levels=2, tau=10.0, nev_max=10, lobpcg_maxit=100, lobpcg_block=16,
-                 lobpcg_tol=1e-7, face_averages=False, seed=12345, stream=None):
+                 lobpcg_tol=1e-7, face_averages=False, seed=12345, stream=None, precision=0):
+        """precision 0: FP64 throughout; 1: the PCG preconditioner's dense
+        subdomain operators are kept in FP32 (widened to FP64 on load),
+        everything else in FP64."""
+        if precision not in (0, 1):
+            raise ValueError("precision must be 0 or 1")
         lib = _lib.load()
         self._lib = lib
         self._coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -86,6 +91,7 @@ class Handle:
         opt.lobpcg_block = int(lobpcg_block)
         opt.lobpcg_tol = float(lobpcg_tol)
         opt.face_averages = int(bool(face_averages))
+        opt.precision = int(precision)
         opt.seed = int(seed)
         if stream is None:
             torch = _torch()
@@ -95,6 +101,7 @@ class Handle:
         _lib.check(lib.ambddc_create(C.byref(mesh), C.byref(dec), C.byref(opt), C.byref(h)))
         self._h = h
         self.dof_per_node = dof_per_node
+        self.precision = int(precision)
         self.n_elems = int(self._en.shape[0])
         self.n_free = int(np.count_nonzero(self._dir == 0))
 
