@@ -56,39 +56,34 @@ void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStr
 // corner or edge only; its entries are listed in dr (pair-vector index and
 // position of the coefficient in the constraint buffer; t-side entries carry
 // the minus sign).  Rows have disjoint supports, so Pi subtracts each row's
-// component independently.
+// component independently: one thread per (row, column) computes the
+// coefficient and updates the row's support, with no barrier.  The rigid-mode
+// deflation needs whole columns and starts after a barrier.
 __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, const double* C,
                              const DRows dr, const double* rb, bool deflate, double* sm) {
   const int n = p.nGs + p.nGt;
   const int nd = p.dr1 - p.dr0;
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* coef = sm;   // [nd * ncol] then [nrb * ncol]
   for (int idx = tid; idx < nd * ncol; idx += nt) {
     const int r = idx / ncol, c = idx % ncol;
-    const double* vc = v + (size_t)c * ldv;
+    double* vc = v + (size_t)c * ldv;
+    const int q0 = dr.ptr[p.dr0 + r], q1 = dr.ptr[p.dr0 + r + 1];
     double dot = 0.0, nrm = 0.0;
-    for (int q = dr.ptr[p.dr0 + r]; q < dr.ptr[p.dr0 + r + 1]; ++q) {
+    for (int q = q0; q < q1; ++q) {
       const int i = dr.idx[q];
       const double a = (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
       dot += a * vc[i];
       nrm += a * a;
     }
-    coef[idx] = nrm > 0.0 ? dot / nrm : 0.0;
-  }
-  __syncthreads();
-  if (nd > 0) {
-    const int q0 = dr.ptr[p.dr0], q1 = dr.ptr[p.dr1];
-    for (int idx = tid; idx < (q1 - q0) * ncol; idx += nt) {
-      const int q = q0 + idx % (q1 - q0), c = idx / (q1 - q0);
-      int r = 0;
-      while (dr.ptr[p.dr0 + r + 1] <= q) ++r;
+    const double coef = nrm > 0.0 ? dot / nrm : 0.0;
+    for (int q = q0; q < q1; ++q) {
       const int i = dr.idx[q];
-      const double a = (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
-      v[i + (size_t)c * ldv] -= coef[r * ncol + c] * a;
+      vc[i] -= coef * (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
     }
   }
-  __syncthreads();
   if (deflate && p.nrb > 0) {
+    __syncthreads();
+    double* coef = sm;   // [nrb * ncol]
     const double* R = rb + p.rb_off;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     for (int idx = wave; idx < p.nrb * ncol; idx += nw) {
@@ -107,8 +102,15 @@ __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, con
       for (int r = 0; r < p.nrb; ++r) corr += coef[r * ncol + c] * R[i + (size_t)r * n];
       v[i + (size_t)c * ldv] -= corr;
     }
-    __syncthreads();
   }
+}
+
+// Columns [c0, c1) of the m-column block handled by this workgroup: the pair
+// kernels below run on a grid of (pairs, PAIR_COL_GROUPS) workgroups.
+__device__ inline void col_range(int m, int& c0, int& c1) {
+  const int per = (m + (int)gridDim.y - 1) / (int)gridDim.y;
+  c0 = (int)blockIdx.y * per;
+  c1 = min(m, c0 + per);
 }
 
 __global__ __launch_bounds__(256) void k_project(const PairDev* P, double* V, int m, int col,
@@ -116,16 +118,19 @@ __global__ __launch_bounds__(256) void k_project(const PairDev* P, double* V, in
                                                  const double* rb, const int* active, bool deflate) {
   __shared__ double sm[64 * 16];
   if (active && !active[blockIdx.x]) return;
+  int c0, c1;
+  col_range(m, c0, c1);
+  if (c0 >= c1) return;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
-  pair_project(p, V + p.v_off + (size_t)col * m * n, n, m, C, dr, rb, deflate, sm);
+  pair_project(p, V + p.v_off + (size_t)(col * m + c0) * n, n, c1 - c0, C, dr, rb, deflate, sm);
 }
 
 void lp_project(const PairDev* P, int np, double* V, int m, int col, const double* C,
                 const DRows dr, const double* rb, const int* active, bool deflate,
                 hipStream_t st) {
   if (np == 0) return;
-  k_project<<<np, 256, 0, st>>>(P, V, m, col, C, dr, rb, active, deflate);
+  k_project<<<dim3(np, PAIR_COL_GROUPS), 256, 0, st>>>(P, V, m, col, C, dr, rb, active, deflate);
   AMB_LAUNCH_CHECK();
 }
 
@@ -140,25 +145,30 @@ __global__ __launch_bounds__(256) void k_to_slab(const PairDev* P, const double*
                                                  bool with_ie, const double* diagG, const int* sh_s,
                                                  const int* sh_t, double* U, const int* active) {
   if (active && !active[blockIdx.x]) return;
+  int c0, c1;
+  col_range(m, c0, c1);
+  if (c0 >= c1) return;
+  const int nc = c1 - c0;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
-  const double* v = V + p.v_off + (size_t)col * m * n;
-  double* us = U + p.us_off;
-  double* ut = U + p.ut_off;
-  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+  const double* v = V + p.v_off + (size_t)(col * m + c0) * n;
+  double* us = U + p.us_off + (size_t)c0 * p.nGs;
+  double* ut = U + p.ut_off + (size_t)c0 * p.nGt;
+  for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
     const int i = idx % n, c = idx / n;
     const double x = v[idx];
     if (i < p.nGs) us[i + (size_t)c * p.nGs] = x;
     else ut[(i - p.nGs) + (size_t)c * p.nGt] = x;
   }
   if (!with_ie) return;
-  for (int idx = threadIdx.x; idx < p.nGs * m; idx += blockDim.x)
+  // (I-E) of column c goes to slot column m + c
+  for (int idx = threadIdx.x; idx < p.nGs * nc; idx += blockDim.x)
     us[(size_t)m * p.nGs + idx] = 0.0;
-  for (int idx = threadIdx.x; idx < p.nGt * m; idx += blockDim.x)
+  for (int idx = threadIdx.x; idx < p.nGt * nc; idx += blockDim.x)
     ut[(size_t)m * p.nGt + idx] = 0.0;
   __syncthreads();
   const int nsh = p.sh1 - p.sh0;
-  for (int idx = threadIdx.x; idx < nsh * m; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < nsh * nc; idx += blockDim.x) {
     const int q = idx % nsh, c = idx / nsh;
     const int is = sh_s[p.sh0 + q], it = sh_t[p.sh0 + q];
     const double ds = pair_ds(p, diagG, is, it), dt = 1.0 - ds;
@@ -172,7 +182,8 @@ void lp_to_slab(const PairDev* P, int np, const double* V, int m, int col, bool 
                 const double* diagG, const int* sh_s, const int* sh_t, double* U, const int* active,
                 hipStream_t st) {
   if (np == 0) return;
-  k_to_slab<<<np, 256, 0, st>>>(P, V, m, col, with_ie, diagG, sh_s, sh_t, U, active);
+  k_to_slab<<<dim3(np, PAIR_COL_GROUPS), 256, 0, st>>>(P, V, m, col, with_ie, diagG, sh_s, sh_t,
+                                                       U, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -182,22 +193,25 @@ __global__ __launch_bounds__(256) void k_from_slab_ab(const PairDev* P, const do
                                                       const double* diagG, const int* sh_s,
                                                       const int* sh_t, const double* C,
                                                       const DRows dr, const int* active) {
-  __shared__ double sm[64 * 16];
   if (active && !active[blockIdx.x]) return;
+  int c0, c1;
+  col_range(m, c0, c1);
+  if (c0 >= c1) return;
+  const int nc = c1 - c0;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
-  const double* ys = Y + p.ys_off;
-  const double* yt = Y + p.yt_off;
-  double* bv = BV + p.v_off + (size_t)col * m * n;
-  double* av = AV + p.v_off + (size_t)col * m * n;
-  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+  const double* ys = Y + p.ys_off + (size_t)c0 * p.nls;
+  const double* yt = Y + p.yt_off + (size_t)c0 * p.nlt;
+  double* bv = BV + p.v_off + (size_t)(col * m + c0) * n;
+  double* av = AV + p.v_off + (size_t)(col * m + c0) * n;
+  for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
     const int i = idx % n, c = idx / n;
     bv[idx] = (i < p.nGs) ? ys[i + (size_t)c * p.nls] : yt[(i - p.nGs) + (size_t)c * p.nlt];
     av[idx] = 0.0;
   }
   __syncthreads();
   const int nsh = p.sh1 - p.sh0;
-  for (int idx = threadIdx.x; idx < nsh * m; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < nsh * nc; idx += blockDim.x) {
     const int q = idx % nsh, c = idx / nsh;
     const int is = sh_s[p.sh0 + q], it = sh_t[p.sh0 + q];
     const double ds = pair_ds(p, diagG, is, it), dt = 1.0 - ds;
@@ -207,15 +221,16 @@ __global__ __launch_bounds__(256) void k_from_slab_ab(const PairDev* P, const do
     av[p.nGs + it + (size_t)c * n] = -dt * a + ds * b;
   }
   __syncthreads();
-  pair_project(p, bv, n, m, C, dr, nullptr, false, sm);
-  pair_project(p, av, n, m, C, dr, nullptr, false, sm);
+  pair_project(p, bv, n, nc, C, dr, nullptr, false, nullptr);
+  pair_project(p, av, n, nc, C, dr, nullptr, false, nullptr);
 }
 
 void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, double* AV,
                      double* BV, const double* diagG, const int* sh_s, const int* sh_t,
                      const double* C, const DRows dr, const int* active, hipStream_t st) {
   if (np == 0) return;
-  k_from_slab_ab<<<np, 256, 0, st>>>(P, Y, m, col, AV, BV, diagG, sh_s, sh_t, C, dr, active);
+  k_from_slab_ab<<<dim3(np, PAIR_COL_GROUPS), 256, 0, st>>>(P, Y, m, col, AV, BV, diagG, sh_s,
+                                                            sh_t, C, dr, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -274,74 +289,86 @@ void lp_coarse(const PairDev* P, int np, const double* Y, int m, const double* K
 __global__ __launch_bounds__(256) void k_from_slab_w(const PairDev* P, const double* Y, int m,
                                                      double* V, const int* active) {
   if (active && !active[blockIdx.x]) return;
+  int c0, c1;
+  col_range(m, c0, c1);
+  if (c0 >= c1) return;
+  const int nc = c1 - c0;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
-  double* w = V + p.v_off + (size_t)m * n;
-  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+  double* w = V + p.v_off + (size_t)(m + c0) * n;
+  const double* ys = Y + p.ys_off + (size_t)c0 * p.nls;
+  const double* yt = Y + p.yt_off + (size_t)c0 * p.nlt;
+  for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
     const int i = idx % n, c = idx / n;
-    w[idx] = -((i < p.nGs) ? Y[p.ys_off + i + (size_t)c * p.nls]
-                           : Y[p.yt_off + (i - p.nGs) + (size_t)c * p.nlt]);
+    w[idx] = -((i < p.nGs) ? ys[i + (size_t)c * p.nls] : yt[(i - p.nGs) + (size_t)c * p.nlt]);
   }
 }
 
 void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V, const int* active,
                     hipStream_t st) {
   if (np == 0) return;
-  k_from_slab_w<<<np, 256, 0, st>>>(P, Y, m, V, active);
+  k_from_slab_w<<<dim3(np, PAIR_COL_GROUPS), 256, 0, st>>>(P, Y, m, V, active);
   AMB_LAUNCH_CHECK();
 }
 
 // R = AX - BX diag(lam) into the W block; per-column relative residuals;
-// a pair stays active until its first nconv columns have converged.
-__global__ __launch_bounds__(256) void k_residual(const PairDev* P, double* V, const double* AV,
-                                                  const double* BV, const double* lam, int m,
-                                                  int nconv, double tol, int* active,
-                                                  double* resn) {
-  __shared__ double red[8];
-  __shared__ int all_ok;
+// a pair stays active until its first nconv columns have converged.  One
+// wave per column (wave reductions, no barrier inside a column).
+constexpr int RES_THREADS = 1024;
+
+__global__ __launch_bounds__(RES_THREADS) void k_residual(const PairDev* P, double* V,
+                                                          const double* AV, const double* BV,
+                                                          const double* lam, int m, int nconv,
+                                                          double tol, int* active, double* resn) {
+  __shared__ int n_bad;
   if (!active[blockIdx.x]) return;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
-  const double* ax = AV + p.v_off;
-  const double* bx = BV + p.v_off;
-  double* w = V + p.v_off + (size_t)m * n;
   const double* l = lam + (size_t)blockIdx.x * m;
-  if (threadIdx.x == 0) all_ok = 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (threadIdx.x == 0) n_bad = 0;
   __syncthreads();
-  for (int c = 0; c < m; ++c) {
+  for (int c = wave; c < m; c += RES_THREADS / 64) {
+    const double* ax = AV + p.v_off + (size_t)c * n;
+    const double* bx = BV + p.v_off + (size_t)c * n;
+    double* w = V + p.v_off + (size_t)(m + c) * n;
+    const double lc = l[c];
     double rr = 0.0, aa = 0.0, bb = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double a = ax[i + (size_t)c * n], b = bx[i + (size_t)c * n];
-      const double r = a - l[c] * b;
-      w[i + (size_t)c * n] = r;
+    for (int i = lane; i < n; i += 64) {
+      const double a = ax[i], b = bx[i];
+      const double r = a - lc * b;
+      w[i] = r;
       rr += r * r;
       aa += a * a;
       bb += b * b;
     }
-    rr = block_sum(rr, red);
-    aa = block_sum(aa, red);
-    bb = block_sum(bb, red);
+    for (int o = 32; o > 0; o >>= 1) {
+      rr += __shfl_xor(rr, o);
+      aa += __shfl_xor(aa, o);
+      bb += __shfl_xor(bb, o);
+    }
     // eigenvalues far below the pair's largest (the exact zeros of a pair with
     // few shared DOFs) are measured against 1e-6 lambda_1 instead of |lambda|
-    const double den = sqrt(aa) + fmax(fabs(l[c]), 1e-6 * fabs(l[0])) * sqrt(bb);
+    const double den = sqrt(aa) + fmax(fabs(lc), 1e-6 * fabs(l[0])) * sqrt(bb);
     const double rel = den > 0.0 ? sqrt(rr) / den : 0.0;
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       resn[(size_t)blockIdx.x * m + c] = rel;
-      if (c < nconv && !(rel <= tol)) all_ok = 0;
+      if (c < nconv && !(rel <= tol)) atomicAdd(&n_bad, 1);
     }
     // soft locking: a converged column contributes no search direction
     if (rel <= tol)
-      for (int i = threadIdx.x; i < n; i += blockDim.x) w[i + (size_t)c * n] = 0.0;
+      for (int i = lane; i < n; i += 64) w[i] = 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0 && all_ok) active[blockIdx.x] = 0;
+  if (threadIdx.x == 0 && n_bad == 0) active[blockIdx.x] = 0;
 }
 
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,
                  const double* lam, int m, int nconv, double tol, int* active, double* resn,
                  hipStream_t st) {
   if (np == 0) return;
-  k_residual<<<np, 256, 0, st>>>(P, V, AV, BV, lam, m, nconv, tol, active, resn);
+  k_residual<<<np, RES_THREADS, 0, st>>>(P, V, AV, BV, lam, m, nconv, tol, active, resn);
   AMB_LAUNCH_CHECK();
 }
 
@@ -584,14 +611,18 @@ __global__ __launch_bounds__(256) void k_commit(const PairDev* P, double* V, dou
                                                 double* BV, const double* T, int m, bool with_p,
                                                 bool only_v, const int* active) {
   if (active && !active[blockIdx.x]) return;
+  int c0, c1;
+  col_range(m, c0, c1);
+  if (c0 >= c1) return;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
   // T layout per pair: [TV | TAV | TBV], each n x 2m, at offset v_off (same 3m*n footprint x2)
   const double* t = T + 2 * p.v_off;
   double* dst[3] = {V + p.v_off, AV + p.v_off, BV + p.v_off};
+  const size_t e0 = (size_t)c0 * n, e1 = (size_t)c1 * n;
   for (int o = 0; o < (only_v ? 1 : 3); ++o) {
     const double* src = t + (size_t)o * n * 2 * m;
-    for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) {
+    for (size_t idx = e0 + threadIdx.x; idx < e1; idx += blockDim.x) {
       dst[o][idx] = src[idx];
       if (with_p) dst[o][(size_t)2 * m * n + idx] = src[(size_t)m * n + idx];
     }
@@ -601,7 +632,7 @@ __global__ __launch_bounds__(256) void k_commit(const PairDev* P, double* V, dou
 void lp_commit(const PairDev* P, int np, double* V, double* AV, double* BV, const double* T,
                int m, bool with_p, bool only_v, const int* active, hipStream_t st) {
   if (np == 0) return;
-  k_commit<<<np, 256, 0, st>>>(P, V, AV, BV, T, m, with_p, only_v, active);
+  k_commit<<<dim3(np, PAIR_COL_GROUPS), 256, 0, st>>>(P, V, AV, BV, T, m, with_p, only_v, active);
   AMB_LAUNCH_CHECK();
 }
 

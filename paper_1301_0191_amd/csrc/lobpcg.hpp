@@ -7,6 +7,9 @@
 namespace ambddc {
 
 constexpr int PAIR_COARSE_MAX = 256;   // pair coarse DOFs (LDS of the coarse correction)
+// The column-parallel pair kernels (slab copies, projection, commit) split a
+// pair's m-column block over this many workgroups.
+constexpr int PAIR_COL_GROUPS = 4;
 
 struct PairDev {
   int s, t, nGs, nGt;
