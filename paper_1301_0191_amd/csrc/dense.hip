@@ -62,80 +62,17 @@ static void gemm_run(const GemmOp& op, double alpha, double beta, hipStream_t st
 
 void GemmOp::run(double alpha, double beta, hipStream_t st) const {
   if (h.empty() || tiles == 0) return;
+  if (a32 && ta) throw Error(1, "GemmOp: FP32 operands are panel-packed, not transposed");
   if (a32) gemm_run<float>(*this, alpha, beta, st);
   else gemm_run<double>(*this, alpha, beta, st);
   AMB_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------------------------
-// FP32 operand copies: one workgroup row per block, columns strided over x
-// --------------------------------------------------------------------------
-
-struct PackDesc {
-  const double* src;
-  int64_t lds;
-  int rows, cols;
-  float* dst;
-  int64_t ldd;
-};
-
-__global__ __launch_bounds__(256) void k_pack_f32(const PackDesc* __restrict__ d) {
-  const PackDesc g = d[blockIdx.y];
-  for (int j = blockIdx.x; j < g.cols; j += gridDim.x) {
-    const double* s = g.src + (size_t)j * g.lds;
-    float* t = g.dst + (size_t)j * g.ldd;
-    for (int i = threadIdx.x; i < g.rows; i += blockDim.x) t[i] = static_cast<float>(s[i]);
-    // zero the padding rows so that vector loads read defined values
-    for (int i = g.rows + threadIdx.x; i < g.ldd; i += blockDim.x) t[i] = 0.0f;
-  }
-}
-
-// Packs every (rows x cols, leading dimension lds) FP64 block into `store`
-// with leading dimension rows rounded up to 4; returns the packed pointers
-// and leading dimensions in pd[].dst / pd[].ldd.
-static void pack_blocks(std::vector<PackDesc>& pd, DBuf<float>& store, hipStream_t st) {
-  int64_t total = 0;
-  int maxc = 1;
-  for (auto& p : pd) {
-    p.ldd = (p.rows + 3) / 4 * 4;
-    total += p.ldd * int64_t(p.cols);
-    maxc = std::max(maxc, p.cols);
-  }
-  store.alloc(size_t(std::max<int64_t>(total, 4)));
-  int64_t off = 0;
-  for (auto& p : pd) {
-    p.dst = store.p + off;
-    off += p.ldd * int64_t(p.cols);
-  }
-  if (pd.empty()) return;
-  if (pd.size() > 65535) throw Error(1, "pack_a_f32: too many blocks");
-  DBuf<PackDesc> dd;
-  dd.upload(pd, st);
-  k_pack_f32<<<dim3(std::min(maxc, 1024), unsigned(pd.size())), 256, 0, st>>>(dd.p);
-  AMB_LAUNCH_CHECK();
-  AMB_HIP(hipStreamSynchronize(st));
-}
-
-void GemmOp::pack_a_f32(DBuf<float>& store, hipStream_t st) {
-  if (a32) throw Error(1, "GemmOp::pack_a_f32 called twice");
-  std::vector<PackDesc> pd;
-  for (const auto& g : h) {
-    const int rows = ta ? g.K : g.M, cols = ta ? g.M : g.K;
-    pd.push_back(PackDesc{static_cast<const double*>(g.A), g.lda, rows, cols, nullptr, 0});
-  }
-  pack_blocks(pd, store, st);
-  for (size_t i = 0; i < h.size(); ++i) {
-    h[i].A = pd[i].dst;
-    h[i].lda = int(pd[i].ldd);
-  }
-  a32 = true;
-}
-
-// --------------------------------------------------------------------------
 // GEMV (transposed, several right-hand sides): one wave per output column
 // --------------------------------------------------------------------------
 
-template <int R, typename T>
+template <int R>
 __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, int nd, double alpha,
                                                 double beta) {
   const int wg = blockIdx.x;
@@ -148,31 +85,14 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
   const int col = (wg - g.wg_start) * 4 + (threadIdx.x >> 6);
   if (col >= g.M) return;
   const int lane = threadIdx.x & 63;
-  const T* a = static_cast<const T*>(g.A) + (size_t)col * g.lda;
+  const double* a = static_cast<const double*>(g.A) + (size_t)col * g.lda;
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  if constexpr (sizeof(T) == 4) {
-    // packed FP32 columns: 16-byte aligned, padded with zeros to a multiple of 4
-    for (int i0 = 4 * lane; i0 < g.K; i0 += 256) {
-      const float4 av = *reinterpret_cast<const float4*>(a + i0);
-      const float as[4] = {av.x, av.y, av.z, av.w};
+  for (int i = lane; i < g.K; i += 64) {
+    const double av = a[i];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u;
-        if (i < g.K) {
-          const double w = as[u];
-#pragma unroll
-          for (int r = 0; r < R; ++r) acc[r] += w * g.X[i + (size_t)r * g.ldx];
-        }
-      }
-    }
-  } else {
-    for (int i = lane; i < g.K; i += 64) {
-      const double av = a[i];
-#pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
-    }
+    for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -190,16 +110,139 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
   }
 }
 
+// --------------------------------------------------------------------------
+// FP32 operator copies, stored transposed in row panels: A' = A^T (M x K) is
+// cut into panels of PANEL_ROWS rows, each panel stored column by column
+// (element (m, k) at (m / 128) * 128 K + 128 k + m % 128; rows past M are
+// zero).  A GEMM tile of 128 rows then reads one contiguous block per K
+// chunk, and the GEMV reads runs of 512 bytes.
+// --------------------------------------------------------------------------
+
+struct PackTDesc {
+  const double* src;   // K x M, leading dimension lds
+  int64_t lds;
+  int K, M;
+  float* dst;          // ceil(M / 128) panels of 128 x K
+  int tiles_k, tile_start;
+};
+
+// One 64 x 64 tile per workgroup, transposed through LDS: reads run along K
+// of the source, writes along M of the copy.
+__global__ __launch_bounds__(256) void k_pack_t_f32(const PackTDesc* __restrict__ d, int nd) {
+  __shared__ float t[64][65];
+  const int tile = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
+  }
+  const PackTDesc g = d[lo];
+  const int lt = tile - g.tile_start;
+  const int k0 = (lt % g.tiles_k) * 64, m0 = (lt / g.tiles_k) * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int kk = e & 63, mm = e >> 6;
+    const int k = k0 + kk, m = m0 + mm;
+    t[mm][kk] = (k < g.K && m < g.M) ? static_cast<float>(g.src[k + (size_t)m * g.lds]) : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int mm = e & 63, kk = e >> 6;
+    const int k = k0 + kk, m = m0 + mm;   // m < ceil(M / 128) * 128 by the tile count
+    if (k < g.K) g.dst[panel_index(m, k, g.K)] = t[mm][kk];
+  }
+}
+
+// Y = alpha A' X + beta Y for 1..3 right-hand sides: a workgroup owns 256
+// rows of A' (a float4 of rows per lane); its four waves take every fourth
+// column of A' and their partial sums meet in LDS.
+constexpr int GN_ROWS = 256;
+
+template <int R>
+__global__ __launch_bounds__(256) void k_gemv_n32(const GemvDesc* __restrict__ d, int nd,
+                                                  double alpha, double beta) {
+  __shared__ double red[3][GN_ROWS * R];
+  const int wg = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
+  }
+  const GemvDesc g = d[lo];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lrow = 4 * lane;
+  const int row0 = (wg - g.wg_start) * GN_ROWS + lrow;
+  // this lane's float4 of rows inside its panel, column 0
+  const float* A = static_cast<const float*>(g.A) + panel_index(row0, 0, g.K);
+  double acc[4][R];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[u][r] = 0.0;
+  if (row0 < g.M) {
+#pragma unroll 4
+    for (int k = wave; k < g.K; k += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(A + (size_t)k * PANEL_ROWS);
+      const double a4[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double x = g.X[k + (size_t)r * g.ldx];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u][r] += a4[u] * x;
+      }
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) red[wave - 1][(lrow + u) * R + r] = acc[u][r];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = row0 + u;
+      if (row >= g.M) break;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = (lrow + u) * R + r;
+        const double v = acc[u][r] + red[0][e] + red[1][e] + red[2][e];
+        double* y = g.Y + row + (size_t)r * g.ldy;
+        *y = alpha * v + (beta != 0.0 ? beta * (*y) : 0.0);
+      }
+    }
+  }
+}
+
 void GemvOp::pack_a_f32(DBuf<float>& store, hipStream_t st) {
   if (a32) throw Error(1, "GemvOp::pack_a_f32 called twice");
   if (!by_nrhs.empty()) throw Error(1, "GemvOp::pack_a_f32 after run");
-  std::vector<PackDesc> pd;
-  for (const auto& g : h)
-    pd.push_back(PackDesc{static_cast<const double*>(g.A), g.lda, g.K, g.M, nullptr, 0});
-  pack_blocks(pd, store, st);
+  std::vector<PackTDesc> pd;
+  std::vector<int64_t> off;
+  int64_t total = 0;
+  int tiles = 0;
+  for (const auto& g : h) {
+    const int panels = ceil_div(g.M, PANEL_ROWS);
+    PackTDesc p{static_cast<const double*>(g.A), g.lda, g.K, g.M, nullptr, ceil_div(g.K, 64),
+                tiles};
+    tiles += p.tiles_k * panels * (PANEL_ROWS / 64);
+    off.push_back(total);
+    total += int64_t(panels) * PANEL_ROWS * g.K;
+    pd.push_back(p);
+  }
+  store.alloc(size_t(std::max<int64_t>(total, 4)));
+  for (size_t i = 0; i < pd.size(); ++i) pd[i].dst = store.p + off[i];
+  if (tiles > 0) {
+    DBuf<PackTDesc> dd;
+    dd.upload(pd, st);
+    k_pack_t_f32<<<tiles, 256, 0, st>>>(dd.p, int(pd.size()));
+    AMB_LAUNCH_CHECK();
+    AMB_HIP(hipStreamSynchronize(st));
+  }
   for (size_t i = 0; i < h.size(); ++i) {
     h[i].A = pd[i].dst;
-    h[i].lda = int(pd[i].ldd);
+    h[i].lda = PANEL_ROWS;   // the panel height; element (m, k) at panel_index(m, k, K)
   }
   a32 = true;
 }
@@ -208,7 +251,7 @@ void GemvOp::finalize(hipStream_t st) {
   wgs = 0;
   for (auto& g : h) {
     g.wg_start = wgs;
-    wgs += ceil_div(g.M, 4);
+    wgs += a32 ? ceil_div(g.M, GN_ROWS) : ceil_div(g.M, 4);
   }
   d.upload(h, st);
   AMB_HIP(hipStreamSynchronize(st));
@@ -220,7 +263,7 @@ void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
     if (by_nrhs.size() < 17) by_nrhs.resize(17);
     if (!by_nrhs[nrhs]) {
       auto g = std::make_unique<GemmOp>();
-      g->ta = true;
+      g->ta = !a32;   // the FP32 copy is stored transposed
       g->narrow = true;
       g->a32 = a32;
       for (const auto& v : h)
@@ -232,12 +275,18 @@ void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
     return;
   }
   const int nd = int(h.size());
+  if (a32) {
+    switch (nrhs) {
+      case 1: k_gemv_n32<1><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+      case 2: k_gemv_n32<2><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+      case 3: k_gemv_n32<3><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+      default: throw Error(1, "GemvOp: nrhs must be in 1..16");
+    }
+    AMB_LAUNCH_CHECK();
+    return;
+  }
   switch (nrhs) {
-#define AMB_CASE(R)                                                     \
-  case R:                                                               \
-    if (a32) k_gemv_t<R, float><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); \
-    else k_gemv_t<R, double><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta);   \
-    break;
+#define AMB_CASE(R) case R: k_gemv_t<R><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
     AMB_CASE(1) AMB_CASE(2) AMB_CASE(3) AMB_CASE(4) AMB_CASE(5) AMB_CASE(6) AMB_CASE(7)
     AMB_CASE(8) AMB_CASE(9) AMB_CASE(10) AMB_CASE(11) AMB_CASE(12) AMB_CASE(13) AMB_CASE(14)
     AMB_CASE(15) AMB_CASE(16)

@@ -4,9 +4,9 @@
 //   LdltOp : signed partial LDL^T (Cholesky with fixed pivot signs), the
 //            trailing block becomes the Schur complement
 //   SymOp  : copy the lower triangle of a square block to the upper one
-// GemmOp and GemvOp can keep their A operands as FP32 copies (pack_a_f32):
-// the operands are rounded once and widened to FP64 as they are loaded, so
-// the products still accumulate in FP64 while HBM traffic for A halves.
+// GemvOp can keep its operators as FP32 copies (pack_a_f32): they are
+// rounded once and widened to FP64 as they are loaded, so the products still
+// accumulate in FP64 while the HBM traffic for the operators halves.
 #pragma once
 #include <memory>
 
@@ -15,7 +15,7 @@
 namespace ambddc {
 
 struct GemmDesc {
-  const void* A;    // const double*, or const float* after pack_a_f32
+  const void* A;    // const double*, or const float* when the op's a32 is set
   const double* B;
   double* C;
   int lda, ldb, ldc;
@@ -27,7 +27,7 @@ struct GemmDesc {
 class GemmOp {
  public:
   bool ta = false, tb = false, narrow = false;  // narrow: 128x32 tiles (N <= 32)
-  bool a32 = false;                             // A operands are FP32 (pack_a_f32)
+  bool a32 = false;                             // A operands are FP32 (GemvOp copies)
   std::vector<GemmDesc> h;
   DBuf<GemmDesc> d;
   int tiles = 0;
@@ -37,16 +37,13 @@ class GemmOp {
     h.push_back(GemmDesc{A, B, C, lda, ldb, ldc, M, N, K, 0, 0, flag});
   }
   void finalize(hipStream_t st);
-  // Round every A block (op(A) is M x K) to FP32 into one packed buffer owned
-  // by `store`, and point the descriptors at it.  Call after the last add()
-  // and before finalize(); the FP64 source must hold its final values.
-  void pack_a_f32(DBuf<float>& store, hipStream_t st);
   void run(double alpha, double beta, hipStream_t st) const;
   bool empty() const { return h.empty(); }
 };
 
 struct GemvDesc {
-  const void* A;    // K x M block, column-major; double, or float after pack_a_f32
+  const void* A;    // K x M double block, column-major; after pack_a_f32 the
+                    // transposed M x K float copy in row panels
   int lda, K, M;
   const double* X;  // K x nrhs
   int ldx;
@@ -70,8 +67,11 @@ class GemvOp {
     h.push_back(GemvDesc{A, lda, K, M, X, ldx, Y, ldy, 0});
   }
   void finalize(hipStream_t st);
-  // FP32 copies of the A blocks (see GemmOp::pack_a_f32); columns are padded
-  // to a multiple of 4 floats so that the GEMV reads them as float4.
+  // Round every A block to FP32 into one buffer owned by `store`, stored
+  // transposed (M x K) in row panels of PANEL_ROWS rows (see mfma_tile.hpp)
+  // so that both the GEMV and the GEMM read it in contiguous runs, and point
+  // the descriptors at it.  Call after the last add() and before finalize();
+  // the FP64 source must hold its final values.
   void pack_a_f32(DBuf<float>& store, hipStream_t st);
   // Y = alpha A^T X + beta Y, nrhs in 1..16
   void run(double alpha, double beta, int nrhs, hipStream_t st) const;

@@ -17,6 +17,23 @@ namespace ambddc {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// FP32 operands are stored in row panels: element (m, k) of an M x K matrix
+// at (m / PANEL_ROWS) * PANEL_ROWS * K + PANEL_ROWS * k + m % PANEL_ROWS.
+constexpr int PANEL_ROWS = 128;
+__host__ __device__ __forceinline__ size_t panel_index(int m, int k, int K) {
+  return (size_t)(m / PANEL_ROWS) * PANEL_ROWS * K + (size_t)k * PANEL_ROWS + (m % PANEL_ROWS);
+}
+
+// Loads through global-address-space pointers: the compiler then emits
+// global loads, which only count in vmcnt, so waiting for LDS reads does not
+// also wait for the next chunk's loads still in flight (flat loads count in
+// both counters).
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  typedef const __attribute__((address_space(1))) T* gptr;
+  return *(gptr)p;
+}
+
 template <int WM, int WN>
 struct TileShape {
   static constexpr int TM = 32 * WM;
@@ -34,7 +51,9 @@ struct TileSmem {
 // op(A)(m, k) = TA ? A[k + m*lda] : A[m + k*lda]
 // op(B)(k, n) = TB ? B[n + k*ldb] : B[k + n*ldb]
 // sign_split >= 0: column k of op(A) is scaled by +1 if k < sign_split, else -1.
-// TAe is the element type of A in memory (double, or float widened on load).
+// TAe is the element type of A in memory: double, or float widened on load.
+// A float A is not transposed (TA false) and stored in row panels
+// (panel_index); lda is then unused.
 template <bool TA, bool TB, int WM, int WN, typename TAe>
 __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
                                           const double* __restrict__ B, int ldb, double* C, int ldc,
@@ -52,7 +71,8 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  double ra[NA], rb[NB];
+  TAe ra[NA];      // raw A values: converted and sign-flipped when stored to LDS
+  double rb[NB];
   // global -> registers for the chunk starting at k0
   auto gload = [&](int k0) {
 #pragma unroll
@@ -62,10 +82,13 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
       if (!TA) { m = idx % TM; k = idx / TM; }
       else { k = idx % KC; m = idx / KC; }
       const int gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < M && gk < K)
-        v = static_cast<double>(TA ? A[gk + (size_t)gm * lda] : A[gm + (size_t)gk * lda]);
-      if (sign_split >= 0 && gk >= sign_split) v = -v;
+      TAe v = TAe(0);
+      if (gm < M && gk < K) {
+        if constexpr (sizeof(TAe) == 4)
+          v = gld(A + panel_index(gm, gk, K));
+        else
+          v = gld(TA ? A + gk + (size_t)gm * lda : A + gm + (size_t)gk * lda);
+      }
       ra[u] = v;
     }
 #pragma unroll
@@ -75,18 +98,22 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
       if (TB) { n = idx % TN; k = idx / TN; }
       else { k = idx % KC; n = idx / KC; }
       const int gn = n0 + n, gk = k0 + k;
-      rb[u] = (gn < N && gk < K) ? (TB ? B[gn + (size_t)gk * ldb] : B[gk + (size_t)gn * ldb]) : 0.0;
+      double v = 0.0;
+      if (gn < N && gk < K) v = gld(TB ? B + gn + (size_t)gk * ldb : B + gk + (size_t)gn * ldb);
+      rb[u] = v;
     }
   };
-  // registers -> LDS buffer
-  auto sstore = [&](int buf) {
+  // registers (chunk starting at k0) -> LDS buffer
+  auto sstore = [&](int buf, int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int idx = tid + u * 256;
       int m, k;
       if (!TA) { m = idx % TM; k = idx / TM; }
       else { k = idx % KC; m = idx / KC; }
-      sm.As[buf][k][m] = ra[u];
+      double v = static_cast<double>(ra[u]);
+      if (sign_split >= 0 && k0 + k >= sign_split) v = -v;
+      sm.As[buf][k][m] = v;
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -99,7 +126,7 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
   };
   if (K > 0) {
     gload(0);
-    sstore(0);
+    sstore(0, 0);
   }
   __syncthreads();
   int buf = 0;
@@ -120,7 +147,7 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (more) sstore(buf ^ 1);
+    if (more) sstore(buf ^ 1, k0 + KC);
     __syncthreads();
     buf ^= 1;
   }
