@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libambddc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "dense.hip", "fem.hip", "bddc.hip", "lobpcg.hip", "solver.cpp"]
+SOURCES = ["plan.cpp", "devmem.cpp", "dense.hip", "fem.hip", "bddc.hip", "lobpcg.hip", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("AMBDDC_ARCH", "gfx950")

@@ -24,6 +24,30 @@ struct Error : std::runtime_error {
 
 #define AMB_LAUNCH_CHECK() AMB_HIP(hipGetLastError())
 
+// Device memory through a cache of freed blocks (devmem.cpp): dev_free keeps
+// the block for later dev_malloc calls of the same rounded size on the same
+// device and for the same stream, the one set by the innermost
+// DevStreamScope on this thread.  A block may be handed out again while
+// earlier work on that stream still uses it; the new owner's work is queued
+// after it on the same stream.
+void* dev_malloc(size_t bytes);
+void dev_free(void* p, size_t bytes);
+void dev_cache_release();      // return every cached block to HIP
+size_t dev_cache_bytes();
+struct DevStreamScope {        // allocations and frees below are for stream st
+  explicit DevStreamScope(hipStream_t st);
+  ~DevStreamScope();
+  DevStreamScope(const DevStreamScope&) = delete;
+  DevStreamScope& operator=(const DevStreamScope&) = delete;
+ private:
+  hipStream_t prev_;
+};
+void dev_stream_acquire(hipStream_t st);   // a handle starts using st
+void dev_stream_release(hipStream_t st);   // ... stops; frees st's cache when unused
+// Queues a host-to-device copy on st through pinned staging memory; the host
+// buffer may be reused or freed as soon as the call returns.
+void upload_async(void* dst, const void* src, size_t bytes, hipStream_t st);
+
 // Owning device buffer.
 template <typename T>
 struct DBuf {
@@ -39,33 +63,25 @@ struct DBuf {
   }
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, n * sizeof(T));
     p = nullptr;
     n = 0;
   }
   void alloc(size_t count) {
     release();
-    n = count;
     if (count == 0) return;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
-      n = 0;
-      (void)hipGetLastError();
-      throw Error(5, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
+    p = static_cast<T*>(dev_malloc(count * sizeof(T)));
+    n = count;
   }
   void zero(hipStream_t st) {
     if (n) AMB_HIP(hipMemsetAsync(p, 0, n * sizeof(T), st));
   }
   // Same-size uploads keep the allocation, so device pointers taken into the
   // buffer (e.g. per-pair flags referenced by GEMM descriptors) stay valid.
+  // The copy is queued on st; the host vector may be a temporary.
   void upload(const std::vector<T>& v, hipStream_t st) {
     if (v.size() != n || !p) alloc(v.size());
-    if (n) {
-      AMB_HIP(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
-      AMB_HIP(hipStreamSynchronize(st));   // the host vector may be a temporary
-    }
+    if (n) upload_async(p, v.data(), n * sizeof(T), st);
   }
   std::vector<T> download(hipStream_t st) const {
     std::vector<T> v(n);

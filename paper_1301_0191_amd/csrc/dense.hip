@@ -41,7 +41,6 @@ void GemmOp::finalize(hipStream_t st) {
     tiles += g.tiles_m * ceil_div(g.N, TN);
   }
   d.upload(h, st);
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 template <bool TA, bool TB, typename TAe>
@@ -238,7 +237,6 @@ void GemvOp::pack_a_f32(DBuf<float>& store, hipStream_t st) {
     dd.upload(pd, st);
     k_pack_t_f32<<<tiles, 256, 0, st>>>(dd.p, int(pd.size()));
     AMB_LAUNCH_CHECK();
-    AMB_HIP(hipStreamSynchronize(st));
   }
   for (size_t i = 0; i < h.size(); ++i) {
     h[i].A = pd[i].dst;
@@ -254,7 +252,6 @@ void GemvOp::finalize(hipStream_t st) {
     wgs += a32 ? ceil_div(g.M, GN_ROWS) : ceil_div(g.M, 4);
   }
   d.upload(h, st);
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
@@ -479,7 +476,6 @@ void LdltOp::finalize(hipStream_t st) {
   pan_pre.upload(pp_all, st);
   upd_pre.upload(up_all, st);
   info.alloc(1);
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 void LdltOp::run(hipStream_t st) {
@@ -542,7 +538,6 @@ void SymOp::finalize(hipStream_t st) {
     tiles += nt * nt;
   }
   d.upload(h, st);
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 void SymOp::run(hipStream_t st) const {

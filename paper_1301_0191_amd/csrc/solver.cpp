@@ -84,7 +84,6 @@ void build_assembly(AssemblyMaps& am, int nelem, const std::vector<int>& elem_tg
   am.elem_ne.upload(ene, st);
   am.eloc_off.upload(eloc_off, st);
   am.eloc.upload(eloc, st);
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace
@@ -205,7 +204,6 @@ void build_level_maps(ambddc_ctx& c, Level& L, const double* emat,
   }
   L.ldl_aug.finalize(st);
   L.sym_aug.finalize(st);
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 void alloc_workspace(Level& L, int nrhs) {
@@ -369,7 +367,6 @@ void build_constraint_maps(ambddc_ctx& c, Level& L) {
   L.ldl_naug.finalize(st);
   L.sym_naug.finalize(st);
   alloc_coarse_workspace(L, std::max(L.nrhs_cap, 1));
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 void check_ldlt(LdltOp& op, hipStream_t st, const char* what, int level) {
@@ -390,7 +387,6 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
     DBuf<int> dz;
     dz.upload(zero, st);
     launch_aug_identity(L.nsub, L.d_aug_off.p, L.d_augN.p, L.d_nI.p, dz.p, L.d_ns.p, st, L.aug.p);
-    AMB_HIP(hipStreamSynchronize(st));
   }
   launch_diag_copy(int(L.nG_tot), L.diagpos.p, L.aug.p, L.diagG.p, st);
   launch_weights(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.diagG.p, L.delta.p, st);
@@ -414,7 +410,6 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
     DBuf<int> dn0;
     dn0.upload(n0, st);
     launch_diag_mean(L.nsub, L.d_aug_off.p, L.d_augN.p, dn0.p, L.d_nG.p, L.aug.p, L.rho.p, st);
-    AMB_HIP(hipStreamSynchronize(st));
   }
 }
 
@@ -428,7 +423,6 @@ void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
     tmp.alloc(L.cadapt_pos.n);
     launch_gather(int(L.cadapt_pos.n), L.cadapt_src.p, L.fc.p, 0, tmp.p, 0, 1, 1.0, st);
     launch_fill_values(int(L.cadapt_pos.n), L.cadapt_pos.p, tmp.p, L.C.p, st);
-    AMB_HIP(hipStreamSynchronize(st));
   }
   L.naug.zero(st);
   launch_neumann_fill(L.neu.p, L.nsub, L.neu_cols, st);
@@ -650,7 +644,6 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
     W.gram_a[v].finalize(st); W.gram_b[v].finalize(st);
     W.upd_v[v].finalize(st);
   }
-  AMB_HIP(hipStreamSynchronize(st));
 }
 
 // Pseudo-inverses of the pair coarse matrices (see lobpcg.hip): null-space
@@ -871,7 +864,6 @@ void build_top(ambddc_ctx& c) {
     rr.upload(std::vector<int>{n}, st);
     dl.upload(std::vector<int>{n}, st);
     launch_copy_block(1, so.p, sl.p, r0.p, rr.p, rr.p, dof.p, dl.p, T.aug.p, T.Kc.p, st);
-    AMB_HIP(hipStreamSynchronize(st));
   }
   {
     DBuf<int> nid, c0, r0;
@@ -879,7 +871,6 @@ void build_top(ambddc_ctx& c) {
     c0.upload(std::vector<int>{0}, st);
     r0.upload(std::vector<int>{n}, st);
     launch_aug_identity(1, T.d_off.p, T.d_ld.p, nid.p, c0.p, r0.p, st, T.aug.p);
-    AMB_HIP(hipStreamSynchronize(st));
   }
   T.ldl.add(T.aug.p, N, N, n, n);
   T.ldl.finalize(st);
@@ -971,7 +962,6 @@ void next_level(ambddc_ctx& c, int li) {
     dgo.upload(std::vector<int64_t>(L.Goff.begin(), L.Goff.end() - 1), st);
     launch_coarse_rigid(N->ndof, N->nrb, ds.p, dr.p, dco.p, dnc.p, L.d_nG.p, dgo.p, L.Gdof.p, L.C.p,
                         L.rigid.p, L.ndof, N->rigid.p, st);
-    AMB_HIP(hipStreamSynchronize(st));
   }
   c.L.push_back(std::move(N));
 }
@@ -1171,6 +1161,12 @@ int guard(const std::function<void()>& fn) {
   }
 }
 
+// Entry points on a handle: device memory is cached for the handle's stream.
+int hguard(ambddc_handle h, const std::function<void()>& fn) {
+  DevStreamScope ds(h ? h->st : nullptr);
+  return guard(fn);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1248,6 +1244,7 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
       throw Error(AMBDDC_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (FP32-stored preconditioners)");
     if (opt->nev_max < 0 || opt->lobpcg_maxit < 1 || opt->lobpcg_tol <= 0.0)
       throw Error(AMBDDC_E_INVALID_ARG, "bad LOBPCG options");
+    DevStreamScope ds(static_cast<hipStream_t>(opt->stream));
     auto c = std::make_unique<ambddc_ctx>();
     c->opt = *opt;
     c->st = static_cast<hipStream_t>(opt->stream);
@@ -1345,12 +1342,13 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
       AMB_HIP(hipStreamSynchronize(st));
     }
     c->L.push_back(std::move(L0));
+    dev_stream_acquire(c->st);
     *out = c.release();
   }));
 }
 
 ambddc_status ambddc_setup(ambddc_handle h, const double* coeff, const double* nu) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !coeff) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (h->dof == 3 && !nu) throw Error(AMBDDC_E_INVALID_ARG, "elasticity needs nu");
     setup_impl(*h, coeff, nu);
@@ -1358,7 +1356,7 @@ ambddc_status ambddc_setup(ambddc_handle h, const double* coeff, const double* n
 }
 
 ambddc_status ambddc_setup_log10(ambddc_handle h, const double* theta, const double* nu) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !theta) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (h->dof == 3 && !nu) throw Error(AMBDDC_E_INVALID_ARG, "elasticity needs nu");
     if (h->coeff_buf.n != size_t(h->n_elems)) h->coeff_buf.alloc(h->n_elems);
@@ -1369,7 +1367,7 @@ ambddc_status ambddc_setup_log10(ambddc_handle h, const double* theta, const dou
 
 ambddc_status ambddc_misfit(ambddc_handle h, const double* X, const double* Xobs, int32_t nrhs,
                             double* R, double* J) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !X || !Xobs || !R) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (h->L.empty()) throw Error(AMBDDC_E_STATE, "misfit needs a created handle");
     if (nrhs < 1 || nrhs > 16) throw Error(AMBDDC_E_INVALID_ARG, "nrhs must be in 1..16");
@@ -1410,7 +1408,7 @@ ambddc_status ambddc_solve(ambddc_handle h, const double* rhs, int32_t nrhs, dou
 
 ambddc_status ambddc_element_gradient(ambddc_handle h, const double* X, const double* Lam,
                                       int32_t nrhs, double* grad) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !X || !Lam || !grad) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (!h->ready) throw Error(AMBDDC_E_STATE, "gradient needs a setup");
     launch_element_gradient(h->n_elems, 8 * h->dof, h->L[0]->ndof, nrhs, h->edofs.p, h->Ke.p, X, Lam,
@@ -1420,7 +1418,7 @@ ambddc_status ambddc_element_gradient(ambddc_handle h, const double* X, const do
 }
 
 ambddc_status ambddc_last_residual(ambddc_handle h, int32_t nrhs, double* res) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !res) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (nrhs != int(h->last_res.size()))
       throw Error(AMBDDC_E_STATE, "nrhs differs from the last solve (" +
@@ -1430,7 +1428,7 @@ ambddc_status ambddc_last_residual(ambddc_handle h, int32_t nrhs, double* res) {
 }
 
 ambddc_status ambddc_get_stats(ambddc_handle h, ambddc_stats* out) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !out) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     *out = h->stats;
   }));
@@ -1446,7 +1444,7 @@ static bool known_class(const std::string& name) {
 }
 
 ambddc_status ambddc_timing_enable(ambddc_handle h, const char* classes) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h) throw Error(AMBDDC_E_INVALID_ARG, "null handle");
     const std::string list = classes ? classes : "";
     size_t a = 0;
@@ -1464,7 +1462,7 @@ ambddc_status ambddc_timing_enable(ambddc_handle h, const char* classes) {
 
 ambddc_status ambddc_timing_read(ambddc_handle h, const char* cls, int32_t* launches,
                                  double* total_ms, double* flops, double* bytes) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !cls) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
     if (!known_class(cls)) throw Error(AMBDDC_E_INVALID_ARG, std::string("unknown timing class '") + cls + "'");
     h->kt.collect();
@@ -1480,7 +1478,7 @@ ambddc_status ambddc_timing_read(ambddc_handle h, const char* cls, int32_t* laun
 
 ambddc_status ambddc_level_info(ambddc_handle h, int32_t level, int32_t* n_dof, int32_t* n_sub,
                                 int32_t* n_pairs, int32_t* n_coarse) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size()))
       throw Error(AMBDDC_E_INVALID_ARG, "bad handle or level");
     const Level& L = *h->L[level];
@@ -1493,7 +1491,7 @@ ambddc_status ambddc_level_info(ambddc_handle h, int32_t level, int32_t* n_dof, 
 
 ambddc_status ambddc_sub_dofs(ambddc_handle h, int32_t level, int32_t sub, int32_t* dofs,
                               int32_t* n_I, int32_t* n_G) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
     const Level& L = *h->L[level];
     if (sub < 0 || sub >= L.nsub) throw Error(AMBDDC_E_INVALID_ARG, "bad subdomain");
@@ -1505,7 +1503,7 @@ ambddc_status ambddc_sub_dofs(ambddc_handle h, int32_t level, int32_t sub, int32
 }
 
 ambddc_status ambddc_get_schur(ambddc_handle h, int32_t level, int32_t sub, double* S) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || !S || level < 0 || level >= int(h->L.size()))
       throw Error(AMBDDC_E_INVALID_ARG, "bad argument");
     const Level& L = *h->L[level];
@@ -1520,7 +1518,7 @@ ambddc_status ambddc_get_schur(ambddc_handle h, int32_t level, int32_t sub, doub
 
 ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int32_t* s, int32_t* t,
                                int32_t* n_face) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
     const Level& L = *h->L[level];
     if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
@@ -1534,7 +1532,7 @@ ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int
 ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, double* lam,
                                      double* resid, int32_t* k, double* lam_next, int32_t* iters,
                                      int32_t* converged) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
     const Level& L = *h->L[level];
     if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
@@ -1552,7 +1550,7 @@ ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pai
 
 ambddc_status ambddc_get_face_constraints(ambddc_handle h, int32_t level, int32_t pair, double* rows,
                                           int32_t* face_dofs) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
     const Level& L = *h->L[level];
     if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
@@ -1569,7 +1567,7 @@ ambddc_status ambddc_get_face_constraints(ambddc_handle h, int32_t level, int32_
 
 ambddc_status ambddc_get_coarse_element(ambddc_handle h, int32_t level, int32_t sub, double* Kc,
                                         int32_t* nc) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
     const Level& L = *h->L[level];
     if (sub < 0 || sub >= L.nsub || L.nc.empty()) throw Error(AMBDDC_E_INVALID_ARG, "bad subdomain");
@@ -1583,7 +1581,7 @@ ambddc_status ambddc_get_coarse_element(ambddc_handle h, int32_t level, int32_t 
 }
 
 ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc, int32_t* n) {
-  return ambddc_status(guard([&] {
+  return ambddc_status(hguard(h, [&] {
     if (!h) throw Error(AMBDDC_E_INVALID_ARG, "null handle");
     if (n) *n = h->top.n;
     if (Kc && h->top.n > 0) {
@@ -1597,8 +1595,13 @@ ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc, int32_t* n) {
 
 void ambddc_destroy(ambddc_handle h) {
   if (!h) return;
-  (void)hipStreamSynchronize(h->st);
-  delete h;
+  hipStream_t st = h->st;
+  {
+    DevStreamScope ds(st);
+    (void)hipStreamSynchronize(st);
+    delete h;
+  }
+  dev_stream_release(st);
 }
 
 }  // extern "C"
