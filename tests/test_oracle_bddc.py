@@ -209,3 +209,70 @@ def test_lanczos_estimate_matches_dense_spectrum():
     cond, lmin, lmax = lanczos_cond(al, be)
     assert lmin >= ev[0] * (1 - 1e-8) and lmax <= ev[-1] * (1 + 1e-8)
     assert cond == pytest.approx(ev[-1] / ev[0], rel=1e-3)
+
+
+def _explicit_alg1(H, dtype):
+    """Alg. 1 on a two-level hierarchy with every subdomain operator formed
+    explicitly (K_II^-1, K_GI K_II^-1, the interface block Z of the saddle
+    inverse, Psi) and rounded through ``dtype``; the coarsest solve stays FP64.
+    Test code: the reading that storing the PCG preconditioner's operators in
+    FP32 leaves the FP64 PCG solution and iteration count unchanged."""
+    L = H.levels[0]
+    ops = []
+    for s in range(L.inp.n_sub):
+        nI = L.n_I[s]
+        K = L.K[s]
+        Ki = np.linalg.inv(K[:nI, :nI])
+        S = K[nI:, nI:] - K[nI:, :nI] @ Ki @ K[:nI, nI:]
+        C = L.C[s]
+        nG, nc = S.shape[0], C.shape[0]
+        M = np.zeros((nG + nc, nG + nc))
+        M[:nG, :nG] = S
+        M[:nG, nG:] = C.T
+        M[nG:, :nG] = C
+        Mi = np.linalg.inv(M)
+        rnd = lambda X: X.astype(dtype).astype(np.float64)
+        ops.append((rnd(Ki), rnd(K[nI:, :nI] @ Ki), rnd(Mi[:nG, :nG]), rnd(Mi[:nG, nG:]),
+                    rnd(Ki @ K[:nI, nI:])))
+
+    def apply(r):
+        u = np.zeros_like(r)
+        rB = r.copy()
+        for s, (Ki, GKi, Z, Psi, KiIG) in enumerate(ops):
+            d, nI = L.sub_dofs[s], L.n_I[s]
+            u[d[:nI]] += Ki @ r[d[:nI]]
+            rB[d[nI:]] -= GKi @ r[d[:nI]]
+        rc = np.zeros(L.n_coarse)
+        fs = []
+        for s, (Ki, GKi, Z, Psi, KiIG) in enumerate(ops):
+            d, nI = L.sub_dofs[s], L.n_I[s]
+            f = L.weights[s] * rB[d[nI:]]
+            fs.append(f)
+            np.add.at(rc, L.Rc[s], Psi.T @ f)
+        uc = sla.cho_solve(H.top_chol, rc)
+        uB = np.zeros_like(r)
+        for s, (Ki, GKi, Z, Psi, KiIG) in enumerate(ops):
+            d, nI = L.sub_dofs[s], L.n_I[s]
+            np.add.at(uB, d[nI:], L.weights[s] * (Z @ fs[s] + Psi @ uc[L.Rc[s]]))
+        for s, (Ki, GKi, Z, Psi, KiIG) in enumerate(ops):
+            d, nI = L.sub_dofs[s], L.n_I[s]
+            u[d[:nI]] -= KiIG @ uB[d[nI:]]
+        return u + uB
+    return apply
+
+
+def test_fp32_stored_preconditioner_keeps_fp64_pcg():
+    prob = W.tiny_poisson(shape=(8, 8, 8), subs=(2, 2, 2), seed=4, coeff="blocks", rhs="normal")
+    H = setup_hierarchy(prob)
+    K = H.levels[0].Kglob
+    f = prob.rhs[:, 0]
+    xd = direct_solve(prob)[:, 0]
+    # the explicit FP64 operators reproduce the oracle's Alg. 1
+    r = np.random.default_rng(0).standard_normal(f.shape[0])
+    np.testing.assert_allclose(_explicit_alg1(H, np.float64)(r), bddc_apply(H, r),
+                               rtol=0, atol=1e-9 * np.abs(bddc_apply(H, r)).max())
+    x0, it0, *_ = pcg(K, f, _explicit_alg1(H, np.float64), 1e-12, 500)
+    x1, it1, *_ = pcg(K, f, _explicit_alg1(H, np.float32), 1e-12, 500)
+    assert abs(it1 - it0) <= 1
+    assert np.linalg.norm(x1 - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert np.linalg.norm(x0 - xd) <= 1e-9 * np.linalg.norm(xd)
