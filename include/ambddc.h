@@ -237,8 +237,9 @@ ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc_host, int32_t* n
  *                  symmetric eigendecomposition with vectors, LAPACK-style
  *                  counts), bytes 8 (2 nb^2 + 2 nb m) per pair;
  *   "pair_apply"   grouped S^s products of the pair LOBPCG: per subdomain
- *                  2 nG^2 c flops and 8 (nG^2 + 2 nG c) bytes, c = columns of
- *                  all its pair slots;
+ *                  with an active pair, 2 nG^2 c flops and 8 (nG^2 + 2 nG c)
+ *                  bytes, c = columns of the slots of its active pairs (tiles
+ *                  whose slots all belong to converged pairs are skipped);
  *   "pair_gram"    Gram matrices V^T (A V), V^T (B V): 2 n nb^2 flops and
  *                  8 (2 n nb + nb^2) bytes per active pair and matrix;
  *   "schur"        batched partial LDL^T of the augmented subdomain matrices

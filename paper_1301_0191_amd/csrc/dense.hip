@@ -15,7 +15,7 @@ __device__ __forceinline__ int ceil_div_dev(int a, int b) { return (a + b - 1) /
 
 template <bool TA, bool TB, int WM, int WN, typename TAe>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, int nd, double alpha,
-                                              double beta) {
+                                              double beta, const int* __restrict__ act) {
   __shared__ TileSmem<WM, WN> sm;
   const int tile = blockIdx.x;
   int lo = 0, hi = nd - 1;
@@ -27,6 +27,13 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, in
   if (g.flag && *g.flag == 0) return;
   const int lt = tile - g.tile_start;
   const int tm = lt % g.tiles_m, tn = lt / g.tiles_m;
+  if (g.scols > 0) {
+    const int c0 = tn * TileShape<WM, WN>::TN;
+    const int c1 = min(g.N, c0 + TileShape<WM, WN>::TN) - 1;
+    bool any = false;
+    for (int j = c0 / g.scols; j <= c1 / g.scols; ++j) any = any || act[g.spair[j]] != 0;
+    if (!any) return;
+  }
   mfma_tile<TA, TB, WM, WN>(static_cast<const TAe*>(g.A), g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N,
                             g.K, tm * TileShape<WM, WN>::TM, tn * TileShape<WM, WN>::TN, alpha,
                             beta, -1, sm);
@@ -36,6 +43,7 @@ void GemmOp::finalize(hipStream_t st) {
   const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
   tiles = 0;
   for (auto& g : h) {
+    if (g.scols > 0 && !act) throw Error(1, "GemmOp: column slots without item flags");
     g.tiles_m = ceil_div(g.M, TM);
     g.tile_start = tiles;
     tiles += g.tiles_m * ceil_div(g.N, TN);
@@ -46,9 +54,11 @@ void GemmOp::finalize(hipStream_t st) {
 template <bool TA, bool TB, typename TAe>
 static void gemm_dispatch(const GemmOp& op, double alpha, double beta, hipStream_t st) {
   if (op.narrow)
-    k_gemm<TA, TB, 4, 1, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+    k_gemm<TA, TB, 4, 1, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta,
+                                                        op.act);
   else
-    k_gemm<TA, TB, 2, 2, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta);
+    k_gemm<TA, TB, 2, 2, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta,
+                                                        op.act);
 }
 
 template <typename TAe>
@@ -264,7 +274,8 @@ void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
       g->narrow = true;
       g->a32 = a32;
       for (const auto& v : h)
-        g->h.push_back(GemmDesc{v.A, v.X, v.Y, v.lda, v.ldx, v.ldy, v.M, nrhs, v.K, 0, 0, nullptr});
+        g->h.push_back(
+            GemmDesc{v.A, v.X, v.Y, v.lda, v.ldx, v.ldy, v.M, nrhs, v.K, 0, 0, nullptr, nullptr, 0});
       g->finalize(st);
       by_nrhs[nrhs] = std::move(g);
     }

@@ -22,19 +22,25 @@ struct GemmDesc {
   int M, N, K;
   int tiles_m, tile_start;
   const int* flag;  // optional: skip the product when *flag == 0
+  // optional column slots: columns [j scols, (j+1) scols) belong to item
+  // spair[j]; a tile whose slots all have act[item] == 0 (GemmOp::act) is
+  // skipped
+  const int* spair;
+  int scols;
 };
 
 class GemmOp {
  public:
   bool ta = false, tb = false, narrow = false;  // narrow: 128x32 tiles (N <= 32)
   bool a32 = false;                             // A operands are FP32 (GemvOp copies)
+  const int* act = nullptr;                     // item flags for column-slot skipping
   std::vector<GemmDesc> h;
   DBuf<GemmDesc> d;
   int tiles = 0;
   void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
-           int K, const int* flag = nullptr) {
+           int K, const int* flag = nullptr, const int* spair = nullptr, int scols = 0) {
     if (M <= 0 || N <= 0) return;
-    h.push_back(GemmDesc{A, B, C, lda, ldb, ldc, M, N, K, 0, 0, flag});
+    h.push_back(GemmDesc{A, B, C, lda, ldb, ldc, M, N, K, 0, 0, flag, spair, scols});
   }
   void finalize(hipStream_t st);
   void run(double alpha, double beta, hipStream_t st) const;

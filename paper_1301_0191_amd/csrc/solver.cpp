@@ -447,11 +447,11 @@ struct PairWork {
   DBuf<PairDev> dp;
   PairIdx idx;
   DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw, Nb, Aug;
-  DBuf<int> active, kout, nnull;
+  DBuf<int> active, kout, nnull, slot_pair;
   GemmOp gS, gM1, gM2, gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
   KTimer* kt = nullptr;
-  double apply_flops = 0.0, apply_bytes = 0.0;   // grouped S products, per launch
   std::vector<int> act;                          // host copy of the active flags
+  std::vector<int> h_slot_off, h_slot_pair;      // pair of every subdomain slot
 };
 
 void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
@@ -574,21 +574,32 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
   W.nnull.alloc(W.np);
   L.fc.alloc(std::max<int64_t>(fcoff, 1));
   L.fc.zero(st);
-  // grouped S / Z / Psi products: one GEMM per subdomain over all its pair slots
+  // grouped S / Z / Psi products: one GEMM per subdomain over all its pair
+  // slots; a tile whose slots all belong to converged pairs is skipped
+  std::vector<int> slot_off(L.nsub + 1, 0), slot_pair;
+  for (int s = 0; s < L.nsub; ++s) slot_off[s + 1] = slot_off[s] + P.sub_npairs[s];
+  slot_pair.assign(std::max(slot_off[L.nsub], 1), 0);
+  for (int p = 0; p < W.np; ++p) {
+    slot_pair[slot_off[P.pairs[p].s] + P.pairs[p].slot_s] = p;
+    slot_pair[slot_off[P.pairs[p].t] + P.pairs[p].slot_t] = p;
+  }
+  W.slot_pair.upload(slot_pair, st);
+  W.h_slot_off = slot_off;
+  W.h_slot_pair = slot_pair;
   W.gS = GemmOp(); W.gM1 = GemmOp(); W.gM2 = GemmOp();
+  W.gS.act = W.gM1.act = W.gM2.act = W.active.p;
   for (int s = 0; s < L.nsub; ++s) {
     const int cols = P.sub_npairs[s] * 2 * m;
     if (cols == 0) continue;
     const int N = L.augN[s], nI = L.nI[s], nG = L.nG[s], nl = L.nl[s], NN = L.naugN[s];
     const double* S = L.aug.p + L.aug_off[s] + nI + int64_t(nI) * N;
     const double* Tn = L.naug.p + L.naug_off[s] + nl + int64_t(nl) * NN;
-    W.gS.add(S, N, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nG, cols, nG);
-    W.apply_flops += 2.0 * nG * double(nG) * cols;
-    W.apply_bytes += 8.0 * (double(nG) * nG + 2.0 * double(nG) * cols);
-    W.gM1.add(Tn, NN, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nl, cols, nG);
+    const int* sp = W.slot_pair.p + slot_off[s];
+    W.gS.add(S, N, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nG, cols, nG, nullptr, sp, 2 * m);
+    W.gM1.add(Tn, NN, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl, nl, cols, nG, nullptr, sp, 2 * m);
     if (L.nc[s] > 0)
       W.gM2.add(Tn + int64_t(nG) * NN, NN, W.Zc.p + Zoff[s], L.nc[s], W.Y.p + Yoff[s], nl, nG, cols,
-                L.nc[s]);
+                L.nc[s], nullptr, sp, 2 * m);
   }
   W.gS.finalize(st);
   W.gM1.finalize(st);
@@ -696,9 +707,24 @@ void pair_pinv(ambddc_ctx& c, Level& L, PairWork& W, int li) {
 void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
   lp_to_slab(W.dp.p, W.np, W.V.p, W.m, col, true, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
              W.active.p, st);
-  W.kt->begin("pair_apply", st);
-  W.gS.run(1.0, 0.0, st);
-  W.kt->end("pair_apply", st, W.apply_flops, W.apply_bytes);
+  if (W.kt->any()) {
+    // algorithmic work: S^s applied to the slots of the active pairs only
+    double fl = 0.0, by = 0.0;
+    for (int s = 0; s < L.nsub; ++s) {
+      int na = 0;
+      for (int j = W.h_slot_off[s]; j < W.h_slot_off[s + 1]; ++j)
+        na += (W.act.empty() || W.act[W.h_slot_pair[j]]) ? 1 : 0;
+      if (na == 0) continue;
+      const double nG = L.nG[s], c = 2.0 * W.m * na;
+      fl += 2.0 * nG * nG * c;
+      by += 8.0 * (nG * nG + 2.0 * nG * c);
+    }
+    W.kt->begin("pair_apply", st);
+    W.gS.run(1.0, 0.0, st);
+    W.kt->end("pair_apply", st, fl, by);
+  } else {
+    W.gS.run(1.0, 0.0, st);
+  }
   lp_from_slab_ab(W.dp.p, W.np, W.Y.p, W.m, col, W.AV.p, W.BV.p, L.diagG.p, W.idx.sh_s.p,
                   W.idx.sh_t.p, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.active.p,
                   st);
