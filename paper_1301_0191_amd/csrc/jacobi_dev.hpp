@@ -63,12 +63,17 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
     if (q >= 0) {
       const double apq = A[p + q * lda];
       if (apq != 0.0) {
-        // tangent of the smaller rotation angle annihilating A_pq:
-        // t = 2 A_pq sgn(d) / (|d| + sqrt(d^2 + 4 A_pq^2)), d = A_qq - A_pp
+        // the smaller rotation angle annihilating A_pq, d = A_qq - A_pp:
+        // cos 2theta = |d| rho with rho = (d^2 + 4 A_pq^2)^{-1/2}, so
+        // c = sqrt(h), h = (1 + |d| rho) / 2, and s = sgn(d) A_pq rho / c
+        // (two reciprocal square roots; c^2 + s^2 = 1 holds exactly in exact
+        // arithmetic)
         const double d = A[q + q * lda] - A[p + p * lda];
-        const double t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
-        c = rsqrt(1.0 + t * t);
-        s = t * c;
+        const double rho = rsqrt(d * d + 4.0 * apq * apq);
+        const double h = 0.5 + 0.5 * fabs(d) * rho;
+        const double ic = rsqrt(h);
+        c = h * ic;
+        s = (d >= 0.0 ? 1.0 : -1.0) * apq * rho * ic;
       }
       // column pass: new col p = c col_p - s col_q, new col q = s col_p + c col_q
       double a[RPT], b[RPT];
