@@ -39,8 +39,62 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, in
                             beta, -1, sm);
 }
 
+// C = alpha sum_s P_s + beta C for every split product, one workgroup each.
+__global__ __launch_bounds__(256) void k_split_sum(const SplitDesc* __restrict__ d,
+                                                   const double* __restrict__ part, double alpha,
+                                                   double beta) {
+  const SplitDesc g = d[blockIdx.x];
+  if (g.flag && *g.flag == 0) return;
+  const int mn = g.M * g.N;
+  const double* p = part + g.poff;
+  for (int e = threadIdx.x; e < mn; e += 256) {
+    double v = 0.0;
+    for (int s = 0; s < g.S; ++s) v += p[(size_t)s * mn + e];
+    double* c = g.C + (e % g.M) + (size_t)(e / g.M) * g.ldc;
+    *c = alpha * v + (beta != 0.0 ? beta * (*c) : 0.0);
+  }
+}
+
 void GemmOp::finalize(hipStream_t st) {
   const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
+  hs.clear();
+  if (ksplit != 1 && !h.empty()) {
+    int t0 = 0, kmin = 1 << 30;
+    for (const auto& g : h) {
+      if (g.scols > 0) throw Error(1, "GemmOp: split-K with column slots");
+      t0 += ceil_div(g.M, TM) * ceil_div(g.N, TN);
+      kmin = std::min(kmin, g.K);
+    }
+    int S = ksplit > 1 ? ksplit : std::max(1, std::min(8, SPLIT_TARGET / std::max(t0, 1)));
+    while (S > 1 && kmin / S < 64) --S;
+    if (S > 1) {
+      std::vector<GemmDesc> hp;
+      std::vector<int64_t> eoff;   // partial block of every piece
+      int64_t poff = 0;
+      for (const auto& g : h) {
+        hs.push_back(SplitDesc{g.C, g.ldc, g.M, g.N, g.flag, poff, S});
+        for (int q = 0; q < S; ++q) {
+          const int k0 = int(int64_t(g.K) * q / S), k1 = int(int64_t(g.K) * (q + 1) / S);
+          GemmDesc e = g;
+          const size_t ao = ta ? size_t(k0) : size_t(k0) * g.lda;
+          const size_t bo = tb ? size_t(k0) * g.ldb : size_t(k0);
+          e.A = static_cast<const double*>(g.A) + ao;
+          e.B = g.B + bo;
+          e.K = k1 - k0;
+          e.C = nullptr;   // set below, once the partial buffer exists
+          e.ldc = g.M;
+          eoff.push_back(poff + int64_t(q) * g.M * g.N);
+          hp.push_back(e);
+        }
+        poff += int64_t(S) * g.M * g.N;
+      }
+      if (a32) throw Error(1, "GemmOp: split-K with FP32 operands");
+      part.alloc(size_t(poff));
+      for (size_t i = 0; i < hp.size(); ++i) hp[i].C = part.p + eoff[i];
+      h.swap(hp);
+      ds.upload(hs, st);
+    }
+  }
   tiles = 0;
   for (auto& g : h) {
     if (g.scols > 0 && !act) throw Error(1, "GemmOp: column slots without item flags");
@@ -72,6 +126,13 @@ static void gemm_run(const GemmOp& op, double alpha, double beta, hipStream_t st
 void GemmOp::run(double alpha, double beta, hipStream_t st) const {
   if (h.empty() || tiles == 0) return;
   if (a32 && ta) throw Error(1, "GemmOp: FP32 operands are panel-packed, not transposed");
+  if (!hs.empty()) {
+    gemm_run<double>(*this, 1.0, 0.0, st);   // partial products
+    AMB_LAUNCH_CHECK();
+    k_split_sum<<<int(hs.size()), 256, 0, st>>>(ds.p, part.p, alpha, beta);
+    AMB_LAUNCH_CHECK();
+    return;
+  }
   if (a32) gemm_run<float>(*this, alpha, beta, st);
   else gemm_run<double>(*this, alpha, beta, st);
   AMB_LAUNCH_CHECK();

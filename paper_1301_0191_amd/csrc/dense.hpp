@@ -29,14 +29,32 @@ struct GemmDesc {
   int scols;
 };
 
+// Reduction of split-K partial products: C = alpha sum_s P_s + beta C.
+struct SplitDesc {
+  double* C;
+  int ldc, M, N;
+  const int* flag;
+  int64_t poff;     // first partial block (M x N, ld M) in GemmOp::part
+  int S;            // number of partial blocks
+};
+
 class GemmOp {
  public:
   bool ta = false, tb = false, narrow = false;  // narrow: 128x32 tiles (N <= 32)
   bool a32 = false;                             // A operands are FP32 (GemvOp copies)
   const int* act = nullptr;                     // item flags for column-slot skipping
+  // Split-K: 0 = chosen at finalize (products with few tiles and long K are
+  // split so that the launch has about SPLIT_TARGET workgroups), 1 = never.
+  // Each product's K range is cut into S pieces whose partial products go to
+  // `part`; a second kernel sums them in a fixed order (deterministic).
+  static constexpr int SPLIT_TARGET = 1024;
+  int ksplit = 1;
   std::vector<GemmDesc> h;
   DBuf<GemmDesc> d;
   int tiles = 0;
+  std::vector<SplitDesc> hs;
+  DBuf<SplitDesc> ds;
+  DBuf<double> part;
   void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
            int K, const int* flag = nullptr, const int* spair = nullptr, int scols = 0) {
     if (M <= 0 || N <= 0) return;

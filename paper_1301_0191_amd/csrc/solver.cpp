@@ -608,6 +608,7 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
   W.orth_c = GemmOp();
   W.orth_u = GemmOp();
   W.orth_c.ta = true;
+  W.orth_c.ksplit = 0;
   W.orth_u.narrow = (m <= 32);
   for (int p = 0; p < W.np; ++p) {
     const PairDev& d = W.hp[p];
@@ -623,6 +624,7 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
   W.orthp_c = GemmOp();
   W.orthp_u = GemmOp();
   W.orthp_c.ta = true;
+  W.orthp_c.ksplit = 0;
   W.orthp_u.narrow = (m <= 32);
   for (int p = 0; p < W.np; ++p) {
     const PairDev& d = W.hp[p];
@@ -639,6 +641,7 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
     W.gram_a[v] = GemmOp(); W.gram_b[v] = GemmOp();
     W.upd_v[v] = GemmOp();
     W.gram_a[v].ta = W.gram_b[v].ta = true;
+    W.gram_a[v].ksplit = W.gram_b[v].ksplit = 0;
     W.upd_v[v].narrow = (2 * m <= 32);
     for (int p = 0; p < W.np; ++p) {
       const PairDev& d = W.hp[p];
