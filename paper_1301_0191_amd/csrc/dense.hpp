@@ -47,7 +47,7 @@ class GemmOp {
   // split so that the launch has about SPLIT_TARGET workgroups), 1 = never.
   // Each product's K range is cut into S pieces whose partial products go to
   // `part`; a second kernel sums them in a fixed order (deterministic).
-  static constexpr int SPLIT_TARGET = 1024;
+  static constexpr int SPLIT_TARGET = 4096;
   int ksplit = 1;
   std::vector<GemmDesc> h;
   DBuf<GemmDesc> d;
