@@ -123,7 +123,11 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* decomp
 /* Numeric set-up (Alg. 3) for element coefficients resident on the device:
  * coeff[n_elems] = kappa (Poisson) or Young's modulus E (elasticity),
  * nu[n_elems] = Poisson ratio (elasticity; NULL for Poisson).  May be called
- * again with new coefficients; the previous hierarchy is replaced.
+ * again with new coefficients; the previous hierarchy is replaced.  The
+ * first set-up on a handle also chooses, by timing both, the tile shape of
+ * the grouped pair-eigenproblem products on every level (64 x 64 or
+ * 128 x 32; both give identical results) and keeps the choice for later
+ * set-ups.
  * Errors: E_NOT_SPD, E_ASSUMPTION, E_INVALID_ARG, E_OOM, E_DEVICE. */
 ambddc_status ambddc_setup(ambddc_handle h, const double* coeff_dev, const double* nu_dev);
 

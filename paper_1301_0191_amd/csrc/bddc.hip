@@ -169,15 +169,11 @@ __global__ __launch_bounds__(256) void k_neumann_fill(const NeuDesc* __restrict_
   const NeuDesc g = d[lo];
   const int j = wg - g.col_start;
   const int nG = g.nG, nc = g.nc, nl = nG + nc;
-  const double rho = *g.rho;
   double* col = g.A + (size_t)j * g.lda;
   for (int i = threadIdx.x; i < nl; i += blockDim.x) {
     double v = 0.0;
     if (i < nG && j < nG) {
-      v = g.S[i + (size_t)j * g.lds];
-      double cc = 0.0;
-      for (int r = 0; r < nc; ++r) cc += g.C[r + (size_t)i * nc] * g.C[r + (size_t)j * nc];
-      v += rho * cc;
+      v = g.S[i + (size_t)j * g.lds];   // rho C^T C is added afterwards by a GEMM
     } else if (i >= nG && j < nG) {
       v = g.C[(i - nG) + (size_t)j * nc];
     } else if (i < nG && j >= nG) {
@@ -189,6 +185,27 @@ __global__ __launch_bounds__(256) void k_neumann_fill(const NeuDesc* __restrict_
     g.A[(nl + j) + (size_t)j * g.lda] = 1.0;
     g.A[j + (size_t)(nl + j) * g.lda] = 1.0;
   }
+}
+
+// dst = sqrt(scale[s]) src on the entries [off[s], off[s] + cnt[s]) of every s
+__global__ __launch_bounds__(256) void k_scale_sqrt_sub(const int64_t* __restrict__ off,
+                                                        const int64_t* __restrict__ cnt,
+                                                        const double* __restrict__ scale,
+                                                        const double* __restrict__ src,
+                                                        double* __restrict__ dst) {
+  const int s = blockIdx.y;
+  const double f = sqrt(scale[s]);
+  const int64_t o = off[s], n = cnt[s];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[o + i] = f * src[o + i];
+}
+
+void launch_scale_sqrt_sub(int nsub, const int64_t* off, const int64_t* cnt, const double* scale,
+                           const double* src, double* dst, hipStream_t st) {
+  if (nsub == 0) return;
+  k_scale_sqrt_sub<<<dim3(16, nsub), 256, 0, st>>>(off, cnt, scale, src, dst);
+  AMB_LAUNCH_CHECK();
 }
 
 void launch_neumann_fill(const NeuDesc* d, int nd, int ncols, hipStream_t st) {

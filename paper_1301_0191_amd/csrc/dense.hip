@@ -138,6 +138,40 @@ void GemmOp::run(double alpha, double beta, hipStream_t st) const {
   AMB_LAUNCH_CHECK();
 }
 
+void TunedGemm::drop_events() {
+  for (auto& e : ev) {
+    for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    e.clear();
+  }
+}
+
+void TunedGemm::run(double alpha, double beta, hipStream_t st) {
+  if (!choice || *choice >= 0) {
+    v[choice ? *choice : 0].run(alpha, beta, st);
+    return;
+  }
+  const int k = calls & 1;
+  hipEvent_t a, b;
+  AMB_HIP(hipEventCreate(&a));
+  AMB_HIP(hipEventCreate(&b));
+  AMB_HIP(hipEventRecord(a, st));
+  v[k].run(alpha, beta, st);
+  AMB_HIP(hipEventRecord(b, st));
+  ev[k].push_back(a);
+  ev[k].push_back(b);
+  if (++calls < 2 * TUNE_CALLS) return;
+  AMB_HIP(hipEventSynchronize(b));
+  float t[2] = {0.0f, 0.0f};
+  for (int q = 0; q < 2; ++q)
+    for (size_t i = 0; i + 1 < ev[q].size(); i += 2) {
+      float ms = 0.0f;
+      AMB_HIP(hipEventElapsedTime(&ms, ev[q][i], ev[q][i + 1]));
+      t[q] += ms;
+    }
+  *choice = t[1] < t[0] ? 1 : 0;
+  drop_events();
+}
+
 // --------------------------------------------------------------------------
 // GEMV (transposed, several right-hand sides): one wave per output column
 // --------------------------------------------------------------------------

@@ -65,6 +65,45 @@ class GemmOp {
   bool empty() const { return h.empty(); }
 };
 
+// One batched product in two tile shapes, 64 x 64 (v[0]) and 128 x 32
+// (v[1]).  The shapes only change which workgroup computes which outputs;
+// every output is summed over K in the same order, so both give the same
+// results.  While *choice < 0, runs alternate the shapes under HIP events;
+// after TUNE_CALLS runs of each, the faster one is written to *choice (which
+// outlives the op, so later set-ups reuse it) and used from then on.
+class TunedGemm {
+ public:
+  static constexpr int TUNE_CALLS = 3;
+  GemmOp v[2];
+  int* choice = nullptr;   // -1: still measuring; null: always v[0]
+  TunedGemm() { v[1].narrow = true; }
+  TunedGemm(const TunedGemm&) = delete;
+  TunedGemm& operator=(const TunedGemm&) = delete;
+  ~TunedGemm() { drop_events(); }
+  void reset() {           // empty both shapes, keep the choice pointer
+    drop_events();
+    v[0] = GemmOp();
+    v[1] = GemmOp();
+    v[1].narrow = true;
+    calls = 0;
+  }
+  void set_act(const int* a) { v[0].act = v[1].act = a; }
+  void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
+           int K, const int* flag = nullptr, const int* spair = nullptr, int scols = 0) {
+    for (auto& g : v) g.add(A, lda, B, ldb, C, ldc, M, N, K, flag, spair, scols);
+  }
+  void finalize(hipStream_t st) {
+    v[0].finalize(st);
+    if (choice) v[1].finalize(st);
+  }
+  void run(double alpha, double beta, hipStream_t st);
+
+ private:
+  int calls = 0;
+  std::vector<hipEvent_t> ev[2];
+  void drop_events();
+};
+
 struct GemvDesc {
   const void* A;    // K x M double block, column-major; after pack_a_f32 the
                     // transposed M x K float copy in row panels

@@ -205,27 +205,7 @@ void launch_csr_values(const CsrMaps& m, const int* edofs, int ne, const double*
   AMB_LAUNCH_CHECK();
 }
 
-// y = K x for nrhs columns (ld = n): one thread per row.
-template <int R>
-__global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rowptr,
-                                              const int* __restrict__ cols,
-                                              const double* __restrict__ vals,
-                                              const double* __restrict__ x, double* y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const double v = vals[k];
-    const int c = cols[k];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += v * x[c + (size_t)r * n];
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) y[i + (size_t)r * n] = acc[r];
-}
-
+// y = K x for any number of right-hand sides (ld = n): one thread per row.
 __global__ __launch_bounds__(256) void k_spmv_any(int n, int nrhs, const int* __restrict__ rowptr,
                                                   const int* __restrict__ cols,
                                                   const double* __restrict__ vals,
@@ -239,17 +219,61 @@ __global__ __launch_bounds__(256) void k_spmv_any(int n, int nrhs, const int* __
   }
 }
 
+// y = K x with G lanes per row (G divides 64, rows aligned to groups of G
+// lanes): the lanes read consecutive entries of the row, so a wave's loads of
+// the values and column indices are contiguous, and the group sums with
+// shuffles.  Used for rows of more than a few entries (27 for Poisson, 81 for
+// elasticity).
+template <int R, int G>
+__global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rowptr,
+                                                const int* __restrict__ cols,
+                                                const double* __restrict__ vals,
+                                                const double* __restrict__ x, double* y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / G, lane = t % G;
+  if (i >= n) return;   // whole groups leave together
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  const int k1 = rowptr[i + 1];
+  for (int k = rowptr[i] + lane; k < k1; k += G) {
+    const double v = vals[k];
+    const int c = cols[k];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += v * x[c + (size_t)r * n];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += __shfl_xor(acc[r], o);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (lane == r % G) y[i + (size_t)r * n] = acc[r];
+}
+
+template <int G>
+static void spmv_g(const CsrMaps& m, const double* vals, const double* x, double* y, int nrhs,
+                   hipStream_t st) {
+  const int g = ceil_div(m.n, 256 / G);
+  switch (nrhs) {
+    case 1: k_spmv_g<1, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
+    case 2: k_spmv_g<2, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
+    case 4: k_spmv_g<4, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
+    case 8: k_spmv_g<8, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
+    case 16: k_spmv_g<16, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
+    default:
+      k_spmv_any<<<ceil_div(m.n, 256), 256, 0, st>>>(m.n, nrhs, m.rowptr.p, m.cols.p, vals, x, y);
+  }
+}
+
 void launch_spmv(const CsrMaps& m, const double* vals, const double* x, double* y, int nrhs,
                  hipStream_t st) {
-  const int g = ceil_div(m.n, 256);
-  switch (nrhs) {
-    case 1: k_spmv<1><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 2: k_spmv<2><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 4: k_spmv<4><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 8: k_spmv<8><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 16: k_spmv<16><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    default: k_spmv_any<<<g, 256, 0, st>>>(m.n, nrhs, m.rowptr.p, m.cols.p, vals, x, y);
-  }
+  if (m.n == 0) return;
+  // lanes per row from the mean row length
+  const double avg = double(m.nnz) / m.n;
+  if (avg > 48.0) spmv_g<32>(m, vals, x, y, nrhs, st);
+  else if (avg > 12.0) spmv_g<16>(m, vals, x, y, nrhs, st);
+  else spmv_g<4>(m, vals, x, y, nrhs, st);
   AMB_LAUNCH_CHECK();
 }
 

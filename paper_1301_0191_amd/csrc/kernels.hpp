@@ -19,6 +19,7 @@ struct AssemblyMaps {
 
 struct CsrMaps {
   int n = 0;
+  int64_t nnz = 0;
   DBuf<int> rowptr, cols;
   DBuf<int64_t> inc_ptr;
   DBuf<int> inc_e, inc_a;
@@ -68,10 +69,15 @@ struct NeuDesc {
   const double* C;  int nc;    // C^s (nc x nG, ld nc)
   double* A;        int lda;   // augmented matrix of order 2(nG+nc)
   int nG;
-  const double* rho;           // scalar on device
+  const double* rho;           // scalar on device (unused by the fill)
   int col_start;
 };
+// Fills [[S, C^T, I, 0], [C, 0, 0, I], [I, 0, 0, 0], [0, I, 0, 0]] (the
+// rho C^T C term of the (1,1) block is added separately).
 void launch_neumann_fill(const NeuDesc* d, int nd, int ncols, hipStream_t st);
+// dst = sqrt(scale[s]) src on the entries [off[s], off[s] + cnt[s]) of every s
+void launch_scale_sqrt_sub(int nsub, const int64_t* off, const int64_t* cnt, const double* scale,
+                           const double* src, double* dst, hipStream_t st);
 void launch_diag_mean(int nsub, const int64_t* off, const int* ld, const int* n0, const int* n,
                       const double* A, double* out, hipStream_t st);
 // K_c^s = trailing(n_G: , n_G:) - rho I  copied compact

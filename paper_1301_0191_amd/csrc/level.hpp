@@ -37,6 +37,9 @@ struct Level {
   LdltOp ldl_naug;
   SymOp sym_naug;
   GemvOp g2, g3;
+  DBuf<double> Cs;                // sqrt(rho_s) C^s
+  DBuf<int64_t> d_c_off, d_c_cnt;
+  GemmOp gcc;                     // rho C^T C added to the (1,1) Neumann block
 
   // FP32 copies of the g1..g4 operators (precision 1)
   DBuf<float> g1_32, g2_32, g3_32, g4_32;

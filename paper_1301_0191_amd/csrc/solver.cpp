@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -104,6 +105,7 @@ struct ambddc_ctx {
   bool ready = false;
   ambddc_stats stats{};
   KTimer kt;   // optional per-class kernel timing
+  std::map<std::string, int> tune;   // tile-shape choices of tuned products (-1: measuring)
   std::vector<double> last_res;   // true relative residuals of the last solve
   DBuf<double> coeff_buf, mis_part, mis_out;   // log10 set-up and misfit workspace
   // PCG workspace
@@ -366,6 +368,26 @@ void build_constraint_maps(ambddc_ctx& c, Level& L) {
   L.neu.upload(nd, st);
   L.ldl_naug.finalize(st);
   L.sym_naug.finalize(st);
+  // rho_s C^T C = (sqrt(rho_s) C)^T (sqrt(rho_s) C) on MFMA, added to S in place
+  L.Cs.alloc(size_t(std::max<int64_t>(L.c_total, 1)));
+  {
+    std::vector<int64_t> co(ns), cn(ns);
+    for (int s = 0; s < ns; ++s) {
+      co[s] = L.c_off[s];
+      cn[s] = int64_t(L.nc[s]) * L.nG[s];
+    }
+    L.d_c_off.upload(co, st);
+    L.d_c_cnt.upload(cn, st);
+  }
+  L.gcc = GemmOp();
+  L.gcc.ta = true;
+  for (int s = 0; s < ns; ++s) {
+    if (L.nc[s] == 0) continue;
+    const double* cs = L.Cs.p + L.c_off[s];
+    L.gcc.add(cs, L.nc[s], cs, L.nc[s], L.naug.p + L.naug_off[s], L.naugN[s], L.nG[s], L.nG[s],
+              L.nc[s]);
+  }
+  L.gcc.finalize(st);
   alloc_coarse_workspace(L, std::max(L.nrhs_cap, 1));
 }
 
@@ -426,6 +448,8 @@ void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
   }
   L.naug.zero(st);
   launch_neumann_fill(L.neu.p, L.nsub, L.neu_cols, st);
+  launch_scale_sqrt_sub(L.nsub, L.d_c_off.p, L.d_c_cnt.p, L.rho.p, L.C.p, L.Cs.p, st);
+  L.gcc.run(1.0, 1.0, st);
   L.ldl_naug.run(st);
   check_ldlt(L.ldl_naug, st, "constrained Neumann factorisation", li);
   L.sym_naug.run(st);
@@ -448,13 +472,14 @@ struct PairWork {
   PairIdx idx;
   DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw, Nb, Aug;
   DBuf<int> active, kout, nnull, slot_pair;
-  GemmOp gS, gM1, gM2, gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
+  TunedGemm gS, gM1, gM2;   // grouped per-subdomain products, tile shape tuned
+  GemmOp gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
   KTimer* kt = nullptr;
   std::vector<int> act;                          // host copy of the active flags
   std::vector<int> h_slot_off, h_slot_pair;      // pair of every subdomain slot
 };
 
-void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
+void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   hipStream_t st = c.st;
   const LevelPlan& P = L.plan;
   const int m = W.m;
@@ -586,8 +611,15 @@ void build_pair_work(ambddc_ctx& c, Level& L, PairWork& W) {
   W.slot_pair.upload(slot_pair, st);
   W.h_slot_off = slot_off;
   W.h_slot_pair = slot_pair;
-  W.gS = GemmOp(); W.gM1 = GemmOp(); W.gM2 = GemmOp();
-  W.gS.act = W.gM1.act = W.gM2.act = W.active.p;
+  // tile shapes: measured on the first set-up of the handle, then reused
+  const std::string lk = "L" + std::to_string(li) + ".";
+  W.gS.reset(); W.gM1.reset(); W.gM2.reset();
+  W.gS.choice = &c.tune.emplace(lk + "S", -1).first->second;
+  W.gM1.choice = &c.tune.emplace(lk + "Z", -1).first->second;
+  W.gM2.choice = &c.tune.emplace(lk + "Psi", -1).first->second;
+  W.gS.set_act(W.active.p);
+  W.gM1.set_act(W.active.p);
+  W.gM2.set_act(W.active.p);
   for (int s = 0; s < L.nsub; ++s) {
     const int cols = P.sub_npairs[s] * 2 * m;
     if (cols == 0) continue;
@@ -788,7 +820,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   if (W.m > 16) throw Error(AMBDDC_E_INVALID_ARG, "lobpcg_block larger than 16 is not supported");
   L.m = W.m;
   W.kt = &c.kt;
-  build_pair_work(c, L, W);
+  build_pair_work(c, L, li, W);
   if (W.np == 0) {
     L.omega = 0.0;
     return;
@@ -1352,6 +1384,7 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
           incp[fi + 1] = int64_t(ie.size());
         }
       c->csr.n = nf;
+      c->csr.nnz = int64_t(cols.size());
       c->csr.rowptr.upload(rowptr, st);
       c->csr.cols.upload(cols, st);
       c->csr.inc_ptr.upload(incp, st);
