@@ -149,7 +149,7 @@ struct LdltDesc {
 class LdltOp {
  public:
   static constexpr int NB = 32;     // panel width
-  static constexpr int OB = 128;    // outer block: columns per full trailing update
+  static constexpr int OB = 256;    // outer block: columns per full trailing update
   static constexpr int TILE = 64;   // trailing update tile
   static constexpr int ROWS = 256;  // panel rows per workgroup
   std::vector<LdltDesc> h;
