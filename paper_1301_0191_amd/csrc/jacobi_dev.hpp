@@ -38,11 +38,8 @@ __device__ inline void jac_pair(int k, int rr, int np, int mm, int n, int& p, in
 // V: n x n (ld ldv) receives the eigenvectors (columns).  Odd lda and ldv
 // keep the LDS accesses free of bank conflicts.  work: JAC_WORK doubles.
 // n <= JAC_MAXN, blockDim = 32 * TPP, TPP in {8, 16, 32}.
-// The sweeps stop once the off-diagonal Frobenius norm is at most
-// sqrt(tol2) times the diagonal one (tol2 >= 1e-30).
 template <int TPP>
-__device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n, double* work,
-                                  double tol2) {
+__device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n, double* work) {
   constexpr int RPT = JAC_MAXN / TPP;   // rows (columns) per thread
   constexpr int NW = TPP / 2;           // waves
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -169,7 +166,7 @@ __device__ inline void jacobi_lds(double* A, int lda, double* V, int ldv, int n,
     if (acc) {
       double to = 0.0, td = 0.0;
       for (int w = 0; w < NW; ++w) { to += red[2 * w]; td += red[2 * w + 1]; }
-      stop = (to <= tol2 * td || to == 0.0);
+      stop = (to <= 1e-30 * td || to == 0.0);
     }
     __syncthreads();
     if (stop) break;

@@ -400,8 +400,7 @@ __device__ inline unsigned long long rr_key(double v, int i) {
 }
 
 __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const double* GB, int nb, int m,
-                                            double* Cf2, double* lam, const int* active,
-                                            const double* resn) {
+                                            double* Cf2, double* lam, const int* active) {
   extern __shared__ double sm[];
   if (active && !active[blockIdx.x]) return;
   const int M3 = 3 * m;
@@ -574,16 +573,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
   __syncthreads();
   double* Y = F;
   const int ly = r | 1;
-  // Jacobi accuracy: 1e-2 of the pair's smallest current column residual
-  // (its most accurate Ritz pair, which must not be disturbed), between
-  // 1e-15 and 1e-6; full accuracy when no residuals are known yet
-  double tolj = 1e-15;
-  if (resn) {
-    double rmin = 1e300;
-    for (int c = 0; c < m; ++c) rmin = fmin(rmin, resn[(size_t)blockIdx.x * m + c]);
-    tolj = fmin(1e-6, fmax(1e-15, 1e-2 * rmin));
-  }
-  jacobi_lds<RR_THREADS / 32>(J, lr, Y, ly, r, work, tolj * tolj);
+  jacobi_lds<RR_THREADS / 32>(J, lr, Y, ly, r, work);
   sort_desc_lds(J, lr, r, perm);
   const int mm = min(m, r);
   double* cf = Cf2 + (size_t)blockIdx.x * M3 * 2 * m;
@@ -607,11 +597,11 @@ size_t rr_smem(int nb) {
 }
 
 void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,
-           double* Cf, double* lam, const int* active, const double* resn, hipStream_t st) {
+           double* Cf, double* lam, const int* active, hipStream_t st) {
   (void)P;
   if (np == 0) return;
   if (nb > 48 || nb < 1) throw Error(1, "Rayleigh-Ritz block larger than 48");
-  k_rr<<<np, RR_THREADS, rr_smem(nb), st>>>(GA, GB, nb, m, Cf, lam, active, resn);
+  k_rr<<<np, RR_THREADS, rr_smem(nb), st>>>(GA, GB, nb, m, Cf, lam, active);
   AMB_LAUNCH_CHECK();
 }
 

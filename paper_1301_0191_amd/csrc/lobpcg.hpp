@@ -64,11 +64,8 @@ void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V,
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,
                  const double* lam, int m, int nconv, double tol, int* active, double* resn,
                  hipStream_t st);
-// resn (np x m, or null): the pairs' current column residuals; the Jacobi
-// eigensolver then stops at 1e-2 of the smallest of them (within [1e-15,
-// 1e-6]) instead of 1e-15.
 void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,
-           double* Cf, double* lam, const int* active, const double* resn, hipStream_t st);
+           double* Cf, double* lam, const int* active, hipStream_t st);
 void lp_commit(const PairDev* P, int np, double* V, double* AV, double* BV, const double* T,
                int m, bool with_p, bool only_v, const int* active, hipStream_t st);
 void lp_pair_coarse(const PairDev* P, int np, const double* kc, const int64_t* kc_off,

@@ -787,14 +787,12 @@ void rayleigh_ritz(Level& L, PairWork& W, int v, bool with_p, hipStream_t st) {
     W.gram_b[v].run(1.0, 0.0, st);
     W.kt->end("pair_gram", st, fg, bg);
     W.kt->begin("pair_rr", st);
-    lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p,
-          v == 0 ? nullptr : W.resn.p, st);
+    lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
     W.kt->end("pair_rr", st, frr, brr);
   } else {
     W.gram_a[v].run(1.0, 0.0, st);
     W.gram_b[v].run(1.0, 0.0, st);
-    lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p,
-          v == 0 ? nullptr : W.resn.p, st);
+    lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
   }
   W.upd_v[v].run(1.0, 0.0, st);
   lp_commit(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.T.p, W.m, with_p, true, W.active.p, st);
