@@ -75,9 +75,12 @@ def traffic_for(kernel_key):
     if not rec:
         return None
     h = hashlib.sha256()
-    for rel in rec["sources"]:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    try:
+        for rel in rec["sources"]:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
     if h.hexdigest() != rec["sources_sha256"]:
         return None
     return rec["bytes_per_launch"]
