@@ -11,7 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "jacobi_dev.hpp"
+#include "rr_eig.hpp"
 #include "lobpcg.hpp"
 
 namespace ambddc {
@@ -380,8 +380,10 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // while the same row operations are accumulated in F (F <- E F, starting
 // from I).  With the pivot rows of F scaled by b_pp^{-1/2} and by D,
 // Fc (r x nb) satisfies Fc GB Fc^T = I, and A_r = Fc GA Fc^T (two small
-// products) is diagonalised by Jacobi.  The Ritz coefficients are Fc^T Y,
-// eigenvalues descending; Cf2 (ld 3m) holds the first m of them (columns
+// products) gives its m largest eigenpairs (Y, descending) by tridiagonal
+// reduction, multisection and inverse iteration (rr_eig.hpp), which only
+// computes the vectors that are kept.  The Ritz coefficients are Fc^T Y;
+// Cf2 (ld 3m) holds the first m of them (columns
 // 0..m-1) and the same with the X rows zeroed (columns m..2m-1, giving the
 // new P).
 //
@@ -391,7 +393,7 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // pivot rows are never touched again (their scaling is applied at the end).
 // The next pivot is found with a 64-bit LDS max over keys (diagonal value
 // with its low 6 bits replaced by 63 - index), in a ring of three slots.
-constexpr int RR_THREADS = 1024;   // 16 waves; 32 threads per Jacobi pair
+constexpr int RR_THREADS = 1024;   // 16 waves (one per wanted eigenpair, m <= 16)
 constexpr int RR_COLS = 3;         // columns per wave (nb <= 48)
 
 __device__ inline unsigned long long rr_key(double v, int i) {
@@ -412,10 +414,10 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
   double* F = B + nb * ld;        // F (nb x nb, ld); later GA Fc^T, then Y
   double* dsc = F + nb * ld;      // nb
   double* rs = dsc + nb;          // nb
-  double* work = rs + nb;         // JAC_WORK
-  unsigned long long* key = reinterpret_cast<unsigned long long*>(work + JAC_WORK);   // 3
+  double* eigws = rs + nb;        // EIG_WS
+  double* elam = eigws + EIG_WS;  // EIG_MAXN
+  unsigned long long* key = reinterpret_cast<unsigned long long*>(elam + EIG_MAXN);   // 3
   int* piv = reinterpret_cast<int*>(key + 3);   // nb
-  int* perm = piv + nb;                          // nb
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nw = nt >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < nb; i += nt) {
@@ -573,27 +575,26 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
   __syncthreads();
   double* Y = F;
   const int ly = r | 1;
-  jacobi_lds<RR_THREADS / 32>(J, lr, Y, ly, r, work);
-  sort_desc_lds(J, lr, r, perm);
   const int mm = min(m, r);
+  sym_top_eig<RR_THREADS>(J, lr, r, mm, Y, ly, elam, eigws);
   double* cf = Cf2 + (size_t)blockIdx.x * M3 * 2 * m;
   for (int idx = tid; idx < nb * m; idx += nt) {
     const int ii = idx % nb, c = idx / nb;
     double v = 0.0;
     if (c < mm) {
-      const double* y = Y + perm[c] * ly;
+      const double* y = Y + c * ly;
       for (int l = 0; l < r; ++l) v += Fc[l + ii * ld] * y[l];
     }
     cf[ii + (size_t)c * M3] = v;
     cf[ii + (size_t)(c + m) * M3] = (ii < m) ? 0.0 : v;
   }
   for (int c = tid; c < m; c += nt)
-    lam[(size_t)blockIdx.x * m + c] = c < mm ? J[perm[c] + perm[c] * lr] : 0.0;
+    lam[(size_t)blockIdx.x * m + c] = c < mm ? elam[c] : 0.0;
 }
 
 size_t rr_smem(int nb) {
   const int ld = nb | 1;
-  return sizeof(double) * (3 * nb * ld + 2 * nb + JAC_WORK + 3) + sizeof(int) * (2 * nb);
+  return sizeof(double) * (3 * nb * ld + 2 * nb + EIG_WS + EIG_MAXN + 3) + sizeof(int) * nb;
 }
 
 void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,
