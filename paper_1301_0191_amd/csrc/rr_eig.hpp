@@ -11,12 +11,12 @@
 //    interior points of the current interval, and the ballot of
 //    "count >= target" picks the sub-interval (a factor EIG_MSP + 1 a pass).
 //    d and e^2 sit one entry per lane and are read with readlane.
-// 3. Their eigenvectors of T by inverse iteration (LU of T - lambda I with
-//    partial pivoting, row i of the factors kept by lane i; two solves),
-//    re-orthogonalised against the earlier members of their cluster
-//    (eigenvalues closer than EIG_CTOL ||T||).  Members are processed in
-//    rounds, the r-th member of every cluster in round r, one wave per member,
-//    so that a vector's predecessors are final before it starts.
+// 3. Their eigenvectors of T by inverse iteration, one wave per eigenvalue,
+//    all at once (LU of T - lambda I with partial pivoting, row i of the
+//    factors kept by lane i; two solves).  After each solve the vectors of
+//    every cluster (eigenvalues closer than EIG_CTOL ||T||) are orthonormalised
+//    by modified Gram-Schmidt in eigenvalue order; the step count is the
+//    largest cluster size, all clusters proceed together.
 // 4. The back-transformation y = H_0 H_1 ... H_{n-3} z, one wave per vector.
 // Wave reductions use DPP row operations and one readlane.
 #pragma once
@@ -194,108 +194,108 @@ __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, 
   }
   __syncthreads();
 
-  // 3. inverse iteration in rounds over the clusters
+  // 3. inverse iteration, one wave per wanted eigenvalue, all at once
   const double ctol = EIG_CTOL * tnorm;
   const double tiny = EPS * fmax(tnorm, 1e-300);
-  int rounds = 1;
+  // rank of this wave's member in its cluster and the cluster's first member
+  int rank = 0, cs = 0, rounds = 1;
   {
-    int rk = 0;
-    for (int j = 1; j < mm; ++j) {
-      rk = (lam[j - 1] - lam[j] <= ctol) ? rk + 1 : 0;
+    int rk = 0, start = 0;
+    for (int i = 0; i < mm; ++i) {
+      if (i > 0 && lam[i - 1] - lam[i] <= ctol) rk += 1;
+      else { rk = 0; start = i; }
       rounds = max(rounds, rk + 1);
+      if (i == wave) { rank = rk; cs = start; }
     }
   }
-  for (int round = 0; round < rounds; ++round) {
-    // the member of this round handled by this wave
-    int j = -1, cs = 0;
-    {
-      int rk = 0, cnt = 0, start = 0;
-      for (int i = 0; i < mm; ++i) {
-        if (i > 0 && lam[i - 1] - lam[i] <= ctol) rk += 1;
-        else { rk = 0; start = i; }
-        if (rk == round) {
-          if (cnt == wave) { j = i; cs = start; }
-          ++cnt;
-        }
+  const int j = wave;
+  const bool member = j < mm;
+  // LU of T - lam_j I with partial pivoting: a chain that every lane runs
+  // alike; lane i keeps row i (reciprocal pivot, the two entries right of
+  // it, multiplier, row swap)
+  double myDi = 0.0, myU1 = 0.0, myU2 = 0.0, myL = 0.0;
+  int mySw = 0;
+  double yv = 0.0;
+  if (member) {
+    const double lj = lam[j];
+    double diag = rl(dl, 0) - lj, sup = n > 1 ? rl(el, 0) : 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double sub_ = rl(el, i), nd = rl(dl, i + 1) - lj;
+      const double nsup = (i + 2 < n) ? rl(el, i + 1) : 0.0;
+      double Di, U1i, U2i, Li;
+      int sw = 0;
+      if (fabs(diag) >= fabs(sub_)) {
+        Di = fabs(diag) >= tiny ? diag : (diag >= 0.0 ? tiny : -tiny);
+        Li = sub_ * rcp_nr(Di);
+        U1i = sup;
+        U2i = 0.0;
+        diag = nd - Li * sup;
+        sup = nsup;
+      } else {
+        Di = sub_;
+        Li = diag * rcp_nr(sub_);
+        U1i = nd;
+        U2i = nsup;
+        sw = 1;
+        diag = sup - Li * nd;
+        sup = -Li * nsup;
+      }
+      if (lane == i) {
+        myDi = rcp_nr(Di);
+        myU1 = U1i;
+        myU2 = U2i;
+        myL = Li;
+        mySw = sw;
       }
     }
-    if (j >= 0) {
-      const double lj = lam[j];
-      // LU of T - lj I with partial pivoting: a uniform chain; lane i keeps
-      // row i (reciprocal pivot, the two superdiagonal entries, multiplier,
-      // row swap)
-      double myDi = 0.0, myU1 = 0.0, myU2 = 0.0, myL = 0.0;
-      int mySw = 0;
-      {
-        double diag = rl(dl, 0) - lj, sup = n > 1 ? rl(el, 0) : 0.0;
-        for (int i = 0; i + 1 < n; ++i) {
-          const double sub_ = rl(el, i), nd = rl(dl, i + 1) - lj;
-          const double nsup = (i + 2 < n) ? rl(el, i + 1) : 0.0;
-          double Di, U1i, U2i, Li;
-          int sw = 0;
-          if (fabs(diag) >= fabs(sub_)) {
-            Di = fabs(diag) >= tiny ? diag : (diag >= 0.0 ? tiny : -tiny);
-            Li = sub_ * rcp_nr(Di);
-            U1i = sup;
-            U2i = 0.0;
-            diag = nd - Li * sup;
-            sup = nsup;
-          } else {
-            Di = sub_;
-            Li = diag * rcp_nr(sub_);
-            U1i = nd;
-            U2i = nsup;
-            sw = 1;
-            diag = sup - Li * nd;
-            sup = -Li * nsup;
-          }
-          if (lane == i) {
-            myDi = rcp_nr(Di);
-            myU1 = U1i;
-            myU2 = U2i;
-            myL = Li;
-            mySw = sw;
-          }
+    if (lane == n - 1) myDi = rcp_nr(fabs(diag) >= tiny ? diag : (diag >= 0.0 ? tiny : -tiny));
+    // start vector: positive, different for every member (members of a
+    // multiple eigenvalue must not start from the same direction)
+    yv = lane < n ? 1.0 + double((lane * 37 + j * 11) % 17) / 17.0 : 0.0;
+    yv *= rsqrt(wave_sum(yv * yv));
+  }
+  for (int it = 0; it < 2; ++it) {
+    if (member) {
+      // forward elimination of the right-hand side; lane i keeps x_i
+      double xi = rl(yv, 0);
+      for (int i = 0; i + 1 < n; ++i) {
+        double xn = rl(yv, i + 1);
+        if (__builtin_amdgcn_readlane(mySw, i)) {
+          const double t = xi;
+          xi = xn;
+          xn = t;
         }
-        if (lane == n - 1) myDi = rcp_nr(fabs(diag) >= tiny ? diag : (diag >= 0.0 ? tiny : -tiny));
+        if (lane == i) yv = xi;
+        xi = xn - rl(myL, i) * xi;
       }
-      // start vector: positive, different for every member (members of a
-      // multiple eigenvalue must not start from the same direction)
-      double yv = lane < n ? 1.0 + double((lane * 37 + j * 11) % 17) / 17.0 : 0.0;
+      if (lane == n - 1) yv = xi;
+      // back substitution
+      double z1 = 0.0, z2 = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        const double z = (rl(yv, i) - rl(myU1, i) * z1 - rl(myU2, i) * z2) * rl(myDi, i);
+        if (lane == i) yv = z;
+        z2 = z1;
+        z1 = z;
+      }
+      // scale to unit norm before the Gram-Schmidt products
       yv *= rsqrt(wave_sum(yv * yv));
-      for (int it = 0; it < 2; ++it) {
-        // forward elimination of the right-hand side; lane i keeps x_i
-        double xi = rl(yv, 0);
-        for (int i = 0; i + 1 < n; ++i) {
-          double xn = rl(yv, i + 1);
-          if (__builtin_amdgcn_readlane(mySw, i)) {
-            const double t = xi;
-            xi = xn;
-            xn = t;
-          }
-          if (lane == i) yv = xi;
-          xi = xn - rl(myL, i) * xi;
-        }
-        if (lane == n - 1) yv = xi;
-        // back substitution
-        double z1 = 0.0, z2 = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-          const double z = (rl(yv, i) - rl(myU1, i) * z1 - rl(myU2, i) * z2) * rl(myDi, i);
-          if (lane == i) yv = z;
-          z2 = z1;
-          z1 = z;
-        }
-        // re-orthogonalise against the finished members of the cluster
-        for (int i = cs; i < j; ++i) {
-          const double yi = lane < n ? Y[lane + (size_t)i * ldy] : 0.0;
-          yv -= wave_sum(yi * yv) * yi;
-        }
-        yv *= rsqrt(wave_sum(yv * yv));
-      }
-      if (lane < n) Y[lane + (size_t)j * ldy] = yv;
     }
-    __syncthreads();
+    // modified Gram-Schmidt inside every cluster, all clusters at once: in
+    // step r the member of rank r is normalised and published, then every
+    // later member of its cluster removes its component
+    for (int r = 0; r < rounds; ++r) {
+      if (member && rank == r) {
+        yv *= rsqrt(wave_sum(yv * yv));
+        if (lane < n) Y[lane + (size_t)j * ldy] = yv;
+      }
+      __syncthreads();
+      if (member && rank > r) {
+        const double yi = lane < n ? Y[lane + (size_t)(cs + r) * ldy] : 0.0;
+        yv -= wave_sum(yi * yv) * yi;
+      }
+    }
   }
+  __syncthreads();
 
   // 4. back-transformation by the reflectors
   if (wave < mm) {
