@@ -391,14 +391,17 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // barrier per step.  A row of F that is not yet a pivot is nonzero only in
 // the columns of earlier pivots and its own, so only those are updated;
 // pivot rows are never touched again (their scaling is applied at the end).
-// The next pivot is found with a 64-bit LDS max over keys (diagonal value
-// with its low 6 bits replaced by 63 - index), in a ring of three slots.
+// The next pivot is the largest key (diagonal value with its low 6 bits
+// replaced by 63 - index; a positive double whose order is that of the
+// values, ties broken by index): every row's key sits in an LDS array, double
+// buffered across steps, and every wave takes the maximum with DPP.
 constexpr int RR_THREADS = 1024;   // 16 waves (one per wanted eigenpair, m <= 16)
 constexpr int RR_COLS = 3;         // columns per wave (nb <= 48)
 
-__device__ inline unsigned long long rr_key(double v, int i) {
-  if (!(v > 0.0)) return 0ull;
-  return ((unsigned long long)__double_as_longlong(v) & ~63ull) | (unsigned long long)(63 - i);
+__device__ inline double rr_key(double v, int i) {
+  if (!(v > 0.0)) return 0.0;
+  return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(v) & ~63ull) |
+                                          (unsigned long long)(63 - i)));
 }
 
 __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const double* GB, int nb, int m,
@@ -416,15 +419,15 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
   double* rs = dsc + nb;          // nb
   double* eigws = rs + nb;        // EIG_WS
   double* elam = eigws + EIG_WS;  // EIG_MAXN
-  unsigned long long* key = reinterpret_cast<unsigned long long*>(elam + EIG_MAXN);   // 3
-  int* piv = reinterpret_cast<int*>(key + 3);   // nb
+  double* key = elam + EIG_MAXN;  // 2 x 64: row keys, double buffered
+  double* pinv = key + 128;       // nb: 1 / pivot, in pivot order
+  int* piv = reinterpret_cast<int*>(pinv + nb);   // nb
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nw = nt >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < nb; i += nt) {
     const double d = gb[i + (size_t)i * nb];
     dsc[i] = d > 1e-300 ? 1.0 / sqrt(d) : 0.0;
   }
-  if (tid < 3) key[tid] = 0ull;
   for (int idx = tid; idx < nb * nb; idx += nt) {
     const int i = idx % nb, k = idx / nb;
     A[i + k * ld] = ga[idx];
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
       if (i < nb) {
         A[i + k * ld] = sa[u];
         B[i + k * ld] = sb[u];
-        if (i == k) atomicMax(&key[0], rr_key(sb[u], i));
+        if (i == k) key[i] = rr_key(sb[u], i);
       }
     }
   }
@@ -461,16 +464,14 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
   uint64_t done = 0;
   int r = 0;
   for (int j = 0; j < nb; ++j) {
-    const unsigned long long kv = key[j % 3];   // the same for every lane
-    const unsigned long long kj =
-        ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(kv >> 32)) << 32) |
-        (unsigned)__builtin_amdgcn_readfirstlane((int)(kv & 0xffffffffu));
+    const double* kcur = key + 64 * (j & 1);
+    double* knext = key + 64 * ((j + 1) & 1);
+    const double kd = wave_max(lane < nb ? kcur[lane] : 0.0);   // the same for every lane
+    const unsigned long long kj = (unsigned long long)__double_as_longlong(kd);
     const double vj = __longlong_as_double((long long)(kj & ~63ull));
     if (kj == 0ull || !(vj > 1e-12)) break;
     const int p = 63 - (int)(kj & 63ull);
     const double inv = 1.0 / B[p + p * ld];
-    unsigned long long* kn = key + (j + 1) % 3;
-    if (tid == 0) key[(j + 2) % 3] = 0ull;
     const int i = lane;
     const bool row = i < nb && i != p && !((done >> i) & 1ull);
     const double gi = row ? B[i + p * ld] * inv : 0.0;
@@ -486,22 +487,28 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
         if (row) x[u] = M[i + k * ld];
       }
     }
+    double dnew = 0.0;
     if (row) {
 #pragma unroll
       for (int u = 0; u < RR_COLS; ++u) {
         const int k = wave + u * nw;
         if (k < nb) {
           double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
-          M[i + k * ld] = x[u] - gi * y[u];
+          const double v = x[u] - gi * y[u];
+          M[i + k * ld] = v;
+          if (k == i) dnew = v;
         }
       }
-      if (i % nw == wave) atomicMax(kn, rr_key(B[i + i * ld], i));
     }
-    if (tid == 0) { piv[j] = p; rs[p] = sqrt(inv); }
+    // the owner of column i publishes row i's key for the next step
+    if (i < nb && i % nw == wave) knext[i] = row ? rr_key(dnew, i) : 0.0;
+    if (tid == 0) { piv[j] = p; pinv[j] = inv; }
     done |= 1ull << p;
     r = j + 1;
     __syncthreads();
   }
+  for (int l = tid; l < r; l += nt) rs[piv[l]] = sqrt(pinv[l]);
+  __syncthreads();
   // Fc[l, k] = rs_p dsc_k F[p, k], p = piv[l] (column-major, ld)
   double* Fc = B;
   for (int idx = tid; idx < r * nb; idx += nt) {
@@ -594,7 +601,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
 
 size_t rr_smem(int nb) {
   const int ld = nb | 1;
-  return sizeof(double) * (3 * nb * ld + 2 * nb + EIG_WS + EIG_MAXN + 3) + sizeof(int) * nb;
+  return sizeof(double) * (3 * nb * ld + 3 * nb + EIG_WS + EIG_MAXN + 128) + sizeof(int) * nb;
 }
 
 void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,

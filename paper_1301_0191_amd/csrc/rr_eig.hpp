@@ -4,7 +4,7 @@
 // 1. Householder reduction to tridiagonal form T = Q^T A Q: for k = 0..n-3 the
 //    reflector H_k = I - tau_k u_k u_k^T (u_k[0] = 1) annihilates A[k+2:, k];
 //    with p = tau A22 u and w = p - (tau/2)(u.p) u the trailing block becomes
-//    A22 - u w^T - w u^T.  u_k is kept in A[k+1:, k].  Three barriers a step.
+//    A22 - u w^T - w u^T.  u_k is kept in A[k+1:, k].  Two barriers a step.
 // 2. The mm largest eigenvalues of T by multisection: a group of EIG_MSP
 //    lanes per eigenvalue evaluates Sturm counts (negative pivots of the
 //    LDL^T of T - xI, with a Newton-refined hardware reciprocal) at EIG_MSP
@@ -55,6 +55,27 @@ __device__ __forceinline__ double wave_sum(double x) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_max(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = (int)(b & 0xffffffff), hi = (int)(b >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+  return fmax(x, __longlong_as_double(((long long)(unsigned)rhi << 32) | (unsigned)rlo));
+}
+// maximum over the wave, returned in every lane (no NaN inputs)
+__device__ __forceinline__ double wave_max(double x) {
+  x = dpp_max<0xb1, 0xf>(x);
+  x = dpp_max<0x4e, 0xf>(x);
+  x = dpp_max<0x141, 0xf>(x);
+  x = dpp_max<0x140, 0xf>(x);
+  x = dpp_max<0x142, 0xa>(x);
+  x = dpp_max<0x143, 0xc>(x);
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
 __device__ __forceinline__ double rl(double v, int i) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), i);
@@ -85,27 +106,34 @@ __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, 
   const int mm = min(m, n);
   if (n <= 0) return;
 
-  // 1. tridiagonal reduction
+  // 1. tridiagonal reduction.  The reflector of column k + 1 is built by
+  // wave 0 right after it has updated that column (the first elements of the
+  // rank-2 update are column k + 1, all in wave 0), so a step needs two
+  // barriers.  reflect(): x holds A[k+1+l, k] in lane l (0 from nk on).
+  auto reflect = [&](int k, int nk, double x) {
+    const double s = wave_sum((lane >= 1 && lane < nk) ? x * x : 0.0);
+    const double alpha = rl(x, 0);
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (s > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + s), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    double* col = A + (k + 1) + (size_t)k * lda;
+    if (lane < nk) col[lane] = (lane == 0) ? 1.0 : x * scale;
+    if (lane == 0) {
+      e[k] = beta;
+      tau[k] = t;
+    }
+  };
+  if (n > 2) {
+    if (wave == 0) reflect(0, n - 1, lane < n - 1 ? A[1 + lane] : 0.0);
+    __syncthreads();
+  }
   for (int k = 0; k + 2 < n; ++k) {
     const int nk = n - k - 1;
-    double* col = A + (k + 1) + (size_t)k * lda;
-    if (wave == 0) {
-      const double x = lane < nk ? col[lane] : 0.0;
-      const double s = wave_sum((lane >= 1 && lane < nk) ? x * x : 0.0);
-      const double alpha = __shfl(x, 0);
-      double t = 0.0, beta = alpha, scale = 0.0;
-      if (s > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + s), alpha);
-        t = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      if (lane < nk) col[lane] = (lane == 0) ? 1.0 : x * scale;
-      if (lane == 0) {
-        e[k] = beta;
-        tau[k] = t;
-      }
-    }
-    __syncthreads();
+    const double* col = A + (k + 1) + (size_t)k * lda;
+    const bool next = k + 3 < n;   // column k + 1 gets a reflector too
     const double tk = tau[k];
     if (tk != 0.0) {
       // p = tau A22 u with 16 lanes per row (A22 symmetric, read by columns)
@@ -119,14 +147,26 @@ __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, 
       }
       __syncthreads();
       const double K = 0.5 * tk * wave_sum(lane < nk ? col[lane] * p[lane] : 0.0);
-      for (int idx = tid; idx < nk * nk; idx += NT) {
+      auto update = [&](int idx) {
         const int i = idx % nk, j = idx / nk;
         const double ui = col[i], uj = col[j];
         const double wi = p[i] - K * ui, wj = p[j] - K * uj;
-        A[(k + 1 + i) + (size_t)(k + 1 + j) * lda] -= ui * wj + wi * uj;
+        double* a = A + (k + 1 + i) + (size_t)(k + 1 + j) * lda;
+        const double v = *a - (ui * wj + wi * uj);
+        *a = v;
+        return v;
+      };
+      // lanes i < nk of wave 0 hold the new A[k+1+i, k+1] in v0
+      const double v0 = tid < nk * nk ? update(tid) : 0.0;
+      if (wave == 0 && next) {
+        const double xn = __shfl_down(v0, 1);
+        reflect(k + 1, nk - 1, lane + 1 < nk ? xn : 0.0);
       }
-      __syncthreads();
+      for (int idx = tid + NT; idx < nk * nk; idx += NT) update(idx);
+    } else if (wave == 0 && next) {
+      reflect(k + 1, nk - 1, lane + 1 < nk ? A[(k + 2 + lane) + (size_t)(k + 1) * lda] : 0.0);
     }
+    __syncthreads();
   }
   for (int i = tid; i < n; i += NT) d[i] = A[i + (size_t)i * lda];
   if (tid == 0 && n >= 2) e[n - 2] = A[(n - 1) + (size_t)(n - 2) * lda];
