@@ -387,8 +387,9 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // 0..m-1) and the same with the X rows zeroed (columns m..2m-1, giving the
 // new P).
 //
-// Elimination: lanes are rows, each wave owns a fixed set of columns, one
-// barrier per step.  A row of F that is not yet a pivot is nonzero only in
+// Elimination: lanes are rows, each of RR_EW waves owns a fixed set of
+// columns, one barrier per step (the other waves only take the pivot
+// maximum, to leave the loop at the same step).  A row of F that is not yet a pivot is nonzero only in
 // the columns of earlier pivots and its own, so only those are updated;
 // pivot rows are never touched again (their scaling is applied at the end).
 // The next pivot is the largest key (diagonal value with its low 6 bits
@@ -396,7 +397,9 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // values, ties broken by index): every row's key sits in an LDS array, double
 // buffered across steps, and every wave takes the maximum with DPP.
 constexpr int RR_THREADS = 1024;   // 16 waves (one per wanted eigenpair, m <= 16)
-constexpr int RR_COLS = 3;         // columns per wave (nb <= 48)
+constexpr int RR_COLS = 3;         // columns per wave when all 16 waves share nb <= 48 columns
+constexpr int RR_EW = 8;           // waves that eliminate (the others only follow the pivots)
+constexpr int RR_ECOLS = 6;        // columns per eliminating wave
 
 __device__ inline double rr_key(double v, int i) {
   if (!(v > 0.0)) return 0.0;
@@ -471,38 +474,42 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
     const double vj = __longlong_as_double((long long)(kj & ~63ull));
     if (kj == 0ull || !(vj > 1e-12)) break;
     const int p = 63 - (int)(kj & 63ull);
-    const double inv = 1.0 / B[p + p * ld];
-    const int i = lane;
-    const bool row = i < nb && i != p && !((done >> i) & 1ull);
-    const double gi = row ? B[i + p * ld] * inv : 0.0;
-    // this wave's columns, batched: B columns not yet eliminated get the
-    // Schur update, F columns of earlier pivots and of p the row operation
-    double x[RR_COLS], y[RR_COLS];
+    if (wave < RR_EW) {
+      const int i = lane, ic = i < nb ? i : nb - 1;
+      const double bpp = B[p + p * ld];
+      const double bip = B[ic + p * ld];
+      // this wave's columns, batched: B columns not yet eliminated get the
+      // Schur update, F columns of earlier pivots and of p the row operation
+      double x[RR_ECOLS], y[RR_ECOLS];
 #pragma unroll
-    for (int u = 0; u < RR_COLS; ++u) {
-      const int k = wave + u * nw;
-      if (k < nb) {
-        const double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
-        y[u] = M[p + k * ld];
-        if (row) x[u] = M[i + k * ld];
-      }
-    }
-    double dnew = 0.0;
-    if (row) {
-#pragma unroll
-      for (int u = 0; u < RR_COLS; ++u) {
-        const int k = wave + u * nw;
+      for (int u = 0; u < RR_ECOLS; ++u) {
+        const int k = wave + u * RR_EW;
         if (k < nb) {
-          double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
-          const double v = x[u] - gi * y[u];
-          M[i + k * ld] = v;
-          if (k == i) dnew = v;
+          const double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
+          y[u] = M[p + k * ld];
+          x[u] = M[ic + k * ld];
         }
       }
+      const double inv = 1.0 / bpp;
+      const bool row = i < nb && i != p && !((done >> i) & 1ull);
+      const double gi = bip * inv;
+      double dnew = 0.0;
+      if (row) {
+#pragma unroll
+        for (int u = 0; u < RR_ECOLS; ++u) {
+          const int k = wave + u * RR_EW;
+          if (k < nb) {
+            double* M = (k == p || ((done >> k) & 1ull)) ? F : B;
+            const double v = x[u] - gi * y[u];
+            M[i + k * ld] = v;
+            if (k == i) dnew = v;
+          }
+        }
+      }
+      // the owner of column i publishes row i's key for the next step
+      if (i < nb && i % RR_EW == wave) knext[i] = row ? rr_key(dnew, i) : 0.0;
+      if (tid == 0) { piv[j] = p; pinv[j] = inv; }
     }
-    // the owner of column i publishes row i's key for the next step
-    if (i < nb && i % nw == wave) knext[i] = row ? rr_key(dnew, i) : 0.0;
-    if (tid == 0) { piv[j] = p; pinv[j] = inv; }
     done |= 1ull << p;
     r = j + 1;
     __syncthreads();

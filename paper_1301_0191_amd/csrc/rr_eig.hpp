@@ -9,7 +9,9 @@
 //    lanes per eigenvalue evaluates Sturm counts (negative pivots of the
 //    LDL^T of T - xI, with a Newton-refined hardware reciprocal) at EIG_MSP
 //    interior points of the current interval, and the ballot of
-//    "count >= target" picks the sub-interval (a factor EIG_MSP + 1 a pass).
+//    "count >= target" picks the sub-interval (a factor EIG_MSP + 1 a pass),
+//    down to a width of 2 eps ||T||: the reduction to tridiagonal form is
+//    backward stable at that absolute level, so more is not resolved.
 //    d and e^2 sit one entry per lane and are read with readlane.
 // 3. Their eigenvectors of T by inverse iteration, one wave per eigenvalue,
 //    all at once (LU of T - lambda I with partial pivoting, row i of the
@@ -206,7 +208,7 @@ __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, 
       const int target = n - ev;   // Sturm count >= target  <=>  x > lambda_ev
       double a = lo, b = hi;
       for (int it = 0; it < 64; ++it) {
-        const bool open = ev < mm && b - a > 2.0 * EPS * fmax(fmax(fabs(a), fabs(b)), 1e-3 * tnorm);
+        const bool open = ev < mm && b - a > 2.0 * EPS * fmax(fmax(fabs(a), fabs(b)), tnorm);
         if (!__ballot(open)) break;
         const double x = a + (b - a) * double(pl + 1) / double(EIG_MSP + 1);
         double q = rl(dl, 0) - x;
