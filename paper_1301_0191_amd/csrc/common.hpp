@@ -161,6 +161,14 @@ struct KTimer {
     cur = -1;
     cur_e = nullptr;
   }
+  // correct the work attributed to a class after the fact (for a launch that
+  // was recorded before the caller knew its exact work)
+  void amend(const char* cls, double df, double db) {
+    const int i = find(cls);
+    if (i < 0) return;
+    acc[i].flops += df;
+    acc[i].bytes += db;
+  }
   void collect() {
     for (auto& q : pend) {
       AMB_HIP(hipEventSynchronize(q.e1));

@@ -479,6 +479,33 @@ struct PairWork {
   std::vector<int> h_slot_off, h_slot_pair;      // pair of every subdomain slot
 };
 
+// Pinned host copy of the active flags, read back through an event so that
+// the stream keeps working while the host waits for it.
+struct FlagReadback {
+  int* h = nullptr;
+  hipEvent_t ev = nullptr;
+  int n = 0;
+  explicit FlagReadback(int np) : n(np) {
+    AMB_HIP(hipHostMalloc((void**)&h, sizeof(int) * std::max(np, 1), hipHostMallocDefault));
+    AMB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+  FlagReadback(const FlagReadback&) = delete;
+  FlagReadback& operator=(const FlagReadback&) = delete;
+  ~FlagReadback() {
+    if (ev) (void)hipEventSynchronize(ev);
+    if (ev) (void)hipEventDestroy(ev);
+    if (h) (void)hipHostFree(h);
+  }
+  void fetch(const int* d, hipStream_t st) {
+    AMB_HIP(hipMemcpyAsync(h, d, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    AMB_HIP(hipEventRecord(ev, st));
+  }
+  std::vector<int> wait() const {
+    AMB_HIP(hipEventSynchronize(ev));
+    return std::vector<int>(h, h + n);
+  }
+};
+
 void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   hipStream_t st = c.st;
   const LevelPlan& P = L.plan;
@@ -739,21 +766,27 @@ void pair_pinv(ambddc_ctx& c, Level& L, PairWork& W, int li) {
   W.Aug.release();
 }
 
+// Algorithmic work of S^s applied to the slots of the active pairs (W.act).
+void apply_work(const Level& L, const PairWork& W, double& fl, double& by) {
+  fl = 0.0;
+  by = 0.0;
+  for (int s = 0; s < L.nsub; ++s) {
+    int na = 0;
+    for (int j = W.h_slot_off[s]; j < W.h_slot_off[s + 1]; ++j)
+      na += (W.act.empty() || W.act[W.h_slot_pair[j]]) ? 1 : 0;
+    if (na == 0) continue;
+    const double nG = L.nG[s], c = 2.0 * W.m * na;
+    fl += 2.0 * nG * nG * c;
+    by += 8.0 * (nG * nG + 2.0 * nG * c);
+  }
+}
+
 void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
   lp_to_slab(W.dp.p, W.np, W.V.p, W.m, col, true, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
              W.active.p, st);
   if (W.kt->any()) {
-    // algorithmic work: S^s applied to the slots of the active pairs only
-    double fl = 0.0, by = 0.0;
-    for (int s = 0; s < L.nsub; ++s) {
-      int na = 0;
-      for (int j = W.h_slot_off[s]; j < W.h_slot_off[s + 1]; ++j)
-        na += (W.act.empty() || W.act[W.h_slot_pair[j]]) ? 1 : 0;
-      if (na == 0) continue;
-      const double nG = L.nG[s], c = 2.0 * W.m * na;
-      fl += 2.0 * nG * nG * c;
-      by += 8.0 * (nG * nG + 2.0 * nG * c);
-    }
+    double fl, by;
+    apply_work(L, W, fl, by);
     W.kt->begin("pair_apply", st);
     W.gS.run(1.0, 0.0, st);
     W.kt->end("pair_apply", st, fl, by);
@@ -837,6 +870,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   lp_project(W.dp.p, W.np, W.V.p, m, 0, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, nullptr, true, st);
   apply_ab(L, W, 0, st);
   rayleigh_ritz(L, W, 0, false, st);
+  FlagReadback flags(W.np);
   int it = 0;
   for (it = 1; it <= c.opt.lobpcg_maxit; ++it) {
     apply_ab(L, W, 0, st);
@@ -847,7 +881,10 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
     }
     lp_residual(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.lam.p, m, nconv, c.opt.lobpcg_tol,
                 W.active.p, W.resn.p, st);
-    if (count_active(W, st) == 0) break;
+    // The new flags travel to the host while the stream already runs the
+    // next block: every kernel and product below skips converged pairs on
+    // the device, so when no pair is left the block is launches without work.
+    flags.fetch(W.active.p, st);
     // W = M R  (eq. bddc_pair: Z^st R + Psi (Psi^T S Psi)^+ Psi^T R, then Pi and deflation)
     lp_to_slab(W.dp.p, W.np, W.V.p, m, 1, false, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
                W.active.p, st);
@@ -860,7 +897,17 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
                true, st);
     W.orth_c.run(1.0, 0.0, st);
     W.orth_u.run(-1.0, 1.0, st);
+    double fl0 = 0.0, by0 = 0.0, fl1 = 0.0, by1 = 0.0;
+    if (W.kt->any()) apply_work(L, W, fl0, by0);   // what apply_ab records (previous flags)
     apply_ab(L, W, 1, st);
+    W.act = flags.wait();
+    if (W.kt->any()) {
+      apply_work(L, W, fl1, by1);
+      W.kt->amend("pair_apply", fl1 - fl0, by1 - by0);
+    }
+    int nact = 0;
+    for (int x : W.act) nact += x != 0;
+    if (nact == 0) break;
     rayleigh_ritz(L, W, it == 1 ? 1 : 2, true, st);
   }
   if (it > c.opt.lobpcg_maxit) apply_ab(L, W, 0, st);   // products of the final X
