@@ -56,27 +56,33 @@ void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStr
 // corner or edge only; its entries are listed in dr (pair-vector index and
 // position of the coefficient in the constraint buffer; t-side entries carry
 // the minus sign).  Rows have disjoint supports, so Pi subtracts each row's
-// component independently: one thread per (row, column) computes the
-// coefficient and updates the row's support, with no barrier.  The rigid-mode
-// deflation needs whole columns and starts after a barrier.
+// component independently: a group of 16 lanes per (row, column) gathers the
+// row's support in parallel, sums with DPP inside the group, and updates the
+// support, with no barrier.  The rigid-mode deflation needs whole columns and
+// starts after a barrier.
 __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, const double* C,
                              const DRows dr, const double* rb, bool deflate, double* sm) {
   const int n = p.nGs + p.nGt;
   const int nd = p.dr1 - p.dr0;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int idx = tid; idx < nd * ncol; idx += nt) {
+  // the 16 lanes of a group share idx, so a group is active or idle as a
+  // whole and the row reduction only reads active lanes
+  const int sub = tid & 15;
+  for (int idx = tid >> 4; idx < nd * ncol; idx += nt >> 4) {
     const int r = idx / ncol, c = idx % ncol;
     double* vc = v + (size_t)c * ldv;
     const int q0 = dr.ptr[p.dr0 + r], q1 = dr.ptr[p.dr0 + r + 1];
     double dot = 0.0, nrm = 0.0;
-    for (int q = q0; q < q1; ++q) {
+    for (int q = q0 + sub; q < q1; q += 16) {
       const int i = dr.idx[q];
       const double a = (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
       dot += a * vc[i];
       nrm += a * a;
     }
+    dot = row16_sum(dot);
+    nrm = row16_sum(nrm);
     const double coef = nrm > 0.0 ? dot / nrm : 0.0;
-    for (int q = q0; q < q1; ++q) {
+    for (int q = q0 + sub; q < q1; q += 16) {
       const int i = dr.idx[q];
       vc[i] -= coef * (i < p.nGs ? 1.0 : -1.0) * C[dr.cpos[q]];
     }
@@ -92,7 +98,7 @@ __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, con
       const double* rr = R + (size_t)r * n;
       double dot = 0.0;
       for (int i = lane; i < n; i += 64) dot += rr[i] * vc[i];
-      for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+      dot = wave_sum(dot);
       if (lane == 0) coef[idx] = dot;
     }
     __syncthreads();
