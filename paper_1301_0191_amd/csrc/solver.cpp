@@ -473,7 +473,7 @@ struct PairWork {
   DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw, Nb, Aug;
   DBuf<int> active, kout, nnull, slot_pair;
   TunedGemm gS, gM1, gM2;   // grouped per-subdomain products, tile shape tuned
-  GemmOp gram_a[3], gram_b[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;
+  GemmOp gram[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;   // gram: V^T AV and V^T BV in one launch
   KTimer* kt = nullptr;
   std::vector<int> act;                          // host copy of the active flags
   std::vector<int> h_slot_off, h_slot_pair;      // pair of every subdomain slot
@@ -697,24 +697,24 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   W.orthp_u.finalize(st);
   for (int v = 0; v < 3; ++v) {
     const int nb = (v + 1) * m;
-    W.gram_a[v] = GemmOp(); W.gram_b[v] = GemmOp();
+    W.gram[v] = GemmOp();
     W.upd_v[v] = GemmOp();
-    W.gram_a[v].ta = W.gram_b[v].ta = true;
-    W.gram_a[v].ksplit = W.gram_b[v].ksplit = 0;
+    W.gram[v].ta = true;
+    W.gram[v].ksplit = 0;
     W.upd_v[v].narrow = (2 * m <= 32);
     for (int p = 0; p < W.np; ++p) {
       const PairDev& d = W.hp[p];
       const int n = d.nGs + d.nGt;
       const int* fl = W.active.p + p;
-      W.gram_a[v].add(W.V.p + d.v_off, n, W.AV.p + d.v_off, n, W.GA.p + size_t(p) * 9 * m * m, nb,
-                      nb, nb, n, fl);
-      W.gram_b[v].add(W.V.p + d.v_off, n, W.BV.p + d.v_off, n, W.GB.p + size_t(p) * 9 * m * m, nb,
-                      nb, nb, n, fl);
+      W.gram[v].add(W.V.p + d.v_off, n, W.AV.p + d.v_off, n, W.GA.p + size_t(p) * 9 * m * m, nb,
+                    nb, nb, n, fl);
+      W.gram[v].add(W.V.p + d.v_off, n, W.BV.p + d.v_off, n, W.GB.p + size_t(p) * 9 * m * m, nb,
+                    nb, nb, n, fl);
       const double* cf = W.Cf.p + size_t(p) * 3 * m * 2 * m;
       double* t = W.T.p + 2 * d.v_off;
       W.upd_v[v].add(W.V.p + d.v_off, n, cf, 3 * m, t, n, n, 2 * m, nb, fl);
     }
-    W.gram_a[v].finalize(st); W.gram_b[v].finalize(st);
+    W.gram[v].finalize(st);
     W.upd_v[v].finalize(st);
   }
 }
@@ -816,15 +816,13 @@ void rayleigh_ritz(Level& L, PairWork& W, int v, bool with_p, hipStream_t st) {
     const double frr = nact * (9.0 * b3 + 4.0 / 3.0 * b3 + 2.0 * double(nb) * nb * W.m);
     const double brr = nact * 8.0 * (2.0 * double(nb) * nb + 2.0 * double(nb) * W.m);
     W.kt->begin("pair_gram", st);
-    W.gram_a[v].run(1.0, 0.0, st);
-    W.gram_b[v].run(1.0, 0.0, st);
+    W.gram[v].run(1.0, 0.0, st);
     W.kt->end("pair_gram", st, fg, bg);
     W.kt->begin("pair_rr", st);
     lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
     W.kt->end("pair_rr", st, frr, brr);
   } else {
-    W.gram_a[v].run(1.0, 0.0, st);
-    W.gram_b[v].run(1.0, 0.0, st);
+    W.gram[v].run(1.0, 0.0, st);
     lp_rr(W.dp.p, W.np, W.GA.p, W.GB.p, nb, W.m, W.Cf.p, W.lam.p, W.active.p, st);
   }
   W.upd_v[v].run(1.0, 0.0, st);
