@@ -54,6 +54,8 @@ typedef enum {
 
 typedef struct ambddc_ctx* ambddc_handle;
 
+enum { AMBDDC_INIT_CE = 0, AMBDDC_INIT_CEF = 1, AMBDDC_INIT_C = 2 };
+
 /* Conforming hexahedral mesh (Section 2).  All pointers are host. */
 typedef struct {
   int32_t n_nodes;
@@ -87,7 +89,22 @@ typedef struct {
                                   FP64, so PCG, which iterates on FP64 residuals,
                                   reaches the same FP64 accuracy; only iteration
                                   counts can change. */
-  int32_t face_averages;       /* 1 = add face averages to the initial constraints (c+e+f) */
+  int32_t initial_constraints; /* initial coarse DOFs (Section 7; the variants of
+                                  Section 8.2's tables): AMBDDC_INIT_CE (0) corners and
+                                  one arithmetic average per edge and displacement
+                                  component; AMBDDC_INIT_CEF (1) also face averages;
+                                  AMBDDC_INIT_C (2) corners only */
+  int32_t keep_edges;          /* 0: adaptive constraint rows keep only their entries on
+                                  the face (the entries on shared edges and corners are
+                                  set to zero, Section 7); 1: rows keep their entries on
+                                  all DOFs the two subdomains share (the rows of
+                                  eq. d-def as they are, which keep the bound
+                                  omega <= tau); the row is a coarse DOF of the pair's
+                                  two subdomains only */
+  int32_t fixed_per_face;      /* 0: Alg. 2 (eigenvalues above tau, at most nev_max);
+                                  k > 0: every face gets the constraints of its k
+                                  largest eigenvectors whatever tau ("3eigv" in
+                                  Section 8.2 is k = 3 with AMBDDC_INIT_CE) */
   uint64_t seed;               /* LOBPCG start vectors */
   void* stream;                /* hipStream_t for all work (NULL = default stream) */
 } ambddc_options;
@@ -102,14 +119,14 @@ typedef struct {
   int32_t n_sub;
   int32_t n_interface;         /* free DOFs on the interface Gamma */
   int32_t n_faces, n_edges, n_corners;   /* globs with at least one free DOF */
-  int32_t n_coarse_initial;    /* initial constraints (corners + edge averages [+ faces]) */
+  int32_t n_coarse_initial;    /* initial constraints of the chosen set (AMBDDC_INIT_*) */
   int32_t n_pairs;             /* adjacent pairs = faces */
 } ambddc_analysis;
 
 /* sub_sizes_host may be NULL, else [2*n_sub]: (n_I, n_Gamma) per subdomain.
  * Pass n_sub_cap = its capacity in subdomains; E_INVALID_ARG if too small. */
 ambddc_status ambddc_analyze(const ambddc_mesh* mesh, const ambddc_decomp* decomp,
-                             int32_t face_averages, ambddc_analysis* out,
+                             int32_t initial_constraints, ambddc_analysis* out,
                              int32_t* sub_sizes_host, int32_t n_sub_cap);
 
 /* Analyse the mesh and decomposition: level-1 DOF numbering, interface and
@@ -128,11 +145,21 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* decomp
  * the grouped pair-eigenproblem products on every level (64 x 64 or
  * 128 x 32; both give identical results) and keeps the choice for later
  * set-ups.
- * Errors: E_NOT_SPD, E_ASSUMPTION, E_INVALID_ARG, E_OOM, E_DEVICE. */
+ * Errors: E_INVALID_ARG (also for a coefficient that is not a finite number,
+ * naming the element, or a Poisson ratio outside (-1, 1/2)), E_NOT_SPD (a
+ * subdomain or coarse factorisation meets a non-positive pivot, e.g. for a
+ * negative coefficient), E_ASSUMPTION (a pair coarse matrix has null vectors
+ * beyond the rigid modes both subdomains share: Assumption 1 of Section 4
+ * fails; the message names the pair), E_OOM, E_DEVICE.  LOBPCG that reaches
+ * lobpcg_maxit is not an error: the unconverged pairs are counted in the
+ * statistics (n_unconverged) and their current Ritz values are used. */
 ambddc_status ambddc_setup(ambddc_handle h, const double* coeff_dev, const double* nu_dev);
 
 /* PCG with the Multilevel BDDC preconditioner (Alg. 1), x0 = 0, stopping when
- * ||f - K x||_2 / ||f||_2 <= rtol per column (FP64 residual).
+ * ||f - K x||_2 / ||f||_2 <= rtol per column (FP64 residual).  The
+ * iteration updates the residual recursively; when that meets rtol, the true
+ * residual f - K x is recomputed, and a column stops only if it meets rtol
+ * too, otherwise it continues from the true residual (residual replacement).
  * rhs_dev, x_dev: device [n_free*nrhs] column-major (ld = n_free).
  * iterations_host[nrhs], cond_host[nrhs] (Lanczos estimate of the
  * preconditioned condition number) may be NULL.  The columns are
@@ -181,6 +208,9 @@ typedef struct {
   double t_phase[16];            /* seconds: 0 assembly+Schur, 1 BDDC init, 2 LOBPCG,
                                     3 selection, 4 enriched BDDC, 5 coarse, 6 total setup,
                                     7 last solve */
+  int32_t pcg_replacements;      /* residual replacements in the last solve: columns whose
+                                    recursive residual met rtol while the recomputed
+                                    f - K x did not, and which went on from the latter */
 } ambddc_stats;
 
 ambddc_status ambddc_get_stats(ambddc_handle h, ambddc_stats* out);
@@ -199,7 +229,8 @@ ambddc_status ambddc_sub_dofs(ambddc_handle h, int32_t level, int32_t sub, int32
 /* Interface Schur complement S of `sub`, n_G x n_G column-major, host. */
 ambddc_status ambddc_get_schur(ambddc_handle h, int32_t level, int32_t sub, double* S_host);
 
-/* Subdomains of pair `pair` (one pair per face glob). */
+/* Subdomains of pair `pair` (one pair per face glob); n_face = number of
+ * DOFs its constraint rows are supported on (see ambddc_get_face_constraints). */
 ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int32_t* s, int32_t* t,
                                int32_t* n_face);
 
@@ -214,8 +245,10 @@ ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pai
                                      int32_t* iters, int32_t* converged);
 
 /* Adaptive constraint rows of the face of `pair`: rows_host[k*n_face],
- * row-major (row l = l-th orthonormal row), and the face's level DOF ids
- * face_dofs_host[n_face], ascending.  Either pointer may be NULL. */
+ * row-major (row l = l-th orthonormal row), and the level DOF ids they are
+ * supported on, face_dofs_host[n_face], ascending: the face DOFs, or with
+ * keep_edges every DOF the two subdomains share.  Either pointer may be
+ * NULL. */
 ambddc_status ambddc_get_face_constraints(ambddc_handle h, int32_t level, int32_t pair,
                                           double* rows_host, int32_t* face_dofs_host);
 

@@ -16,7 +16,9 @@ C^s and C^t.  Alg. 2 picks, per pair, the smallest k with
 lambda_{k+1} <= tau, capped at nev_max (Section 8 uses at most 10).
 
 Readings: D = [C^s_shared, -C^t_shared] (one row per shared initial coarse
-DOF: the coarse DOFs of s and t agree); the pair weights are the
+DOF: the coarse DOFs of s and t agree); with keep_edges the rows stay on all
+of Gamma^st and are applied to s and t only (a coarse DOF of the pair, not
+of the other subdomains on the shared edges); the pair weights are the
 stiffness-scaling weights renormalised over {s, t}; when both subdomains
 are floating, the pair-continuous rigid modes (in null D and null S^st)
 are removed from the factor space; the QR rank tolerance is 1e-10 max|R_jj|.
@@ -78,8 +80,24 @@ def pair_rigid(L, s, t, ops):
     return np.vstack([R[ops["Gs"]], R[ops["Gt"]]])
 
 
-def pair_eigenproblem(L, s, t, face_glob, tau, nev_max):
-    """Dense solution of the pair eigenproblem and the resulting constraints."""
+def pair_eigenproblem(L, s, t, face_glob, tau, nev_max, keep_edges=False, fixed=0,
+                      span_upto=0):
+    """Dense solution of the pair eigenproblem and the resulting constraints.
+
+    The rows follow eq. d-def: c_l = Pi (I-E)^T S (I-E) Pi w_l for the k
+    selected eigenvectors, supported on the shared DOFs Gamma^st with
+    halves [c^s, -c^s] (Prop. 1).  The s-half is kept on all of Gamma^st
+    (keep_edges, the form the theory asks for) or, by default, restricted to
+    the face DOFs, i.e. the entries on the shared edges and corners are set
+    to zero (Section 7); then a reduced QR orthonormalises them.
+
+    k is min(#{lambda > tau}, nev_max) (Alg. 2), or, with fixed > 0, the
+    fixed count min(fixed, n_factor) regardless of tau (the "3eigv" runs of
+    Section 8.2: three eigenvector constraints per face in place of the
+    face averages).  span_upto > 0 also returns, as "span_rows", the
+    orthonormalised rows of the first span_upto eigenvectors (used to check
+    a selection that cuts a cluster of equal eigenvalues, where only the
+    span of the whole cluster is fixed)."""
     ops = pair_operators(L, s, t)
     n = ops["ns"] + ops["nt"]
     D = ops["D"]
@@ -101,39 +119,54 @@ def pair_eigenproblem(L, s, t, face_glob, tau, nev_max):
     lam, W = sla.eigh(Ah, Bh)
     lam = lam[::-1]
     W = W[:, ::-1]
-    k = int(min(np.count_nonzero(lam > tau), nev_max))
+    if fixed > 0:
+        k = int(min(fixed, len(lam)))
+    else:
+        k = int(min(np.count_nonzero(lam > tau), nev_max))
     lam_next = float(lam[k]) if k < len(lam) else 0.0
-    face = face_glob["dofs"]
+    # support of the rows: Gamma^st (keep_edges) or the face DOFs only
+    face = ops["shared"] if keep_edges else face_glob["dofs"]
     pos = np.searchsorted(ops["Gs"], face)
-    rows = np.zeros((0, len(face)))
-    c_full = None
-    if k > 0:
-        Wf = Q @ W[:, :k]
-        PiD = QD @ QD.T
-        c_full = PiD @ Afull @ Wf                 # eq. d-def, columns c_l
-        F = c_full[pos, :]                        # s-half on the face DOFs
+    PiD = QD @ QD.T
+
+    def rows_of(j):
+        """Orthonormal rows from the first j eigenvectors (eq. d-def, then
+        the restriction to `face`, then reduced QR with the rank test)."""
+        if j == 0:
+            return np.zeros((0, len(face))), None
+        c = PiD @ Afull @ (Q @ W[:, :j])         # eq. d-def, columns c_l
+        F = c[pos, :]                             # s-half on the kept DOFs
         Qr, Rr = np.linalg.qr(F, mode="reduced")
         dR = np.abs(np.diag(Rr))
         keep = dR > QR_RANK_TOL * dR.max() if dR.size else np.zeros(0, bool)
-        rows = Qr[:, keep].T
+        r = Qr[:, keep].T
         # canonical sign of each row: its largest-magnitude entry (first on
         # ties) positive; only the span is fixed by the method
-        for r in rows:
-            if r[np.argmax(np.abs(r))] < 0:
-                r *= -1.0
-    return dict(s=s, t=t, lam=lam, k=k, lam_next=lam_next, rows=rows, face_dofs=face,
-                c_full=c_full, n=n, n_factor=Q.shape[1], both_floating=both_floating)
+        for x in r:
+            if x[np.argmax(np.abs(x))] < 0:
+                x *= -1.0
+        return r, c
+
+    rows, c_full = rows_of(k)
+    out = dict(s=s, t=t, lam=lam, k=k, lam_next=lam_next, rows=rows, face_dofs=face,
+               c_full=c_full, n=n, n_factor=Q.shape[1], both_floating=both_floating,
+               Q=Q, Ah=Ah, Bh=Bh)
+    if span_upto > 0:
+        out["span_rows"] = rows_of(min(span_upto, len(lam)))[0]
+    return out
 
 
-def enrich_level(L, tau, nev_max, pairs=None):
+def enrich_level(L, tau, nev_max, pairs=None, keep_edges=False, fixed=0):
     """Alg. 2 on one level: solve every pair problem and append the adaptive
-    face constraints to C^s and C^t.  Records omega_i (max lambda_{k+1})."""
+    face constraints to C^s and C^t.  Records omega_i (max lambda_{k+1}).
+    keep_edges and fixed as in pair_eigenproblem."""
     from .substructure import rebuild_constraint_matrices
     results = []
     sel = range(len(L.pairs)) if pairs is None else pairs
     for p in sel:
         s, t, g = L.pairs[p]
-        res = pair_eigenproblem(L, s, t, L.globs[g], tau, nev_max)
+        res = pair_eigenproblem(L, s, t, L.globs[g], tau, nev_max, keep_edges=keep_edges,
+                                fixed=fixed)
         res["pair"] = p
         results.append(res)
     for res in results:

@@ -61,19 +61,22 @@ def _prepare_full_space(L):
 
 
 def setup_hierarchy(prob, adaptive=True, tau=None, nev_max=None, face_averages=False,
-                    Ke=None, pair_subset=None):
-    """Adaptive-Multilevel BDDC set-up (Alg. 3) for ``prob.levels`` levels."""
+                    Ke=None, pair_subset=None, keep_edges=False, fixed=0, corners_only=False):
+    """Adaptive-Multilevel BDDC set-up (Alg. 3) for ``prob.levels`` levels.
+    keep_edges / fixed: see adaptive.pair_eigenproblem; corners_only /
+    face_averages select the initial constraints 'c' / 'c+e+f'."""
     tau = prob.tau if tau is None else tau
     nev_max = prob.nev_max if nev_max is None else nev_max
     H = Hierarchy()
     inp = level1_input(prob, Ke)
     nlev = prob.levels
     for i in range(nlev - 1):
-        L = build_level(inp, face_averages=face_averages)
+        L = build_level(inp, face_averages=face_averages, corners_only=corners_only)
         if i == 0:
             L.Kglob = fem.assemble_global(prob, None if Ke is None else Ke)
-        if adaptive and np.isfinite(tau):
-            enrich_level(L, tau, nev_max, pairs=pair_subset if i == 0 else None)
+        if adaptive and (np.isfinite(tau) or fixed > 0):
+            enrich_level(L, tau, nev_max, pairs=pair_subset if i == 0 else None,
+                         keep_edges=keep_edges, fixed=fixed)
         coarse_basis(L)
         _prepare_full_space(L)
         H.levels.append(L)

@@ -150,10 +150,17 @@ def classify(inp):
     return node_sets, globs
 
 
-def build_level(inp, face_averages=False):
+def build_level(inp, face_averages=False, corners_only=False, only=None):
     """Subdomain matrices, globs, weights, initial constraints and Schur
     complements of one level (initial constraints = corners + edge averages,
-    Section 7; optionally face averages as well)."""
+    Section 7; optionally face averages as well ('c+e+f'), or corners alone
+    ('c'), the variants of Section 8.2's tables).
+
+    only: None, or a collection of subdomains: then the dense matrices and
+    Schur complements are formed for those subdomains alone (the others get
+    None) and the global weights are skipped; the structure (globs, DOF
+    sets, constraints, pairs) is always complete.  Used to time a sample of
+    a large workload; the pair problem of two sampled subdomains is exact."""
     L = Level(inp=inp)
     node_sets, globs = classify(inp)
     L.globs = globs
@@ -180,6 +187,9 @@ def build_level(inp, face_averages=False):
     for e in range(len(inp.elem_dofs)):
         sub_elems[int(inp.elem_sub[e])].append(e)
     for s in range(n_sub):
+        if only is not None and s not in only:
+            L.K.append(None)
+            continue
         dofs = L.sub_dofs[s]
         loc = {int(g): i for i, g in enumerate(dofs)}
         n = len(dofs)
@@ -191,18 +201,19 @@ def build_level(inp, face_averages=False):
             K[np.ix_(li, li)] += inp.elem_mats[e][np.ix_(keep, keep)]
         L.K.append(K)
     # stiffness-scaling weights: delta_j^s = K^s_jj / sum_r K^r_jj
-    diag_sum = np.zeros(inp.n_dof)
-    for s in range(n_sub):
-        nI = L.n_I[s]
-        G = L.sub_dofs[s][nI:]
-        np.add.at(diag_sum, G, np.diag(L.K[s])[nI:])
-    for s in range(n_sub):
-        nI = L.n_I[s]
-        G = L.sub_dofs[s][nI:]
-        L.weights.append(np.diag(L.K[s])[nI:] / diag_sum[G])
+    if only is None:
+        diag_sum = np.zeros(inp.n_dof)
+        for s in range(n_sub):
+            nI = L.n_I[s]
+            G = L.sub_dofs[s][nI:]
+            np.add.at(diag_sum, G, np.diag(L.K[s])[nI:])
+        for s in range(n_sub):
+            nI = L.n_I[s]
+            G = L.sub_dofs[s][nI:]
+            L.weights.append(np.diag(L.K[s])[nI:] / diag_sum[G])
     # Schur complements S^s = K_GG - K_GI K_II^{-1} K_IG
     for s in range(n_sub):
-        L.S.append(schur(L.K[s], L.n_I[s]))
+        L.S.append(None if L.K[s] is None else schur(L.K[s], L.n_I[s]))
     # initial constraints
     cons = []
     glob_cons = []
@@ -212,7 +223,8 @@ def build_level(inp, face_averages=False):
             for j in gl["dofs"]:
                 ids.append(len(cons))
                 cons.append(dict(glob=g, dofs=np.array([j]), w=np.array([1.0])))
-        elif gl["type"] == "edge" or (gl["type"] == "face" and face_averages):
+        elif (gl["type"] == "edge" and not corners_only) or \
+                (gl["type"] == "face" and face_averages):
             comps = inp.dof_comp[gl["dofs"]]
             for c in np.unique(comps):
                 dd = gl["dofs"][comps == c]

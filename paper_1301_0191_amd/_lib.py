@@ -36,8 +36,13 @@ class Decomp(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tau", C.c_double), ("nev_max", C.c_int32), ("lobpcg_maxit", C.c_int32),
                 ("lobpcg_block", C.c_int32), ("lobpcg_tol", C.c_double),
-                ("precision", C.c_int32), ("face_averages", C.c_int32), ("seed", C.c_uint64),
-                ("stream", C.c_void_p)]
+                ("precision", C.c_int32), ("initial_constraints", C.c_int32),
+                ("keep_edges", C.c_int32), ("fixed_per_face", C.c_int32),
+                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+# initial constraint sets (AMBDDC_INIT_*)
+INITIAL = {"c+e": 0, "c+e+f": 1, "c": 2}
 
 
 class Stats(C.Structure):
@@ -45,7 +50,7 @@ class Stats(C.Structure):
                 ("n_pairs", C.c_int32 * 8), ("n_coarse", C.c_int32 * 8),
                 ("n_adaptive", C.c_int32 * 8), ("lobpcg_iters", C.c_int32 * 8),
                 ("n_unconverged", C.c_int32 * 8), ("omega_tilde", C.c_double * 8),
-                ("t_phase", C.c_double * 16)]
+                ("t_phase", C.c_double * 16), ("pcg_replacements", C.c_int32)]
 
 
 class Analysis(C.Structure):

@@ -10,8 +10,12 @@ J = 1/2 sum_k ||x_k - x_obs,k||^2, the adjoint lambda_k = K^{-1}(x_k - x_obs,k)
 Forward runs the library's set-up from theta (coefficients computed on the
 device), the multilevel BDDC-PCG solve and the misfit kernel; backward reuses
 the same handle (same hierarchy, same preconditioner) for the adjoint solve
-and assembles the element gradient in the library.  The argument tensors stay
-on the GPU; no step runs on the host.
+and assembles the element gradient in the library.  If the handle was set up
+again between forward and backward (another forward, a finite-difference
+probe), backward first repeats the set-up at the forward's theta, so the
+adjoint solve and the element matrices always belong to the theta the
+gradient is taken at.  The argument tensors stay on the GPU; no step runs on
+the host.
 """
 from __future__ import annotations
 
@@ -29,19 +33,25 @@ class BddcMisfit(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, handle, F, x_obs, rtol=1e-10, maxit=1000):
-        handle.setup_log10(theta.detach().contiguous())
+        th = theta.detach().contiguous().clone()
+        handle.setup_log10(th)
         X = handle.solve(F, rtol=rtol, maxit=maxit).x
         J, R = handle.misfit(X, x_obs)
-        ctx.save_for_backward(X, R)
+        ctx.save_for_backward(X, R, th)
         ctx.handle = handle
+        ctx.setup_count = handle.setup_count
         ctx.rtol = rtol
         ctx.maxit = maxit
         return theta.new_tensor(J)
 
     @staticmethod
     def backward(ctx, grad_J):
-        X, R = ctx.saved_tensors
+        X, R, th = ctx.saved_tensors
         h = ctx.handle
+        if h.setup_count != ctx.setup_count:
+            # the handle now holds another set-up: restore the forward's
+            h.setup_log10(th)
+            ctx.setup_count = h.setup_count
         Lam = h.solve(R, rtol=ctx.rtol, maxit=ctx.maxit).x
         g = h.element_gradient(X, Lam)
         return g * grad_J, None, None, None, None, None

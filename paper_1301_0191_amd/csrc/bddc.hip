@@ -508,6 +508,43 @@ void launch_pow10(size_t n, const double* theta, double* out, hipStream_t st) {
   AMB_LAUNCH_CHECK();
 }
 
+// dst[:, c] = src[:, c] for the columns c with mask[c] != 0 (residual
+// replacement of the PCG columns whose true residual lags the recursive one)
+__global__ void k_copy_cols(int n, const double* src, double* dst, const int* mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || !mask[c]) return;
+  dst[i + (size_t)c * n] = src[i + (size_t)c * n];
+}
+
+void launch_copy_cols(int n, int nrhs, const double* src, double* dst, const int* mask,
+                      hipStream_t st) {
+  if (n == 0 || nrhs == 0) return;
+  dim3 g(ceil_div(n, 256), nrhs);
+  k_copy_cols<<<g, 256, 0, st>>>(n, src, dst, mask);
+  AMB_LAUNCH_CHECK();
+}
+
+// Input check of the element data: bad[0] = 1 + the first element whose
+// coefficient is not a finite number (0 if none), bad[1] the same for a
+// Poisson ratio outside (-1, 1/2) or not finite (nu may be null).
+__global__ void k_check_coeff(int n, const double* coeff, const double* nu, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double c = coeff[i];
+  if (!(fabs(c) <= 1.7976931348623157e308)) atomicMin(&bad[0], i + 1);
+  if (nu) {
+    const double v = nu[i];
+    if (!(v > -1.0 && v < 0.5)) atomicMin(&bad[1], i + 1);
+  }
+}
+
+void launch_check_coeff(int n, const double* coeff, const double* nu, int* bad, hipStream_t st) {
+  if (n == 0) return;
+  k_check_coeff<<<ceil_div(n, 256), 256, 0, st>>>(n, coeff, nu, bad);
+  AMB_LAUNCH_CHECK();
+}
+
 // out = a - b elementwise
 __global__ void k_sub(size_t n, const double* a, const double* b, double* out) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;

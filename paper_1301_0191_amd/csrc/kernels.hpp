@@ -112,5 +112,8 @@ void launch_coarse_rigid(int n2, int nrb, const int* sub_of, const int* row_of, 
 void launch_copy(double* dst, const double* src, size_t n, hipStream_t st);
 void launch_pow10(size_t n, const double* theta, double* out, hipStream_t st);
 void launch_sub(size_t n, const double* a, const double* b, double* out, hipStream_t st);
+void launch_copy_cols(int n, int nrhs, const double* src, double* dst, const int* mask,
+                      hipStream_t st);
+void launch_check_coeff(int n, const double* coeff, const double* nu, int* bad, hipStream_t st);
 
 }  // namespace ambddc

@@ -872,13 +872,14 @@ void lp_rigid(const PairDev* P, int np, const double* rigid, int ndof, const int
   AMB_LAUNCH_CHECK();
 }
 
-// Selection (Alg. 2) and constraint rows: k = #{lambda_j > tau, j < nev_max};
-// c_l = (A w_l) restricted to the face DOFs of s (edge and corner entries
-// dropped), orthonormalised by Gram-Schmidt (twice) with the rank test
+// Selection (Alg. 2) and constraint rows: k = #{lambda_j > tau, j < nev_max}
+// (or k = fixed when fixed > 0); c_l = (A w_l) restricted to the support of
+// the rows in s (the face DOFs, edge and corner entries dropped, or all
+// shared DOFs), orthonormalised by Gram-Schmidt (twice) with the rank test
 // |R_jj| > 1e-10 max |R_jj|; rows stored row-major (nev_max x nface).
 __global__ __launch_bounds__(256) void k_select(const PairDev* P, const double* AV,
                                                 const double* lam, int m, int nev_max, double tau,
-                                                const int* face_s, double* fc, int* kout,
+                                                int fixed, const int* face_s, double* fc, int* kout,
                                                 double* lam_next) {
   extern __shared__ double sm[];
   __shared__ double red[8];
@@ -888,7 +889,8 @@ __global__ __launch_bounds__(256) void k_select(const PairDev* P, const double* 
   const double* l = lam + (size_t)blockIdx.x * m;
   const int cap = min(nev_max, m);
   int k = 0;
-  while (k < cap && l[k] > tau) ++k;
+  if (fixed > 0) k = cap;
+  else while (k < cap && l[k] > tau) ++k;
   if (threadIdx.x == 0) lam_next[blockIdx.x] = (k < m) ? l[k] : 0.0;
   const int nf = p.nface;
   double* Q = sm;   // k x nf (row-major)
@@ -941,11 +943,12 @@ __global__ __launch_bounds__(256) void k_select(const PairDev* P, const double* 
 }
 
 void lp_select(const PairDev* P, int np, const double* AV, const double* lam, int m, int nev_max,
-               double tau, const int* face_s, int nface_max, double* fc, int* kout,
+               double tau, int fixed, const int* face_s, int nface_max, double* fc, int* kout,
                double* lam_next, hipStream_t st) {
   if (np == 0) return;
   const size_t sm = sizeof(double) * size_t(std::min(nev_max, m)) * nface_max;
-  k_select<<<np, 256, sm, st>>>(P, AV, lam, m, nev_max, tau, face_s, fc, kout, lam_next);
+  if (sm > 64 * 1024) throw Error(1, "constraint rows of a face exceed the selection kernel's LDS");
+  k_select<<<np, 256, sm, st>>>(P, AV, lam, m, nev_max, tau, fixed, face_s, fc, kout, lam_next);
   AMB_LAUNCH_CHECK();
 }
 

@@ -82,7 +82,7 @@ void lp_pinv_extract(const PairDev* P, int np, const double* Aug, const double* 
 void lp_rigid(const PairDev* P, int np, const double* rigid, int ndof, const int* gdof,
               double* rb, hipStream_t st);
 void lp_select(const PairDev* P, int np, const double* AV, const double* lam, int m, int nev_max,
-               double tau, const int* face_s, int nface_max, double* fc, int* kout,
+               double tau, int fixed, const int* face_s, int nface_max, double* fc, int* kout,
                double* lam_next, hipStream_t st);
 
 }  // namespace ambddc

@@ -76,7 +76,9 @@ std::string level1_input(int n_nodes, int n_elems, int dof, const int32_t* elem_
   return "";
 }
 
-std::string build_level_plan(LevelPlan& L, bool face_averages) {
+std::string build_level_plan(LevelPlan& L, int init, bool keep_edges) {
+  if (init != INIT_CE && init != INIT_CEF && init != INIT_C) return "unknown initial constraint set";
+  const bool face_averages = init == INIT_CEF, edge_averages = init != INIT_C;
   LevelInput& in = L.in;
   const int nn = in.n_node, ns = in.n_sub;
   // node -> sorted set of subdomains (via sorted (node, sub) keys)
@@ -173,7 +175,7 @@ std::string build_level_plan(LevelPlan& L, bool face_averages) {
         c.dofs = {j};
         L.cons.push_back(c);
       }
-    } else if (gl.type == GLOB_EDGE || face_averages) {
+    } else if ((gl.type == GLOB_EDGE && edge_averages) || (gl.type == GLOB_FACE && face_averages)) {
       std::vector<int> comps;
       for (int j : gl.dofs) comps.push_back(in.dof_comp[j]);
       std::vector<int> uc = comps;
@@ -222,12 +224,20 @@ std::string build_level_plan(LevelPlan& L, bool face_averages) {
         ++b;
       }
     }
-    for (int j : P.face_dofs) {
-      int is = lower_index(S.dofs, j, S.nI, S.nI + S.nG);
-      int it = lower_index(T.dofs, j, T.nI, T.nI + T.nG);
-      if (is < 0 || it < 0) return "face DOF missing from a subdomain interface";
-      P.face_s.push_back(is);
-      P.face_t.push_back(it);
+    if (keep_edges) {
+      // rows on every shared DOF (ascending level ids, like the intersection)
+      P.face_dofs.clear();
+      for (int q : P.sh_s) P.face_dofs.push_back(S.dofs[S.nI + q]);
+      P.face_s = P.sh_s;
+      P.face_t = P.sh_t;
+    } else {
+      for (int j : P.face_dofs) {
+        int is = lower_index(S.dofs, j, S.nI, S.nI + S.nG);
+        int it = lower_index(T.dofs, j, T.nI, T.nI + T.nG);
+        if (is < 0 || it < 0) return "face DOF missing from a subdomain interface";
+        P.face_s.push_back(is);
+        P.face_t.push_back(it);
+      }
     }
   }
   add_adaptive_constraints(L, std::vector<int>(L.pairs.size(), 0));

@@ -52,8 +52,8 @@ struct Pair {
   int s = -1, t = -1, glob = -1;
   std::vector<int> sh_s, sh_t;      // shared DOFs: local interface index in s / t
   std::vector<int> dr_s, dr_t;      // shared coarse DOFs: row of C^s / C^t
-  std::vector<int> face_s, face_t;  // face DOFs: local interface index in s / t
-  std::vector<int> face_dofs;       // level ids of the face DOFs (ascending)
+  std::vector<int> face_s, face_t;  // support of the adaptive rows: local interface index in s / t
+  std::vector<int> face_dofs;       // level ids of that support (ascending)
   std::vector<int> pc_s, pc_t;      // pair-coarse index of each row of C^s / C^t
   int n_cp = 0;
   bool both_floating = false;
@@ -71,10 +71,16 @@ struct LevelPlan {
   int n_cons_initial = 0;
 };
 
-// Build globs, subdomain DOF sets, initial constraints (corners, edge
-// averages per component, optional face averages) and pair maps.
-// Returns an empty string on success, else an error message.
-std::string build_level_plan(LevelPlan& L, bool face_averages);
+// Initial constraint sets (Section 7 and Section 8.2's variants).
+enum InitCons { INIT_CE = 0, INIT_CEF = 1, INIT_C = 2 };
+
+// Build globs, subdomain DOF sets, initial constraints (corners; edge
+// averages per component unless `init` is INIT_C; face averages for
+// INIT_CEF) and pair maps.  The support of a pair's adaptive rows
+// (face_dofs, face_s, face_t) is its face, or with keep_edges all DOFs the
+// two subdomains share.  Returns an empty string on success, else an error
+// message.
+std::string build_level_plan(LevelPlan& L, int init, bool keep_edges);
 
 // Append adaptive constraints (k[p] rows on the face of pair p) and rebuild
 // the per-subdomain constraint lists and pair-coarse maps.

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <map>
 #include <memory>
 #include <numeric>
@@ -111,10 +112,15 @@ struct ambddc_ctx {
   // PCG workspace
   int pcg_cap = 0, pcg_maxit = 0;
   DBuf<double> px, pr, pz, pp, pq, pdot, ppart, pah, pbh, plz;
-  DBuf<int> pact, pnal;
+  DBuf<int> pact, pnal, pmask;
+  int pcg_repl = 0;   // residual replacements in the last solve
 };
 
 namespace {
+
+// Most adaptive constraints one face can receive: nev_max under Alg. 2, or
+// the fixed count per face.
+int nsel_max(const ambddc_options& o) { return o.fixed_per_face > 0 ? o.fixed_per_face : o.nev_max; }
 
 // ---------------------------------------------------------------------------
 // level structure
@@ -590,7 +596,7 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
     d.fc_off = fcoff;
     L.fc_off[p] = fcoff;
     L.face_nf[p] = d.nface;
-    fcoff += int64_t(c.opt.nev_max) * d.nface;
+    fcoff += int64_t(nsel_max(c.opt)) * d.nface;
     W.hp[p] = d;
   }
   if (W.ncp_max > PAIR_COARSE_MAX)
@@ -844,7 +850,7 @@ int count_active(PairWork& W, hipStream_t st) {
 void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   hipStream_t st = c.st;
   PairWork W;
-  const int nev = c.opt.nev_max;
+  const int nev = nsel_max(c.opt);
   W.m = std::max(c.opt.lobpcg_block, nev + 1);
   if (W.m > 16) throw Error(AMBDDC_E_INVALID_ARG, "lobpcg_block larger than 16 is not supported");
   L.m = W.m;
@@ -911,7 +917,8 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   if (it > c.opt.lobpcg_maxit) apply_ab(L, W, 0, st);   // products of the final X
   L.lobpcg_its = std::min(it, c.opt.lobpcg_maxit);
   L.n_unconv = count_active(W, st);
-  lp_select(W.dp.p, W.np, W.AV.p, W.lam.p, m, nev, c.opt.tau, W.idx.face_s.p, W.nface_max, L.fc.p,
+  lp_select(W.dp.p, W.np, W.AV.p, W.lam.p, m, nev, c.opt.tau, c.opt.fixed_per_face,
+            W.idx.face_s.p, W.nface_max, L.fc.p,
             W.kout.p, W.lnext.p, st);
   L.pair_k = W.kout.download(st);
   L.pair_lnext = W.lnext.download(st);
@@ -1046,7 +1053,7 @@ void next_level(ambddc_ctx& c, int li) {
   auto N = std::make_unique<Level>();
   std::string e = next_level_input(L.plan, c.parents[li], N->plan.in);
   if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
-  e = build_level_plan(N->plan, c.opt.face_averages != 0);
+  e = build_level_plan(N->plan, c.opt.initial_constraints, c.opt.keep_edges != 0);
   if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
   std::vector<int64_t> koff(L.kc_off.begin(), L.kc_off.end() - 1);
   build_level_maps(c, *N, L.kc.p, koff);
@@ -1081,6 +1088,19 @@ void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
   const double t0 = now_s();
   c.ready = false;
   std::memset(&c.stats, 0, sizeof(c.stats));
+  {
+    const int big = std::numeric_limits<int>::max();
+    DBuf<int> bad;
+    bad.upload(std::vector<int>{big, big}, st);
+    launch_check_coeff(c.n_elems, coeff, c.dof == 3 ? nu : nullptr, bad.p, st);
+    const std::vector<int> b = bad.download(st);
+    if (b[0] != big)
+      throw Error(AMBDDC_E_INVALID_ARG,
+                  "coefficient of element " + std::to_string(b[0] - 1) + " is not a finite number");
+    if (b[1] != big)
+      throw Error(AMBDDC_E_INVALID_ARG, "Poisson ratio of element " + std::to_string(b[1] - 1) +
+                                            " is not in (-1, 1/2)");
+  }
   const int ne = 8 * c.dof;
   launch_element_matrices(c.coords.p, c.en.p, coeff, nu, c.n_elems, c.dof, c.Ke.p, st);
   launch_csr_values(c.csr, c.edofs.p, ne, c.Ke.p, c.csr_vals.p, st);
@@ -1088,7 +1108,7 @@ void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
   Level& L0 = *c.L[0];
   L0.plan = c.plan0;
   L0.nrhs_cap = 0;
-  const bool adaptive = c.opt.tau > 0.0 && std::isfinite(c.opt.tau);
+  const bool adaptive = (c.opt.tau > 0.0 && std::isfinite(c.opt.tau)) || c.opt.fixed_per_face > 0;
   double tph[8] = {0};
   for (int li = 0; li < c.levels - 1; ++li) {
     if (li > 0) next_level(c, li - 1);
@@ -1178,6 +1198,7 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
   for (int k = 0; k < nrhs; ++k) {
     its[k] = 0;
   }
+  c.pcg_repl = 0;
   AMB_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < nrhs; ++k)
     if (hff[k] == 0.0) act[k] = 0;
@@ -1216,15 +1237,41 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
     launch_dot_cols(n, nrhs, c.pr.p, c.pr.p, c.ppart.p, rr, st);
     AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     AMB_HIP(hipStreamSynchronize(st));
-    bool changed = false;
+    bool changed = false, cand = false;
+    std::vector<int> meets(nrhs, 0);
     for (int k = 0; k < nrhs; ++k) {
       if (!act[k]) continue;
       nal[k] = it + 1;
       its[k] = it + 1;
-      if (hrr[k] <= rtol * rtol * hff[k]) {
-        act[k] = 0;
-        changed = true;
-        --nact;
+      if (hrr[k] <= rtol * rtol * hff[k]) meets[k] = cand = true;
+    }
+    if (cand) {
+      // The recursive residual drifts from f - K x by rounding (most on
+      // ill-conditioned problems), so a column stops only when its true
+      // residual, recomputed here, meets rtol as well; otherwise the true
+      // residual replaces the recursive one and the iteration goes on.
+      launch_spmv(c.csr, c.csr_vals.p, x, c.pq.p, nrhs, st);
+      launch_sub(nn, f, c.pq.p, c.pq.p, st);
+      launch_dot_cols(n, nrhs, c.pq.p, c.pq.p, c.ppart.p, rr, st);
+      AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+      AMB_HIP(hipStreamSynchronize(st));
+      std::vector<int> repl(nrhs, 0);
+      bool any_repl = false;
+      for (int k = 0; k < nrhs; ++k) {
+        if (!meets[k]) continue;
+        if (hrr[k] <= rtol * rtol * hff[k]) {
+          act[k] = 0;
+          changed = true;
+          --nact;
+        } else {
+          repl[k] = 1;
+          any_repl = true;
+          ++c.pcg_repl;
+        }
+      }
+      if (any_repl) {
+        c.pmask.upload(repl, st);
+        launch_copy_cols(n, nrhs, c.pq.p, c.pr.p, c.pmask.p, st);
       }
     }
     if (nact == 0) break;
@@ -1250,6 +1297,7 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
   }
   AMB_HIP(hipStreamSynchronize(st));
   c.stats.t_phase[7] = now_s() - t0;
+  c.stats.pcg_replacements = c.pcg_repl;
   return nact;
 }
 
@@ -1290,7 +1338,9 @@ void ambddc_default_options(ambddc_options* o) {
   o->lobpcg_block = 16;
   o->lobpcg_tol = 1e-7;
   o->precision = 0;
-  o->face_averages = 0;
+  o->initial_constraints = AMBDDC_INIT_CE;
+  o->keep_edges = 0;
+  o->fixed_per_face = 0;
   o->seed = 12345;
   o->stream = nullptr;
 }
@@ -1298,7 +1348,7 @@ void ambddc_default_options(ambddc_options* o) {
 const char* ambddc_last_error(void) { return g_err.c_str(); }
 
 ambddc_status ambddc_analyze(const ambddc_mesh* mesh, const ambddc_decomp* dec,
-                             int32_t face_averages, ambddc_analysis* out, int32_t* sizes,
+                             int32_t initial_constraints, ambddc_analysis* out, int32_t* sizes,
                              int32_t n_sub_cap) {
   return ambddc_status(guard([&] {
     if (!mesh || !dec || !out || !mesh->elem_nodes || !mesh->dirichlet || !dec->elem_to_sub)
@@ -1310,7 +1360,7 @@ ambddc_status ambddc_analyze(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     std::string e = level1_input(mesh->n_nodes, mesh->n_elems, mesh->dof_per_node, mesh->elem_nodes,
                                  mesh->dirichlet, dec->elem_to_sub, P.in, fof);
     if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
-    e = build_level_plan(P, face_averages != 0);
+    e = build_level_plan(P, initial_constraints, false);
     if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
     std::memset(out, 0, sizeof(*out));
     out->n_free = P.in.n_dof;
@@ -1348,8 +1398,11 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     if (dec->levels > 2 && !dec->parents) throw Error(AMBDDC_E_INVALID_ARG, "missing parent maps");
     if (opt->precision != 0 && opt->precision != 1)
       throw Error(AMBDDC_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (FP32-stored preconditioners)");
-    if (opt->nev_max < 0 || opt->lobpcg_maxit < 1 || opt->lobpcg_tol <= 0.0)
+    if (opt->nev_max < 0 || opt->lobpcg_maxit < 1 || opt->lobpcg_tol <= 0.0 ||
+        opt->fixed_per_face < 0)
       throw Error(AMBDDC_E_INVALID_ARG, "bad LOBPCG options");
+    if (opt->initial_constraints < 0 || opt->initial_constraints > 2)
+      throw Error(AMBDDC_E_INVALID_ARG, "initial_constraints must be AMBDDC_INIT_CE, _CEF or _C");
     DevStreamScope ds(static_cast<hipStream_t>(opt->stream));
     auto c = std::make_unique<ambddc_ctx>();
     c->opt = *opt;
@@ -1361,7 +1414,7 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     std::string e = level1_input(mesh->n_nodes, mesh->n_elems, mesh->dof_per_node, mesh->elem_nodes,
                                  mesh->dirichlet, dec->elem_to_sub, c->plan0.in, c->free_of_full);
     if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
-    e = build_level_plan(c->plan0, opt->face_averages != 0);
+    e = build_level_plan(c->plan0, opt->initial_constraints, opt->keep_edges != 0);
     if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
     // parent maps, checked level by level
     int nsub = c->plan0.in.n_sub;

@@ -31,7 +31,16 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def analyze(coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, face_averages=False):
+def _initial(initial, face_averages):
+    if face_averages:
+        initial = "c+e+f"
+    if initial not in _lib.INITIAL:
+        raise ValueError(f"initial constraints must be one of {sorted(_lib.INITIAL)}")
+    return _lib.INITIAL[initial]
+
+
+def analyze(coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, face_averages=False,
+            initial="c+e"):
     """Host-only level-1 structure counts and per-subdomain (n_I, n_Gamma)."""
     lib = _lib.load()
     co = np.ascontiguousarray(coords, dtype=np.float64)
@@ -44,7 +53,7 @@ def analyze(coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, face_avera
     out = _lib.Analysis()
     nsub = int(e2s.max()) + 1
     sizes = np.zeros(2 * nsub, dtype=np.int32)
-    _lib.check(lib.ambddc_analyze(C.byref(mesh), C.byref(dec), int(bool(face_averages)),
+    _lib.check(lib.ambddc_analyze(C.byref(mesh), C.byref(dec), _initial(initial, face_averages),
                                   C.byref(out), sizes.ctypes.data_as(C.c_void_p), nsub))
     d = {f: getattr(out, f) for f, _ in _lib.Analysis._fields_}
     d["sub_sizes"] = sizes.reshape(nsub, 2)
@@ -64,10 +73,14 @@ class Handle:
 
     def __init__(self, coords, elem_nodes, dirichlet, dof_per_node, elem_to_sub, parents=(),
                  levels=2, tau=10.0, nev_max=10, lobpcg_maxit=100, lobpcg_block=16,
-                 lobpcg_tol=1e-7, face_averages=False, seed=12345, stream=None, precision=0):
+                 lobpcg_tol=1e-7, face_averages=False, seed=12345, stream=None, precision=0,
+                 initial="c+e", keep_edges=False, fixed_per_face=0):
         """precision 0: FP64 throughout; 1: the PCG preconditioner's dense
         subdomain operators are kept in FP32 (widened to FP64 on load),
-        everything else in FP64."""
+        everything else in FP64.  initial: "c+e" (default), "c+e+f" (or
+        face_averages=True) or "c"; keep_edges: adaptive rows keep their
+        entries on shared edges and corners; fixed_per_face = k > 0: k
+        eigenvector constraints per face regardless of tau ("3eigv": 3)."""
         if precision not in (0, 1):
             raise ValueError("precision must be 0 or 1")
         lib = _lib.load()
@@ -90,7 +103,9 @@ class Handle:
         opt.lobpcg_maxit = int(lobpcg_maxit)
         opt.lobpcg_block = int(lobpcg_block)
         opt.lobpcg_tol = float(lobpcg_tol)
-        opt.face_averages = int(bool(face_averages))
+        opt.initial_constraints = _initial(initial, face_averages)
+        opt.keep_edges = int(bool(keep_edges))
+        opt.fixed_per_face = int(fixed_per_face)
         opt.precision = int(precision)
         opt.seed = int(seed)
         if stream is None:
@@ -100,6 +115,7 @@ class Handle:
         h = C.c_void_p()
         _lib.check(lib.ambddc_create(C.byref(mesh), C.byref(dec), C.byref(opt), C.byref(h)))
         self._h = h
+        self.setup_count = 0   # set-up calls on this handle (numeric state version)
         self.dof_per_node = dof_per_node
         self.precision = int(precision)
         self.n_elems = int(self._en.shape[0])
@@ -126,6 +142,7 @@ class Handle:
     # --- numeric calls --------------------------------------------------
     def setup(self, coeff, nu=None, check=True):
         """coeff, nu: float64 GPU tensors of length n_elems."""
+        self.setup_count += 1
         code = self._lib.ambddc_setup(self._h, _dev_ptr(coeff), None if nu is None else _dev_ptr(nu))
         if check:
             _lib.check(code)
@@ -153,6 +170,7 @@ class Handle:
 
     def setup_log10(self, theta, nu=None, check=True):
         """Set-up with coefficients 10^theta computed on the device."""
+        self.setup_count += 1
         code = self._lib.ambddc_setup_log10(self._h, _dev_ptr(theta),
                                             None if nu is None else _dev_ptr(nu))
         if check:
@@ -189,7 +207,8 @@ class Handle:
                     n_pairs=list(s.n_pairs[:L]), n_coarse=list(s.n_coarse[:L]),
                     n_adaptive=list(s.n_adaptive[:L]), lobpcg_iters=list(s.lobpcg_iters[:L]),
                     n_unconverged=list(s.n_unconverged[:L]),
-                    omega_tilde=list(s.omega_tilde[:L]), t_phase=list(s.t_phase[:8]))
+                    omega_tilde=list(s.omega_tilde[:L]), t_phase=list(s.t_phase[:8]),
+                    pcg_replacements=s.pcg_replacements)
 
     def level_info(self, level):
         a = [C.c_int32() for _ in range(4)]

@@ -4,7 +4,9 @@ FP64 oracle, central finite differences and the scaling identity.
 Workload C5: Poisson 32^3, 4x4x4 subdomains, theta ~ N(2,1) per element,
 8 unit point sources; x_obs from the perturbed theta_obs by the oracle's
 direct solve.  Tolerances: J and the gradient within 1e-8 (relative to
-max|g|) of the oracle's direct-solve gradient (PCG at rtol 1e-13); central
+max|g|) of the oracle's direct-solve gradient (PCG at rtol 1e-13), with the FP64 preconditioner
+and with its operators stored in FP32 (PCG on FP64 residuals refines the
+solutions to the same accuracy); central
 differences (h = 1e-4, the GPU solver at rtol 1e-13) within 1e-4 relative
 plus 1e-6 max|g| absolute; the scaling identity
 sum_e g_e = -ln10 sum_k (x_k - x_obs,k)^T x_k, exact since
@@ -51,20 +53,21 @@ def _case(name):
     return _CASES[name]
 
 
-def _gpu(prob):
+def _gpu(prob, precision=0):
     torch = torch_cuda()
     from paper_1301_0191_amd import Handle
-    h = Handle.from_problem(prob)
+    h = Handle.from_problem(prob, precision=precision)
     dev = torch.device("cuda:0")
     F = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to(dev)
     return torch, h, dev, F
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("name", ["tiny", "c5"])
-def test_autograd_gradient_matches_oracle(name):
-    log("CASE adjoint vs oracle", name)
+def test_autograd_gradient_matches_oracle(name, precision):
+    log("CASE adjoint vs oracle", name, "precision", precision)
     prob, theta, x_obs, fd, J_or, g_or, X_or = _case(name)
-    torch, h, dev, F = _gpu(prob)
+    torch, h, dev, F = _gpu(prob, precision)
     from paper_1301_0191_amd.adjoint import misfit
     th = torch.from_numpy(theta).to(dev).requires_grad_(True)
     xo = torch.from_numpy(np.ascontiguousarray(x_obs.T)).to(dev)
@@ -116,4 +119,24 @@ def test_gradient_scaling_identity_c5():
     assert J == pytest.approx(0.5 * float(np.sum(Rh * Rh)), rel=1e-12)
     rhs = -np.log(10.0) * float(np.sum(Rh * Xh))
     assert float(np.sum(g)) == pytest.approx(rhs, rel=1e-9)
+    h.close()
+
+
+def test_backward_after_another_forward_on_the_same_handle():
+    """The handle is set up at theta2 between forward(theta1) and backward:
+    the gradient must still be the one at theta1."""
+    log("CASE adjoint, interleaved forward")
+    prob, theta, x_obs, fd, J_or, g_or, X_or = _case("tiny")
+    torch, h, dev, F = _gpu(prob)
+    from paper_1301_0191_amd.adjoint import misfit
+    xo = torch.from_numpy(np.ascontiguousarray(x_obs.T)).to(dev)
+    th1 = torch.from_numpy(theta).to(dev).requires_grad_(True)
+    J1 = misfit(th1, h, F, xo, rtol=1e-13)
+    th2 = torch.from_numpy(theta + 0.3).to(dev).requires_grad_(True)
+    J2 = misfit(th2, h, F, xo, rtol=1e-13)
+    J1.backward()
+    g = th1.grad.cpu().numpy()
+    assert float(J1) == pytest.approx(J_or, rel=1e-9)
+    assert float(J2) != pytest.approx(J_or, rel=1e-3)
+    assert np.abs(g - g_or).max() <= 1e-8 * np.abs(g_or).max()
     h.close()

@@ -6,12 +6,15 @@ oracle cannot run the whole method in test time.
   eigenproblem and the largest one are solved densely by the oracle on its
   own level-1 structures (dense Schur complements of all subdomains) and
   compared with the library's eigenvalues, selected counts, first unselected
-  eigenvalue and constraint spans.
-* Properties that hold at any size: after a solve to recursive residual
-  1e-11, the true FP64 residual (K assembled by the oracle) is below
-  max(1e-10, the rounding floor 100 eps || |K| |x| || / ||f|| of a residual
-  computed in FP64) and agrees with the residual the library reports; the
-  condition estimate is >= 1; every pair converged.
+  eigenvalue and constraint spans (gpu_common.check_pair, which also checks
+  a selection that cuts a cluster against the span of the whole cluster).
+* Properties that hold at any size: the library stops a column only when
+  its recomputed true residual meets rtol (residual replacement), so after
+  a solve to rtol 5e-11 the true FP64 residual ||f - K x|| / ||f|| with K
+  assembled by the oracle is <= 1e-10 (the target; the margin covers the
+  rounding of the two residual evaluations) and agrees with the residual
+  the library reports; the condition estimate is >= 1; every pair
+  converged.
 """
 import numpy as np
 import pytest
@@ -20,7 +23,7 @@ import workloads as W
 from oracle import fem
 from oracle.adaptive import pair_eigenproblem
 from oracle.substructure import build_level, level1_input
-from gpu_common import gpu_handle, gpu_solve, subspace_gap
+from gpu_common import check_pair, gpu_handle, gpu_solve
 
 pytestmark = pytest.mark.gpu
 
@@ -43,42 +46,22 @@ def test_c3_sampled_pairs_and_true_residual():
     n_sel = 0
     for p in sample:
         s, t, g = L.pairs[p]
-        assert h.pair_info(0, p)[:2] == (s, t)
         r = pair_eigenproblem(L, s, t, L.globs[g], prob.tau, prob.nev_max)
-        gp = h.pair_result(0, p)
-        assert gp["converged"], p
-        kk = min(prob.nev_max + 1, len(r["lam"]))
-        lam_o = r["lam"][:kk]
-        err = np.abs(gp["lam"][:kk] - lam_o)
-        assert (err <= np.maximum(1e-6 * np.abs(lam_o), 1e-10 * abs(lam_o[0]))).all(), (p, err)
-        assert gp["k"] == len(r["rows"]), (p, gp["k"], len(r["rows"]))
-        if r["lam_next"] > 0:
-            assert gp["lam_next"] == pytest.approx(r["lam_next"], rel=1e-6)
-        if gp["k"] > 0:
-            n_sel += 1
-            rows, fd = h.face_constraints(0, p, gp["k"])
-            np.testing.assert_array_equal(fd, r["face_dofs"])
-            lam = r["lam"]
-            k = gp["k"]
-            cut_gap = (lam[k - 1] - lam[k]) / lam[k - 1] if k < len(lam) else 1.0
-            if cut_gap > 1e-3:
-                assert subspace_gap(rows, r["rows"]) <= 1e-6, p
-        log("  pair", p, "n", r["n"], "k", gp["k"], "lam1", lam_o[0])
+        k = check_pair(h, 0, p, L, r, prob, log=log)
+        n_sel += k > 0
+        log("  pair", p, "n", r["n"], "k", k, "lam1", r["lam"][0])
     log("  pairs with constraints in the sample:", n_sel)
     torch = pytest.importorskip("torch")
     rhs = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda:0")
-    out = h.solve(rhs, rtol=1e-11, maxit=2000)
+    out = h.solve(rhs, rtol=5e-11, maxit=2000)
     X = out.x.cpu().numpy().T
     K = fem.assemble_global(prob)
     f = prob.rhs
     res = np.linalg.norm(f - K @ X, axis=0) / np.linalg.norm(f, axis=0)
-    # rounding floor of the residual of any FP64 vector: each entry of K x is
-    # a sum of at most 81 products, so |fl(K x) - K x| <= ~81 eps |K| |x|
-    floor = 100 * np.finfo(float).eps * np.linalg.norm(abs(K) @ np.abs(X), axis=0) / \
-        np.linalg.norm(f, axis=0)
     log("  its", out.iterations, "cond", out.cond, "true residual", res, "library's",
-        out.true_residual, "rounding floor", floor)
-    assert (res <= np.maximum(1e-10, floor)).all()
-    assert np.allclose(out.true_residual, res, rtol=0.1, atol=1e-3 * floor.max())
+        out.true_residual, "residual replacements", h.stats()["pcg_replacements"])
+    assert (res <= 1e-10).all()
+    assert (np.asarray(out.true_residual) <= 5e-11).all()
+    assert np.allclose(out.true_residual, res, rtol=0.5, atol=1e-11)
     assert out.cond[0] >= 1.0 - 1e-9
     h.close()

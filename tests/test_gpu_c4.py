@@ -9,7 +9,8 @@ cannot run the whole method in test time.
   level-1 pair problems depend only on level-1 data).
 * Properties that hold at any size: every column's true FP64 residual
   ||f - K x|| / ||f||, with K assembled by the oracle, is <= 1e-10 after a
-  solve to recursive residual 1e-11; the
+  solve to rtol 5e-11 (the library checks the recomputed true residual
+  before it stops a column); the
   lockstep columns report their own iteration counts; condition estimates
   are >= 1; the level-2 pair results are converged and ordered.
 """
@@ -20,7 +21,7 @@ import workloads as W
 from oracle import fem
 from oracle.adaptive import pair_eigenproblem
 from oracle.substructure import build_level, level1_input
-from gpu_common import gpu_handle, gpu_solve, subspace_gap
+from gpu_common import check_pair, gpu_handle, gpu_solve
 
 pytestmark = pytest.mark.gpu
 
@@ -43,31 +44,14 @@ def test_c4_sampled_pairs_and_true_residuals():
     assert len(L.pairs) == 1344
     for p in range(0, 1344, 56):
         s, t, g = L.pairs[p]
-        assert h.pair_info(0, p)[:2] == (s, t)
         r = pair_eigenproblem(L, s, t, L.globs[g], prob.tau, prob.nev_max)
-        gp = h.pair_result(0, p)
-        assert gp["converged"]
-        kk = min(prob.nev_max + 1, len(r["lam"]))
-        lam_o = r["lam"][:kk]
-        err = np.abs(gp["lam"][:kk] - lam_o)
-        assert (err <= np.maximum(1e-6 * np.abs(lam_o), 1e-10 * abs(lam_o[0]))).all(), (p, err)
-        assert gp["k"] == len(r["rows"]), (p, gp["k"], len(r["rows"]))
-        if r["lam_next"] > 0:
-            assert gp["lam_next"] == pytest.approx(r["lam_next"], rel=1e-6)
-        if gp["k"] > 0:
-            rows, fd = h.face_constraints(0, p, gp["k"])
-            np.testing.assert_array_equal(fd, r["face_dofs"])
-            lam = r["lam"]
-            k = gp["k"]
-            cut_gap = (lam[k - 1] - lam[k]) / lam[k - 1] if k < len(lam) else 1.0
-            if cut_gap > 1e-3:
-                assert subspace_gap(rows, r["rows"]) <= 1e-6, p
+        check_pair(h, 0, p, L, r, prob, log=log)
     for p in range(12):
         gp = h.pair_result(1, p)
         assert gp["converged"]
         assert np.all(np.diff(gp["lam"][:prob.nev_max + 1]) <= 0)
     log("  pairs ok; solve")
-    X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-11)
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=5e-11)
     K = fem.assemble_global(prob)
     res = np.linalg.norm(prob.rhs - K @ X, axis=0) / np.linalg.norm(prob.rhs, axis=0)
     log("  its", its, "max residual", res.max())

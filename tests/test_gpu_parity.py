@@ -6,9 +6,17 @@ Tolerances (FP64 path):
 * K_c^s (explicit saddle inverse, conditioning up to ~1e8 with the
   coefficient jumps): 1e-8 relative;
 * pair eigenvalues: 1e-6 relative (the target); selected counts identical;
-  constraint spans: sine of the largest principal angle <= 1e-6 where the
-  cut eigenvalue gap is not tiny;
-* solution: ||x - x_direct|| / ||x_direct|| <= 1e-9 at rtol 1e-12.
+  constraint spans: sine of the largest principal angle <= 1e-6, or, where
+  the selection cuts a cluster of eigenvalues, the rows inside the span of
+  the whole cluster (gpu_common.check_pair);
+* solution: ||x - x_direct|| / ||x_direct|| <= 1e-10 (the north-star
+  target), at rtol 1e-12 on the small cases and 1e-13 on C1 and C2 (their
+  coefficient contrast of 1e6 makes K ill-conditioned: the oracle's own PCG
+  at rtol 1e-12 stops at an error of 6e-11 on C1).  Attained errors are
+  printed.
+* the variants of Section 8.2's tables (initial constraints c+e+f and c, the
+  fixed "3eigv" selection) and the keep-edges rows: the same bar against the
+  oracle run with the same options.
 """
 import numpy as np
 import pytest
@@ -16,7 +24,7 @@ import pytest
 import workloads as W
 import oracle as O
 from oracle.substructure import build_level, coarse_basis, level1_input
-from gpu_common import gpu_handle, gpu_solve, subspace_gap, torch_cuda
+from gpu_common import check_pair, gpu_handle, gpu_solve, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -70,48 +78,19 @@ def test_nonadaptive_pcg(case):
     X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
     Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-12, adaptive=False)
     xd = O.direct_solve(prob)
-    assert np.linalg.norm(X - xd) <= 1e-9 * np.linalg.norm(xd)
+    err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
+    log("  its", its, "oracle", ito, "err", err)
+    assert err <= 1e-10
     assert abs(its[0] - ito[0]) <= max(2, 0.05 * ito[0])
     assert cond[0] == pytest.approx(co[0], rel=1e-4)
     assert cond[0] >= 1.0 - 1e-9
     h.close()
 
 
-def check_pairs(h, prob, H, level=0):
+def check_pairs(h, prob, H, level=0, **okw):
     L = H.levels[level]
-    res = L.adaptive["results"]
-    nk = prob.nev_max + 1
-    for p, r in enumerate(res):
-        s, t, nf = h.pair_info(level, p)
-        assert (s, t) == (r["s"], r["t"])
-        g = h.pair_result(level, p)
-        assert g["converged"], (level, p, g["resid"])
-        kk = min(nk, len(r["lam"]))
-        # eigenvalues that vanish in exact arithmetic (pairs with few shared
-        # DOFs) are rounding noise on both sides (the dense oracle's at ~1e-12
-        # lambda_1): they are compared in absolute terms, 1e-10 lambda_1; all
-        # others to 1e-6 relative, and every eigenvalue within a decade of tau,
-        # which decides the selection, strictly relative
-        lam_o = r["lam"][:kk]
-        err = np.abs(g["lam"][:kk] - lam_o)
-        ok = err <= np.maximum(1e-6 * np.abs(lam_o), 1e-10 * abs(lam_o[0]))
-        assert ok.all(), (level, p, err, lam_o)
-        near = lam_o >= 0.1 * prob.tau
-        if near.any():
-            strict = np.abs(g["lam"][:kk] - lam_o)[near] / lam_o[near]
-            assert strict.max() <= 1e-6, (level, p, strict.max())
-        assert g["k"] == len(r["rows"]), (level, p, g["k"], len(r["rows"]))
-        if r["lam_next"] > 0:
-            assert g["lam_next"] == pytest.approx(r["lam_next"], rel=1e-6)
-        if g["k"] > 0:
-            rows, fd = h.face_constraints(level, p, g["k"])
-            np.testing.assert_array_equal(fd, r["face_dofs"])
-            lam = r["lam"]
-            k = g["k"]
-            cut_gap = (lam[k - 1] - lam[k]) / lam[k - 1] if k < len(lam) else 1.0
-            if cut_gap > 1e-3:
-                assert subspace_gap(rows, r["rows"]) <= 1e-6, (level, p)
-            np.testing.assert_allclose(rows @ rows.T, np.eye(k), atol=1e-10)
+    for p, r in enumerate(L.adaptive["results"]):
+        check_pair(h, level, p, L, r, prob, log=log, **okw)
 
 
 @pytest.mark.parametrize("case", ["poisson", "poisson_ragged", "elasticity", "c1", "c2"])
@@ -125,12 +104,61 @@ def test_adaptive_parity_and_solution(case):
     assert st["n_coarse"][0] == H.stats["n_coarse"][0]
     assert st["omega_tilde"][0] == pytest.approx(H.stats["omega"][0], rel=1e-6)
     check_pairs(h, prob, H)
-    X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
+    rtol = 1e-13 if case in ("c1", "c2") else 1e-12
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=rtol, raise_on_noconv=False)
     xd = O.direct_solve(prob)
     err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
-    log("  its", its, "cond", cond, "err", err)
-    assert err <= 1e-9
+    log("  its", its, "cond", cond, "err", err, "replacements", h.stats()["pcg_replacements"])
+    assert err <= 1e-10
     assert cond[0] >= 1.0 - 1e-9
+    h.close()
+
+
+VARIANTS = {
+    # name: (case, library options, oracle options)
+    "poisson_cef": ("poisson", dict(initial="c+e+f"), dict(face_averages=True)),
+    "elasticity_cef": ("elasticity", dict(initial="c+e+f"), dict(face_averages=True)),
+    "poisson_c": ("poisson", dict(initial="c"), dict(corners_only=True)),
+    "elasticity_3eigv": ("elasticity", dict(fixed_per_face=3), dict(fixed=3)),
+    "poisson_ragged_3eigv": ("poisson_ragged", dict(fixed_per_face=3), dict(fixed=3)),
+    "poisson_keep_edges": ("poisson", dict(keep_edges=True), dict(keep_edges=True)),
+    "ragged_keep_edges": ("poisson_ragged", dict(keep_edges=True), dict(keep_edges=True)),
+    "elasticity_keep_edges": ("elasticity", dict(keep_edges=True), dict(keep_edges=True)),
+    "c1_keep_edges": ("c1", dict(keep_edges=True), dict(keep_edges=True)),
+    "c2_keep_edges": ("c2", dict(keep_edges=True), dict(keep_edges=True)),
+}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_constraint_variants(variant):
+    """Initial constraint sets c / c+e+f, the fixed "3eigv" selection and the
+    keep-edges rows (Section 7, Section 8.2) against the oracle with the same
+    options: counts, pair eigenvalues, rows, coarse matrices, solution."""
+    log("CASE variant", variant)
+    case, lopt, oopt = VARIANTS[variant]
+    prob = TINY[case]() if case in TINY else W.CONFIGS[case](0)
+    h = gpu_handle(prob, **lopt)
+    H = O.setup_hierarchy(prob, **oopt)
+    st = h.stats()
+    assert st["n_adaptive"][0] == H.stats["n_adaptive"][0]
+    assert st["n_coarse"][0] == H.stats["n_coarse"][0]
+    if H.stats["omega"][0] > 0:
+        assert st["omega_tilde"][0] == pytest.approx(H.stats["omega"][0], rel=1e-6)
+    pk = {k: v for k, v in oopt.items() if k in ("keep_edges", "fixed")}
+    check_pairs(h, prob, H, **pk)
+    L = H.levels[0]
+    for s in range(L.inp.n_sub):
+        Kc = h.coarse_element(0, s)
+        assert np.linalg.norm(Kc - L.Kc[s]) <= 1e-8 * np.linalg.norm(L.Kc[s]), s
+    rtol = 1e-13 if case in ("c1", "c2") else 1e-12
+    X, its, cond = gpu_solve(h, prob.rhs, rtol=rtol, raise_on_noconv=False)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-12, H=H)
+    xd = O.direct_solve(prob)
+    err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
+    log("  its", its, "oracle", ito, "cond", cond, co, "omega", st["omega_tilde"], "err", err)
+    assert err <= 1e-10
+    assert cond[0] >= 1.0 - 1e-9
+    assert cond[0] == pytest.approx(co[0], rel=1e-3) or abs(its[0] - ito[0]) <= 2
     h.close()
 
 
@@ -148,7 +176,9 @@ def test_three_level_parity():
     X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-12)
     Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-12, H=H)
     xd = O.direct_solve(prob)
-    assert np.linalg.norm(X - xd) <= 1e-9 * np.linalg.norm(xd)
+    err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
+    log("  its", its, "oracle", ito, "err", err)
+    assert err <= 1e-10
     assert abs(its[0] - ito[0]) <= max(2, 0.05 * ito[0])
     assert cond[0] == pytest.approx(co[0], rel=1e-3)
     h.close()
@@ -164,7 +194,7 @@ def test_multiple_rhs_lockstep():
         x1, it1, c1 = gpu_solve(h, prob.rhs[:, j:j + 1], rtol=1e-12)
         assert it1[0] == its[j]
         np.testing.assert_allclose(X[:, j], x1[:, 0], rtol=0, atol=1e-13 * np.abs(x1).max())
-        assert np.linalg.norm(X[:, j] - xd[:, j]) <= 1e-9 * np.linalg.norm(xd[:, j])
+        assert np.linalg.norm(X[:, j] - xd[:, j]) <= 1e-10 * np.linalg.norm(xd[:, j])
     h.close()
 
 

@@ -52,7 +52,7 @@ def test_default_options_without_gpu():
     assert opt.precision == 0
 
 
-def _oracle_structure(prob, face_averages=False):
+def _oracle_structure(prob, initial="c+e"):
     """Level-1 structure counts from the oracle's own classification."""
     import numpy as np
     from oracle.substructure import classify, level1_input
@@ -71,7 +71,8 @@ def _oracle_structure(prob, face_averages=False):
     for g in globs:
         if g["type"] == "corner":
             n_coarse += len(g["dofs"])
-        elif g["type"] == "edge" or (g["type"] == "face" and face_averages):
+        elif (g["type"] == "edge" and initial != "c") or (g["type"] == "face" and
+                                                           initial == "c+e+f"):
             n_coarse += len(np.unique(inp.dof_comp[g["dofs"]]))
     return dict(n_free=inp.n_dof, n_sub=inp.n_sub, n_interface=int(dof_iface.sum()),
                 n_faces=types.count("face"), n_edges=types.count("edge"),
@@ -100,10 +101,10 @@ def test_host_analysis_matches_oracle_classification(case):
         # uneven boxes with elasticity DOFs, like the elasticity workload's cuts
         prob = W.make_problem((20, 18, 16), None, dof_per_node=3, seed=4,
                               cuts=[[0, 5, 11, 20], [0, 7, 18], [0, 6, 10, 16]])
-    for fa in (False, True):
+    for fa in ("c+e", "c+e+f", "c"):
         got = analyze(prob.coords, prob.elem_nodes, prob.dirichlet, prob.dof_per_node,
-                      prob.elem_to_sub, face_averages=fa)
-        want = _oracle_structure(prob, face_averages=fa)
+                      prob.elem_to_sub, initial=fa)
+        want = _oracle_structure(prob, initial=fa)
         for k in ("n_free", "n_sub", "n_interface", "n_faces", "n_edges", "n_corners",
                   "n_coarse_initial", "n_pairs"):
             assert got[k] == want[k], (case, fa, k, got[k], want[k])
