@@ -48,11 +48,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1, 2],
                     help="mode of the timed headline steps: 0 = FP64 throughout, 1 = the PCG "
-                         "preconditioner's dense subdomain operators stored in FP32")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the steps in the other precision mode")
+                         "preconditioner's dense subdomain operators stored in FP32, 2 = also "
+                         "the pair LOBPCG's operator products in FP32 (MFMA, FP32 "
+                         "accumulation) before an FP64 polish")
+    ap.add_argument("--compare", default="0,2",
+                    help="precision modes also timed on the same workload (comma-separated; "
+                         "empty for none)")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="subdomains (and about as many pairs) the oracle handles for a "
                          "sampled CPU baseline, scaled to the whole workload by operation "
@@ -280,7 +283,7 @@ def main():
 
         def step():
             h.setup(coeff, nu)
-            return h.solve(rhs, rtol=args.rtol, maxit=2000, x=x)
+            return h.solve(rhs, rtol=args.rtol, maxit=2000, x=x, raise_on_noconv=False)
 
         for i in range(args.warmup):
             step()
@@ -323,7 +326,10 @@ def main():
         return kernels
 
     main_m = run(args.precision)
-    other_m = run(1 - args.precision) if not args.no_compare else None
+    others = {}
+    for tok in (args.compare or "").split(","):
+        if tok.strip() and int(tok) != args.precision:
+            others[int(tok)] = run(int(tok))
     timed, T, res, st = main_m["timed"], main_m["T"], main_m["res"], main_m["st"]
     kernels = kernel_table(main_m)
     dom = max((c for c in SINGLE_KERNEL if c in kernels), key=lambda c: timed[c]["ms"],
@@ -352,16 +358,26 @@ def main():
                 "pcg_iterations": r.iterations,
                 "true_residual_max": max(r.true_residual) if r.true_residual else None,
                 "adaptive_constraints": m["st"]["n_adaptive"],
+                "omega_tilde": m["st"]["omega_tilde"],
                 "lobpcg_iterations": m["st"]["lobpcg_iters"],
+                "lobpcg_iterations_fp32": m["st"]["lobpcg_iters_fp32"],
+                "lobpcg_select_s": m["st"]["t_phase"][2],
+                "pair_apply": {kk: k["pair_apply"][kk] for kk in ("avg_launch_us", "tflops")}
+                if "pair_apply" in k else None,
                 "bddc_apply": {kk: k["bddc_apply"][kk] for kk in ("avg_launch_us", "gbps")}
                 if "bddc_apply" in k else None}
 
     modes = None
-    if other_m is not None:
-        by_p = {args.precision: main_m, 1 - args.precision: other_m}
-        modes = {"fp64": mode_summary(by_p[0]), "fp32_stored_preconditioners": mode_summary(by_p[1])}
-        modes["speedup_fp32_stored_vs_fp64"] = (modes["fp64"]["ms_per_step"]
-                                                / modes["fp32_stored_preconditioners"]["ms_per_step"])
+    names = {0: "fp64", 1: "fp32_stored_preconditioners", 2: "fp32_lobpcg_and_preconditioners"}
+    if others:
+        by_p = dict(others)
+        by_p[args.precision] = main_m
+        modes = {names[pm]: mode_summary(mm) for pm, mm in sorted(by_p.items())}
+        if 0 in by_p:
+            t64 = float(np.median(by_p[0]["step_s"]))
+            for pm, mm in by_p.items():
+                if pm != 0:
+                    modes[f"speedup_{names[pm]}_vs_fp64"] = t64 / float(np.median(mm["step_s"]))
     out = {
         "metric": METRIC,
         "value": float(np.median(main_m["step_s"])),
@@ -373,7 +389,9 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f64 (preconditioner operators stored f32)",
+        "dtype": {0: "f64", 1: "f64 (preconditioner operators stored f32)",
+                  2: "f32 MFMA (pair LOBPCG products, preconditioner operators) + f64 (Gram, "
+                     "Rayleigh-Ritz, polish, Schur, PCG residuals)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": prob.name, "n_free": st["n_free"], "subdomains": st["n_sub"],
                    "pairs": st["n_pairs"], "levels": prob.levels, "tau": prob.tau,
@@ -385,6 +403,7 @@ def main():
         "analysis_s": main_m["analysis_s"],
         "pcg_iterations": res.iterations,
         "pcg_residual_replacements": st["pcg_replacements"],
+        "pcg_converged": bool(res.true_residual) and max(res.true_residual) <= args.rtol,
         "true_residual_max": max(res.true_residual) if res.true_residual else None,
         "cond": res.cond,
         "lobpcg_iterations": st["lobpcg_iters"],

@@ -80,15 +80,25 @@ typedef struct {
   int32_t lobpcg_maxit;        /* LOBPCG iteration cap (e.g. 100) */
   int32_t lobpcg_block;        /* LOBPCG block size m >= nev_max+1 (e.g. 16) */
   double lobpcg_tol;           /* relative residual tolerance (e.g. 1e-8) */
-  int32_t precision;           /* 0 = FP64 everywhere; 1 = the dense subdomain
-                                  operators of the PCG preconditioner (Alg. 1 on
-                                  every substructured level) stored in FP32 and
-                                  widened to FP64 on load.  Everything else (Schur
-                                  complements, the whole adaptive set-up, the
-                                  coarsest problem, PCG vectors and residuals) stays
-                                  FP64, so PCG, which iterates on FP64 residuals,
-                                  reaches the same FP64 accuracy; only iteration
-                                  counts can change. */
+  int32_t precision;           /* 0 = FP64 everywhere.
+                                  1 = the dense subdomain operators of the PCG
+                                  preconditioner (Alg. 1 on every substructured
+                                  level) stored in FP32 and widened to FP64 on load;
+                                  PCG iterates on FP64 residuals, so it reaches the
+                                  same FP64 accuracy (iterative refinement around
+                                  the rounded preconditioner).
+                                  2 = precision 1, and the pair LOBPCG starts with
+                                  its operator products (S^s, and the Neumann
+                                  inverse and coarse basis of the pair
+                                  preconditioner) on FP32 copies with FP32 MFMA
+                                  accumulation; each pair moves to FP64 products
+                                  once its residual reaches 1e-5 or stops halving
+                                  over three iterations, and converges to
+                                  lobpcg_tol in FP64, so eigenvalues, the tau
+                                  decision and the constraints are those of FP64.
+                                  Gram matrices, Rayleigh-Ritz, orthogonalisation,
+                                  Schur complements and the coarsest problem stay
+                                  FP64 in every mode. */
   int32_t initial_constraints; /* initial coarse DOFs (Section 7; the variants of
                                   Section 8.2's tables): AMBDDC_INIT_CE (0) corners and
                                   one arithmetic average per edge and displacement
@@ -159,15 +169,38 @@ ambddc_status ambddc_setup(ambddc_handle h, const double* coeff_dev, const doubl
  * ||f - K x||_2 / ||f||_2 <= rtol per column (FP64 residual).  The
  * iteration updates the residual recursively; when that meets rtol, the true
  * residual f - K x is recomputed, and a column stops only if it meets rtol
- * too, otherwise it continues from the true residual (residual replacement).
+ * too; otherwise it restarts from the true residual (residual replacement),
+ * unless the true residual fell by less than half since the column's
+ * previous check: then rtol lies below what FP64 attains on this system
+ * (the rounding floor of f - K x) and the column stops, counted in
+ * ambddc_stats.pcg_stalled, with E_NO_CONVERGENCE.
  * rhs_dev, x_dev: device [n_free*nrhs] column-major (ld = n_free).
  * iterations_host[nrhs], cond_host[nrhs] (Lanczos estimate of the
  * preconditioned condition number) may be NULL.  The columns are
  * independent recurrences advanced in lockstep.  Errors: E_STATE before
- * setup, E_NO_CONVERGENCE (x holds the last iterate), E_DEVICE. */
+ * setup, E_NO_CONVERGENCE (maxit reached or a stalled column; x holds the
+ * last iterate and ambddc_last_residual its true residuals), E_DEVICE. */
 ambddc_status ambddc_solve(ambddc_handle h, const double* rhs_dev, int32_t nrhs, double rtol,
                            int32_t maxit, double* x_dev, int32_t* iterations_host,
                            double* cond_host);
+
+/* ambddc_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same PCG and preconditioner, with every scratch buffer of the solve
+ * (the PCG columns, dot products, coefficient histories, column flags) in
+ * one fixed device array of 64 MiB per GPU, held until the process ends; it
+ * calls no device allocator.  Arguments, results and errors as ambddc_solve,
+ * and the results are identical to it.  Limits, rejected with
+ * E_INVALID_ARG: nrhs in 1..3, no more than the preconditioner's workspace
+ * of the handle holds (1 after set-up; an ambddc_solve with more columns
+ * prepares more), and (4 n_free + 2 maxit + 270) nrhs doubles must fit in
+ * the array (n_free nrhs up to about two million).  Every call on a GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (from two
+ * threads or two streams) race and must not be issued; each call
+ * initialises what it reads. */
+ambddc_status ambddc_solve_noalloc(ambddc_handle h, const double* rhs_dev, int32_t nrhs,
+                                   double rtol, int32_t maxit, double* x_dev,
+                                   int32_t* iterations_host, double* cond_host);
 
 /* True relative residuals ||f_k - K x_k||_2 / ||f_k||_2 of the last
  * ambddc_solve (recomputed with one product by K after the iteration, which
@@ -203,6 +236,8 @@ typedef struct {
   int32_t n_coarse[8];           /* coarse DOFs after enrichment */
   int32_t n_adaptive[8];         /* adaptive constraints added */
   int32_t lobpcg_iters[8];       /* LOBPCG iterations run (lockstep) */
+  int32_t lobpcg_iters_fp32[8];  /* of those, iterations in which some pair ran FP32
+                                    products (precision 2) */
   int32_t n_unconverged[8];      /* pairs not converged at lobpcg_maxit */
   double omega_tilde[8];         /* max over pairs of the first unselected eigenvalue */
   double t_phase[16];            /* seconds: 0 assembly+Schur, 1 BDDC init, 2 LOBPCG,
@@ -211,6 +246,8 @@ typedef struct {
   int32_t pcg_replacements;      /* residual replacements in the last solve: columns whose
                                     recursive residual met rtol while the recomputed
                                     f - K x did not, and which went on from the latter */
+  int32_t pcg_stalled;           /* columns of the last solve stopped because their true
+                                    residual no longer fell above rtol (E_NO_CONVERGENCE) */
 } ambddc_stats;
 
 ambddc_status ambddc_get_stats(ambddc_handle h, ambddc_stats* out);

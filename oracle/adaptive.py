@@ -33,6 +33,7 @@ import numpy as np
 import scipy.linalg as sla
 
 QR_RANK_TOL = 1e-10
+ZERO_EIG = 1e-9       # pair eigenvalues below ZERO_EIG max(1, lambda_1) are rounding zeros
 
 
 def pair_operators(L, s, t):
@@ -92,7 +93,7 @@ def pair_eigenproblem(L, s, t, face_glob, tau, nev_max, keep_edges=False, fixed=
     to zero (Section 7); then a reduced QR orthonormalises them.
 
     k is min(#{lambda > tau}, nev_max) (Alg. 2), or, with fixed > 0, the
-    fixed count min(fixed, n_factor) regardless of tau (the "3eigv" runs of
+    fixed count min(fixed, #{lambda > rounding zero}) regardless of tau (the "3eigv" runs of
     Section 8.2: three eigenvector constraints per face in place of the
     face averages).  span_upto > 0 also returns, as "span_rows", the
     orthonormalised rows of the first span_upto eigenvectors (used to check
@@ -120,7 +121,9 @@ def pair_eigenproblem(L, s, t, face_glob, tau, nev_max, keep_edges=False, fixed=
     lam = lam[::-1]
     W = W[:, ::-1]
     if fixed > 0:
-        k = int(min(fixed, len(lam)))
+        # an eigenvalue that is zero up to rounding gives c = A w = 0: no
+        # constraint, so the fixed count never takes one
+        k = int(min(fixed, np.count_nonzero(lam > ZERO_EIG * max(1.0, lam[0]))))
     else:
         k = int(min(np.count_nonzero(lam > tau), nev_max))
     lam_next = float(lam[k]) if k < len(lam) else 0.0

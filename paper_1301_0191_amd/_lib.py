@@ -49,8 +49,10 @@ class Stats(C.Structure):
     _fields_ = [("levels", C.c_int32), ("n_free", C.c_int32), ("n_sub", C.c_int32 * 8),
                 ("n_pairs", C.c_int32 * 8), ("n_coarse", C.c_int32 * 8),
                 ("n_adaptive", C.c_int32 * 8), ("lobpcg_iters", C.c_int32 * 8),
+                ("lobpcg_iters_fp32", C.c_int32 * 8),
                 ("n_unconverged", C.c_int32 * 8), ("omega_tilde", C.c_double * 8),
-                ("t_phase", C.c_double * 16), ("pcg_replacements", C.c_int32)]
+                ("t_phase", C.c_double * 16), ("pcg_replacements", C.c_int32),
+                ("pcg_stalled", C.c_int32)]
 
 
 class Analysis(C.Structure):
@@ -70,6 +72,9 @@ _SIGS = {
     "ambddc_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ambddc_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
                                C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "ambddc_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                       C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double)]),
     "ambddc_element_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_void_p]),
     "ambddc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),

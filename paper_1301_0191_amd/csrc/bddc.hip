@@ -356,11 +356,15 @@ void launch_pcg_update_x_r(int n, int nrhs, const double* rz, const double* pq, 
   AMB_LAUNCH_CHECK();
 }
 
+// beta = rz_new / rz; 0 for a column whose residual was just replaced by
+// the true one (restart: p = z), whose repl flag is cleared here.
 __global__ void k_pcg_beta(int nrhs, const double* rz_new, double* rz, double* beta,
-                           const int* active, double* bhist, int it, int maxit) {
+                           const int* active, int* repl, double* bhist, int it, int maxit) {
   const int c = threadIdx.x;
   if (c >= nrhs) return;
-  const double b = active[c] ? rz_new[c] / rz[c] : 0.0;
+  const bool restart = repl && repl[c];
+  if (restart) repl[c] = 0;
+  const double b = active[c] && !restart ? rz_new[c] / rz[c] : 0.0;
   beta[c] = b;
   if (active[c]) {
     bhist[it + (size_t)c * maxit] = b;
@@ -378,12 +382,108 @@ __global__ void k_pcg_p(int n, const double* beta, const int* active, double* p,
 
 // beta = rz_new / rz (stored after rz_new in the same array: rz_new[nrhs..2nrhs) used as scratch)
 void launch_pcg_update_p(int n, int nrhs, const double* rz_new, double* rz, const int* active,
-                         double* p, const double* z, double* beta_hist, int it, int maxit,
-                         hipStream_t st) {
+                         int* restart, double* p, const double* z, double* beta_hist, int it,
+                         int maxit, hipStream_t st) {
   double* beta = rz + nrhs;   // scratch right after rz
-  k_pcg_beta<<<1, 64, 0, st>>>(nrhs, rz_new, rz, beta, active, beta_hist, it, maxit);
+  k_pcg_beta<<<1, 64, 0, st>>>(nrhs, rz_new, rz, beta, active, restart, beta_hist, it, maxit);
   dim3 g(ceil_div(n, 256), nrhs);
   k_pcg_p<<<g, 256, 0, st>>>(n, beta, active, p, z);
+  AMB_LAUNCH_CHECK();
+}
+
+// PCG column flags, kept on the device (one thread per column, nrhs <= 64).
+// cnt[0]: columns whose recursive residual met rtol in this iteration,
+// cnt[1]: active columns, cnt[2]: residual replacements of this check.
+__global__ void k_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* repl,
+                                 int* stall, double* tprev, int* cnt) {
+  const int c = threadIdx.x;
+  if (c < nrhs) {
+    act[c] = ff[c] > 0.0 ? 1 : 0;
+    nal[c] = 0;
+    repl[c] = 0;
+    stall[c] = 0;
+    tprev[c] = 0.0;
+  }
+  __syncthreads();
+  if (c == 0) {
+    int a = 0;
+    for (int k = 0; k < nrhs; ++k) a += act[k];
+    cnt[0] = 0;
+    cnt[1] = a;
+    cnt[2] = 0;
+    cnt[3] = 0;
+  }
+}
+
+void launch_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* repl, int* stall,
+                           double* tprev, int* cnt, hipStream_t st) {
+  k_pcg_init_flags<<<1, 64, 0, st>>>(nrhs, ff, act, nal, repl, stall, tprev, cnt);
+  AMB_LAUNCH_CHECK();
+}
+
+// After iteration `it`: every active column has taken it + 1 steps; meets[c]
+// says its recursive residual rr[c] <= rtol^2 ff[c].
+__global__ void k_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2,
+                            const int* act, int* nal, int* meets, int* cnt, int it) {
+  const int c = threadIdx.x;
+  if (c < nrhs) {
+    const int m = act[c] && rr[c] <= rtol2 * ff[c];
+    meets[c] = m;
+    if (act[c]) nal[c] = it + 1;
+  }
+  __syncthreads();
+  if (c == 0) {
+    int k = 0;
+    for (int j = 0; j < nrhs; ++j) k += meets[j];
+    cnt[0] = k;
+  }
+}
+
+void launch_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2, const int* act,
+                      int* nal, int* meets, int* cnt, int it, hipStream_t st) {
+  k_pcg_meets<<<1, 64, 0, st>>>(nrhs, rr, ff, rtol2, act, nal, meets, cnt, it);
+  AMB_LAUNCH_CHECK();
+}
+
+// For the columns in meets, with their true residuals tt: the column stops
+// (act = 0) if tt <= rtol^2 ff; it stops as stalled (stall = 1) if the true
+// residual fell by less than half since the column's previous check (tprev:
+// the rounding floor of f - K x in FP64 is reached above rtol); otherwise it
+// is marked for residual replacement (repl = 1, which also restarts its
+// search direction).  cnt[3] counts stalled columns.
+__global__ void k_pcg_true(int nrhs, const double* tt, const double* ff, double rtol2, int* act,
+                           const int* meets, int* repl, int* stall, double* tprev, int* cnt) {
+  const int c = threadIdx.x;
+  if (c < nrhs && meets[c]) {
+    const double t = tt[c];
+    if (t <= rtol2 * ff[c]) {
+      act[c] = 0;
+    } else if (tprev[c] > 0.0 && t > 0.25 * tprev[c]) {
+      act[c] = 0;
+      stall[c] = 1;
+    } else {
+      repl[c] = 1;
+      tprev[c] = t;
+    }
+  }
+  __syncthreads();
+  if (c == 0) {
+    int a = 0, r = 0, sl = 0;
+    for (int j = 0; j < nrhs; ++j) {
+      a += act[j];
+      r += repl[j];
+      sl += stall[j];
+    }
+    cnt[1] = a;
+    cnt[2] = r;
+    cnt[3] = sl;
+  }
+}
+
+void launch_pcg_true(int nrhs, const double* tt, const double* ff, double rtol2, int* act,
+                     const int* meets, int* repl, int* stall, double* tprev, int* cnt,
+                     hipStream_t st) {
+  k_pcg_true<<<1, 64, 0, st>>>(nrhs, tt, ff, rtol2, act, meets, repl, stall, tprev, cnt);
   AMB_LAUNCH_CHECK();
 }
 

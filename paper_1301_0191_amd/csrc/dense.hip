@@ -13,9 +13,46 @@ __device__ __forceinline__ int ceil_div_dev(int a, int b) { return (a + b - 1) /
 // GEMM
 // --------------------------------------------------------------------------
 
+// Column-slot test of a tile: does any slot in [c0, c1] belong to an item
+// whose flags meet the mask?
+__device__ __forceinline__ bool slots_live(const GemmDesc& g, int c0, int c1, const int* act,
+                                           int mask, int excl) {
+  bool any = false, veto = false;
+  for (int j = c0 / g.scols; j <= c1 / g.scols; ++j) {
+    const int a = act[g.spair[j]];
+    any = any || (a & mask) != 0;
+    veto = veto || (a & excl) != 0;
+  }
+  return any && !veto;
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_f32(const GemmDesc* __restrict__ d, int nd,
+                                                  double alpha, double beta,
+                                                  const int* __restrict__ act, int mask,
+                                                  int excl) {
+  __shared__ TileSmem32<WM, WN> sm;
+  const int tile = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc g = d[lo];
+  if (g.flag && *g.flag == 0) return;
+  const int lt = tile - g.tile_start;
+  const int tm = lt % g.tiles_m, tn = lt / g.tiles_m;
+  if (g.scols > 0 &&
+      !slots_live(g, tn * 32 * WN, min(g.N, (tn + 1) * 32 * WN) - 1, act, mask, excl))
+    return;
+  mfma_tile_f32<WM, WN>(static_cast<const float*>(g.A), g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N,
+                        g.K, tm * 32 * WM, tn * 32 * WN, alpha, beta, sm);
+}
+
 template <bool TA, bool TB, int WM, int WN, typename TAe>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, int nd, double alpha,
-                                              double beta, const int* __restrict__ act) {
+                                              double beta, const int* __restrict__ act, int mask,
+                                              int excl) {
   __shared__ TileSmem<WM, WN> sm;
   const int tile = blockIdx.x;
   int lo = 0, hi = nd - 1;
@@ -30,9 +67,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, in
   if (g.scols > 0) {
     const int c0 = tn * TileShape<WM, WN>::TN;
     const int c1 = min(g.N, c0 + TileShape<WM, WN>::TN) - 1;
-    bool any = false;
-    for (int j = c0 / g.scols; j <= c1 / g.scols; ++j) any = any || act[g.spair[j]] != 0;
-    if (!any) return;
+    if (!slots_live(g, c0, c1, act, mask, excl)) return;
   }
   mfma_tile<TA, TB, WM, WN>(static_cast<const TAe*>(g.A), g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N,
                             g.K, tm * TileShape<WM, WN>::TM, tn * TileShape<WM, WN>::TN, alpha,
@@ -58,7 +93,7 @@ __global__ __launch_bounds__(256) void k_split_sum(const SplitDesc* __restrict__
 void GemmOp::finalize(hipStream_t st) {
   const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
   hs.clear();
-  if (ksplit != 1 && !h.empty()) {
+  if (ksplit != 1 && !h.empty() && !f32) {
     int t0 = 0, kmin = 1 << 30;
     for (const auto& g : h) {
       if (g.scols > 0) throw Error(1, "GemmOp: split-K with column slots");
@@ -109,10 +144,10 @@ template <bool TA, bool TB, typename TAe>
 static void gemm_dispatch(const GemmOp& op, double alpha, double beta, hipStream_t st) {
   if (op.narrow)
     k_gemm<TA, TB, 4, 1, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta,
-                                                        op.act);
+                                                        op.act, op.act_mask, op.act_excl);
   else
     k_gemm<TA, TB, 2, 2, TAe><<<op.tiles, 256, 0, st>>>(op.d.p, int(op.h.size()), alpha, beta,
-                                                        op.act);
+                                                        op.act, op.act_mask, op.act_excl);
 }
 
 template <typename TAe>
@@ -125,6 +160,17 @@ static void gemm_run(const GemmOp& op, double alpha, double beta, hipStream_t st
 
 void GemmOp::run(double alpha, double beta, hipStream_t st) const {
   if (h.empty() || tiles == 0) return;
+  if (f32) {
+    if (ta || tb || !hs.empty()) throw Error(1, "GemmOp: FP32 products are not transposed or split");
+    if (narrow)
+      k_gemm_f32<4, 1><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act, act_mask,
+                                              act_excl);
+    else
+      k_gemm_f32<2, 2><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act, act_mask,
+                                              act_excl);
+    AMB_LAUNCH_CHECK();
+    return;
+  }
   if (a32 && ta) throw Error(1, "GemmOp: FP32 operands are panel-packed, not transposed");
   if (!hs.empty()) {
     gemm_run<double>(*this, 1.0, 0.0, st);   // partial products
@@ -146,6 +192,10 @@ void TunedGemm::drop_events() {
 }
 
 void TunedGemm::run(double alpha, double beta, hipStream_t st) {
+  if (follow) {
+    v[*follow >= 0 ? *follow : 0].run(alpha, beta, st);
+    return;
+  }
   if (!choice || *choice >= 0) {
     v[choice ? *choice : 0].run(alpha, beta, st);
     return;
@@ -170,6 +220,45 @@ void TunedGemm::run(double alpha, double beta, hipStream_t st) {
     }
   *choice = t[1] < t[0] ? 1 : 0;
   drop_events();
+}
+
+// --------------------------------------------------------------------------
+// FP32 copies of dense blocks (one workgroup per 4096 entries)
+// --------------------------------------------------------------------------
+
+constexpr int CVT_PER_WG = 4096;
+
+__global__ __launch_bounds__(256) void k_cvt_f32(const CvtDesc* __restrict__ d, int nd) {
+  const int wg = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
+  }
+  const CvtDesc g = d[lo];
+  const int64_t n = int64_t(g.rows) * g.cols;
+  const int64_t e0 = int64_t(wg - g.wg_start) * CVT_PER_WG;
+  for (int64_t e = e0 + threadIdx.x; e < min(n, e0 + CVT_PER_WG); e += 256) {
+    const int64_t r = e % g.rows, c = e / g.rows;
+    g.dst[r + c * g.ldd] = static_cast<float>(g.src[r + c * g.lds]);
+  }
+}
+
+void convert_blocks_f32(const std::vector<CvtDesc>& blocks, hipStream_t st) {
+  std::vector<CvtDesc> h;
+  int wgs = 0;
+  for (CvtDesc b : blocks) {
+    const int64_t n = int64_t(b.rows) * b.cols;
+    if (n <= 0) continue;
+    b.wg_start = wgs;
+    wgs += ceil_div(n, CVT_PER_WG);
+    h.push_back(b);
+  }
+  if (h.empty()) return;
+  DBuf<CvtDesc> d;
+  d.upload(h, st);
+  k_cvt_f32<<<wgs, 256, 0, st>>>(d.p, int(h.size()));
+  AMB_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------------------------

@@ -42,7 +42,14 @@ class GemmOp {
  public:
   bool ta = false, tb = false, narrow = false;  // narrow: 128x32 tiles (N <= 32)
   bool a32 = false;                             // A operands are FP32 (GemvOp copies)
+  // f32: A operands are plain column-major FP32 (lda), B is rounded to FP32
+  // as it is staged, and the products accumulate in FP32 on FP32 MFMA; C
+  // stays FP64.  Not transposed, no split-K.
+  bool f32 = false;
   const int* act = nullptr;                     // item flags for column-slot skipping
+  int act_mask = ~0;                            // a slot counts when (act[item] & act_mask) != 0
+  int act_excl = 0;                             // ... and a tile is skipped when any of its
+                                                // slots has (act[item] & act_excl) != 0
   // Split-K: 0 = chosen at finalize (products with few tiles and long K are
   // split so that the launch has about SPLIT_TARGET workgroups), 1 = never.
   // Each product's K range is cut into S pieces whose partial products go to
@@ -76,25 +83,33 @@ class TunedGemm {
   static constexpr int TUNE_CALLS = 3;
   GemmOp v[2];
   int* choice = nullptr;   // -1: still measuring; null: always v[0]
+  // follow: take the shape another op has chosen (v[0] until it has) and
+  // never measure (for an op whose early calls have no work to time)
+  const int* follow = nullptr;
   TunedGemm() { v[1].narrow = true; }
   TunedGemm(const TunedGemm&) = delete;
   TunedGemm& operator=(const TunedGemm&) = delete;
   ~TunedGemm() { drop_events(); }
-  void reset() {           // empty both shapes, keep the choice pointer
+  void reset() {           // empty both shapes, keep the choice and follow pointers
     drop_events();
     v[0] = GemmOp();
     v[1] = GemmOp();
     v[1].narrow = true;
     calls = 0;
   }
-  void set_act(const int* a) { v[0].act = v[1].act = a; }
+  void set_act(const int* a, int mask = ~0, int excl = 0) {
+    v[0].act = v[1].act = a;
+    v[0].act_mask = v[1].act_mask = mask;
+    v[0].act_excl = v[1].act_excl = excl;
+  }
+  void set_f32() { v[0].f32 = v[1].f32 = true; }
   void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
            int K, const int* flag = nullptr, const int* spair = nullptr, int scols = 0) {
     for (auto& g : v) g.add(A, lda, B, ldb, C, ldc, M, N, K, flag, spair, scols);
   }
   void finalize(hipStream_t st) {
     v[0].finalize(st);
-    if (choice) v[1].finalize(st);
+    if (choice || follow) v[1].finalize(st);
   }
   void run(double alpha, double beta, hipStream_t st);
 
@@ -140,6 +155,17 @@ class GemvOp {
   void run(double alpha, double beta, int nrhs, hipStream_t st) const;
   bool empty() const { return h.empty(); }
 };
+
+// FP32 copies of dense blocks: dst (ld ldd) = src (ld lds), rows x cols.
+struct CvtDesc {
+  const double* src;
+  int64_t lds;
+  int rows, cols;
+  float* dst;
+  int64_t ldd;
+  int wg_start;
+};
+void convert_blocks_f32(const std::vector<CvtDesc>& blocks, hipStream_t st);
 
 struct LdltDesc {
   double* A;

@@ -96,10 +96,17 @@ void launch_pcg_update_x_r(int n, int nrhs, const double* rz, const double* pq, 
                            double* x, double* r, const double* p, const double* q, double* alpha_hist,
                            int it, int maxit, hipStream_t st);
 void launch_pcg_update_p(int n, int nrhs, const double* rz_new, double* rz, const int* active,
-                         double* p, const double* z, double* beta_hist, int it, int maxit,
-                         hipStream_t st);
+                         int* restart, double* p, const double* z, double* beta_hist, int it,
+                         int maxit, hipStream_t st);
 void launch_lanczos_cond(int nrhs, const int* nalpha, const double* alpha, const double* beta,
                          int maxit, double* out, hipStream_t st);
+void launch_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* repl, int* stall,
+                           double* tprev, int* cnt, hipStream_t st);
+void launch_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2, const int* act,
+                      int* nal, int* meets, int* cnt, int it, hipStream_t st);
+void launch_pcg_true(int nrhs, const double* tt, const double* ff, double rtol2, int* act,
+                     const int* meets, int* repl, int* stall, double* tprev, int* cnt,
+                     hipStream_t st);
 void launch_fill(double* p, size_t n, double v, hipStream_t st);
 void launch_move(int n, const int64_t* sidx, const double* src, int64_t lds, const int64_t* didx,
                  double* dst, int64_t ldd, int nrhs, hipStream_t st);

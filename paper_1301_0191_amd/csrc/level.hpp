@@ -57,6 +57,7 @@ struct Level {
   DBuf<double> fc;
   double omega = 0.0;
   int lobpcg_its = 0, n_unconv = 0, n_added = 0;
+  int lobpcg_its32 = 0;   // iterations in which some pair ran FP32 products
 };
 
 struct Top {

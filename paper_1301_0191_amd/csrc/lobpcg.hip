@@ -317,17 +317,26 @@ void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V,
   AMB_LAUNCH_CHECK();
 }
 
-// R = AX - BX diag(lam) into the W block; per-column relative residuals;
-// a pair stays active until its first nconv columns have converged.  One
-// wave per column (wave reductions, no barrier inside a column).
+// R = AX - BX diag(lam) into the W block; per-column relative residuals.
+// active[p] is the pair's phase: 2 = FP64 products (a pair stays active
+// until its first nconv columns have converged to tol; converged columns are
+// soft-locked), 1 = FP32 products (no column converges or locks; the pair
+// moves to phase 2 once the largest residual of its first nconv columns is
+// <= tol32, or has not halved over the last three iterations: the FP32
+// products stall there).  hist: 4 doubles per pair (the last three of those
+// largest residuals, newest first, and their count).  One wave per column
+// (wave reductions, no barrier inside a column).
 constexpr int RES_THREADS = 1024;
 
 __global__ __launch_bounds__(RES_THREADS) void k_residual(const PairDev* P, double* V,
                                                           const double* AV, const double* BV,
                                                           const double* lam, int m, int nconv,
-                                                          double tol, int* active, double* resn) {
+                                                          double tol, double tol32, int* active,
+                                                          double* resn, double* hist) {
   __shared__ int n_bad;
-  if (!active[blockIdx.x]) return;
+  __shared__ double relc[32];
+  const int mode = active[blockIdx.x];
+  if (!mode) return;
   const PairDev p = P[blockIdx.x];
   const int n = p.nGs + p.nGt;
   const double* l = lam + (size_t)blockIdx.x * m;
@@ -360,21 +369,36 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const PairDev* P, doub
     const double rel = den > 0.0 ? sqrt(rr) / den : 0.0;
     if (lane == 0) {
       resn[(size_t)blockIdx.x * m + c] = rel;
-      if (c < nconv && !(rel <= tol)) atomicAdd(&n_bad, 1);
+      if (c < 32) relc[c] = rel;
+      if (mode == 2 && c < nconv && !(rel <= tol)) atomicAdd(&n_bad, 1);
     }
     // soft locking: a converged column contributes no search direction
-    if (rel <= tol)
+    if (mode == 2 && rel <= tol)
       for (int i = lane; i < n; i += 64) w[i] = 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0 && n_bad == 0) active[blockIdx.x] = 0;
+  if (threadIdx.x != 0) return;
+  if (mode == 2) {
+    if (n_bad == 0) active[blockIdx.x] = 0;
+    return;
+  }
+  double r = 0.0;
+  for (int c = 0; c < min(nconv, 32); ++c) r = fmax(r, relc[c]);
+  double* h = hist + 4 * (size_t)blockIdx.x;
+  const bool stalled = h[3] >= 3.0 && r > 0.5 * h[2];
+  if (r <= tol32 || stalled || !(r == r)) active[blockIdx.x] = 2;
+  h[2] = h[1];
+  h[1] = h[0];
+  h[0] = r;
+  h[3] += 1.0;
 }
 
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,
-                 const double* lam, int m, int nconv, double tol, int* active, double* resn,
-                 hipStream_t st) {
+                 const double* lam, int m, int nconv, double tol, double tol32, int* active,
+                 double* resn, double* hist, hipStream_t st) {
   if (np == 0) return;
-  k_residual<<<np, RES_THREADS, 0, st>>>(P, V, AV, BV, lam, m, nconv, tol, active, resn);
+  k_residual<<<np, RES_THREADS, 0, st>>>(P, V, AV, BV, lam, m, nconv, tol, tol32, active, resn,
+                                         hist);
   AMB_LAUNCH_CHECK();
 }
 
@@ -402,10 +426,11 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // replaced by 63 - index; a positive double whose order is that of the
 // values, ties broken by index): every row's key sits in an LDS array, double
 // buffered across steps, and every wave takes the maximum with DPP.
-constexpr int RR_THREADS = 1024;   // 16 waves (one per wanted eigenpair, m <= 16)
-constexpr int RR_COLS = 3;         // columns per wave when all 16 waves share nb <= 48 columns
+constexpr int RR_THREADS = 1024;   // 16 waves
+constexpr int RR_MAXNB = 64;       // order of the reduced problem (3m, m <= 21)
+constexpr int RR_COLS = 4;         // columns per wave when all 16 waves share nb <= 64 columns
 constexpr int RR_EW = 8;           // waves that eliminate (the others only follow the pivots)
-constexpr int RR_ECOLS = 6;        // columns per eliminating wave
+constexpr int RR_ECOLS = 8;        // columns per eliminating wave
 
 __device__ inline double rr_key(double v, int i) {
   if (!(v > 0.0)) return 0.0;
@@ -621,8 +646,26 @@ void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb,
            double* Cf, double* lam, const int* active, hipStream_t st) {
   (void)P;
   if (np == 0) return;
-  if (nb > 48 || nb < 1) throw Error(1, "Rayleigh-Ritz block larger than 48");
-  k_rr<<<np, RR_THREADS, rr_smem(nb), st>>>(GA, GB, nb, m, Cf, lam, active);
+  if (nb > RR_MAXNB || nb < 1) throw Error(1, "Rayleigh-Ritz block larger than 64");
+  const size_t sm = rr_smem(nb);
+  if (sm > 64 * 1024) {
+    // more than the default LDS of a workgroup (up to 96 KB for nb = 63):
+    // gfx950 has 160 KB per CU; ask for it once and fail cleanly if refused
+    static size_t granted = 0;
+    if (sm > granted) {
+      int dev = 0, lim = 0;
+      AMB_HIP(hipGetDevice(&dev));
+      AMB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      if (size_t(lim) < sm)
+        throw Error(1, "Rayleigh-Ritz of order " + std::to_string(nb) + " needs " +
+                           std::to_string(sm) + " bytes of LDS; the device allows " +
+                           std::to_string(lim));
+      AMB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rr),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(sm)));
+      granted = sm;
+    }
+  }
+  k_rr<<<np, RR_THREADS, sm, st>>>(GA, GB, nb, m, Cf, lam, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -889,7 +932,10 @@ __global__ __launch_bounds__(256) void k_select(const PairDev* P, const double* 
   const double* l = lam + (size_t)blockIdx.x * m;
   const int cap = min(nev_max, m);
   int k = 0;
-  if (fixed > 0) k = cap;
+  // with a fixed count, eigenvalues that are zero up to rounding (their
+  // c = A w vanishes) are never taken
+  const double zero = 1e-9 * fmax(1.0, l[0]);
+  if (fixed > 0) while (k < min(cap, fixed) && l[k] > zero) ++k;
   else while (k < cap && l[k] > tau) ++k;
   if (threadIdx.x == 0) lam_next[blockIdx.x] = (k < m) ? l[k] : 0.0;
   const int nf = p.nface;

@@ -61,9 +61,10 @@ void lp_coarse(const PairDev* P, int np, const double* Y, int m, const double* K
                hipStream_t st);
 void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V, const int* active,
                     hipStream_t st);
+// active[p]: 0 converged, 1 FP32 products, 2 FP64 products (see lobpcg.hip)
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,
-                 const double* lam, int m, int nconv, double tol, int* active, double* resn,
-                 hipStream_t st);
+                 const double* lam, int m, int nconv, double tol, double tol32, int* active,
+                 double* resn, double* hist, hipStream_t st);
 void lp_rr(const PairDev* P, int np, const double* GA, const double* GB, int nb, int m,
            double* Cf, double* lam, const int* active, hipStream_t st);
 void lp_commit(const PairDev* P, int np, double* V, double* AV, double* BV, const double* T,

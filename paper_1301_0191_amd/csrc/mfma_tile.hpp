@@ -169,3 +169,116 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
 }
 
 }  // namespace ambddc
+
+namespace ambddc {
+
+// ---------------------------------------------------------------------------
+// FP32 variant: C = alpha * A * B + beta * C with A FP32 (column-major, lda),
+// B FP64 rounded to FP32 as it is staged, products and sums on
+// v_mfma_f32_16x16x4f32 (FP32 accumulation), C FP64.  Same tiling as the
+// FP64 tile: 4 waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16), K staged
+// through LDS in chunks of KC32, double buffered, one barrier per chunk.
+// MFMA 16x16x4 f32 operands: A lane l holds A[l % 16][l / 16], B lane l
+// holds B[l / 16][l % 16]; D lane l, element r holds D[4 (l / 16) + r][l % 16].
+// ---------------------------------------------------------------------------
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+constexpr int KC32 = 32;
+
+template <int WM, int WN>
+struct TileSmem32 {
+  float As[2][KC32][32 * WM + 4];
+  float Bs[2][KC32][32 * WN + 4];
+};
+
+template <int WM, int WN>
+__device__ __forceinline__ void mfma_tile_f32(const float* __restrict__ A, int lda,
+                                              const double* __restrict__ B, int ldb, double* C,
+                                              int ldc, int M, int N, int K, int m0, int n0,
+                                              double alpha, double beta, TileSmem32<WM, WN>& sm) {
+  constexpr int TM = 32 * WM, TN = 32 * WN, KC = KC32;
+  constexpr int NA = KC * TM / 256, NB = KC * TN / 256;   // staged values per thread
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  flt4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+  float ra[NA];
+  double rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int idx = tid + u * 256;
+      const int m = idx % TM, k = idx / TM;
+      const int gm = m0 + m, gk = k0 + k;
+      ra[u] = (gm < M && gk < K) ? gld(A + gm + (size_t)gk * lda) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int idx = tid + u * 256;
+      const int k = idx % KC, n = idx / KC;
+      const int gn = n0 + n, gk = k0 + k;
+      rb[u] = (gn < N && gk < K) ? gld(B + gk + (size_t)gn * ldb) : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int idx = tid + u * 256;
+      sm.As[buf][idx / TM][idx % TM] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int idx = tid + u * 256;
+      sm.Bs[buf][idx % KC][idx / KC] = static_cast<float>(rb[u]);
+    }
+  };
+  if (K > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    const bool more = k0 + KC < K;
+    if (more) gload(k0 + KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sm.As[buf][kr][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sm.Bs[buf][kr][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          double* c = C + gm + (size_t)gn * ldc;
+          double v = alpha * static_cast<double>(acc[i][j][r]);
+          if (beta != 0.0) v += beta * (*c);
+          *c = v;
+        }
+      }
+}
+
+}  // namespace ambddc

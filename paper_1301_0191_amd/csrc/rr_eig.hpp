@@ -92,7 +92,8 @@ __device__ __forceinline__ double rcp_nr(double q) {
 
 // A: n x n symmetric (ld lda), destroyed.  Y: n x mm eigenvectors (ld ldy),
 // lam: mm eigenvalues, descending, mm = min(m, n).  ws: EIG_WS doubles.
-// n <= EIG_MAXN, m <= NT / 64.
+// n <= EIG_MAXN, m <= 4 NT / 64 (the eigenvectors are computed by the NT / 64
+// waves in passes of NT / 64).
 template <int NT>
 __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, int ldy,
                                    double* lam, double* ws) {
@@ -239,18 +240,23 @@ __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, 
   // 3. inverse iteration, one wave per wanted eigenvalue, all at once
   const double ctol = EIG_CTOL * tnorm;
   const double tiny = EPS * fmax(tnorm, 1e-300);
+  constexpr int NW = NT / 64;
+  // Pass q computes the eigenvectors j = q NW + wave.  Members of a cluster
+  // that fall in earlier passes are final by then, so the Gram-Schmidt
+  // rounds of a pass also remove their components.
+  for (int j0 = 0; j0 < mm; j0 += NW) {
   // rank of this wave's member in its cluster and the cluster's first member
   int rank = 0, cs = 0, rounds = 1;
+  const int j = j0 + wave;
   {
     int rk = 0, start = 0;
-    for (int i = 0; i < mm; ++i) {
+    for (int i = 0; i < min(mm, j0 + NW); ++i) {
       if (i > 0 && lam[i - 1] - lam[i] <= ctol) rk += 1;
       else { rk = 0; start = i; }
-      rounds = max(rounds, rk + 1);
-      if (i == wave) { rank = rk; cs = start; }
+      if (i >= j0) rounds = max(rounds, rk + 1);
+      if (i == j) { rank = rk; cs = start; }
     }
   }
-  const int j = wave;
   const bool member = j < mm;
   // LU of T - lam_j I with partial pivoting: a chain that every lane runs
   // alike; lane i keeps row i (reciprocal pivot, the two entries right of
@@ -338,10 +344,11 @@ __device__ inline void sym_top_eig(double* A, int lda, int n, int m, double* Y, 
     }
   }
   __syncthreads();
+  }
 
   // 4. back-transformation by the reflectors
-  if (wave < mm) {
-    double* y = Y + (size_t)wave * ldy;
+  for (int jv = wave; jv < mm; jv += NW) {
+    double* y = Y + (size_t)jv * ldy;
     for (int k = n - 3; k >= 0; --k) {
       const double tk = tau[k];
       if (tk == 0.0) continue;

@@ -6,6 +6,7 @@
 #include <functional>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -107,16 +108,21 @@ struct ambddc_ctx {
   ambddc_stats stats{};
   KTimer kt;   // optional per-class kernel timing
   std::map<std::string, int> tune;   // tile-shape choices of tuned products (-1: measuring)
-  std::vector<double> last_res;   // true relative residuals of the last solve
   DBuf<double> coeff_buf, mis_part, mis_out;   // log10 set-up and misfit workspace
-  // PCG workspace
+  // PCG workspace of ambddc_solve (carved into a PcgWork)
   int pcg_cap = 0, pcg_maxit = 0;
-  DBuf<double> px, pr, pz, pp, pq, pdot, ppart, pah, pbh, plz;
-  DBuf<int> pact, pnal, pmask;
+  DBuf<double> pwd;
+  DBuf<int> pwi;
   int pcg_repl = 0;   // residual replacements in the last solve
+  double last_res[16] = {};   // true relative residuals of the last solve
+  int n_last_res = 0;
 };
 
 namespace {
+
+// Residual at which a pair's LOBPCG leaves FP32 products for FP64 ones
+// (precision 2), unless it stalls earlier.
+constexpr double LOBPCG_TOL32 = 1e-5;
 
 // Most adaptive constraints one face can receive: nev_max under Alg. 2, or
 // the fixed count per face.
@@ -255,7 +261,7 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
     L.g3.add(B + nl + nG + int64_t(nl) * NN, NN, L.nc[s], nG, L.w_ucl.p + L.cloff[s],
              int(std::max<int64_t>(L.cl_tot, 1)), L.w_y2.p + L.y2off[s], int(L.y2_tot));
   }
-  if (c.opt.precision == 1) {
+  if (c.opt.precision >= 1) {
     // Alg. 1's dense operators are only read by the preconditioner: keep them
     // in FP32 (the FP64 blocks stay for the Schur complements and set-up)
     L.g1.pack_a_f32(L.g1_32, st);
@@ -478,7 +484,13 @@ struct PairWork {
   PairIdx idx;
   DBuf<double> V, AV, BV, T, GA, GB, Cf, lam, resn, U, Y, Zc, Kp, rb, lnext, Cxw, Nb, Aug;
   DBuf<int> active, kout, nnull, slot_pair;
+  DBuf<double> hist;        // per pair: residual history of the FP32 phase
   TunedGemm gS, gM1, gM2;   // grouped per-subdomain products, tile shape tuned
+  // the same products on FP32 copies of S^s and the Neumann inverse with FP32
+  // accumulation, for pairs in the FP32 phase (precision 2)
+  TunedGemm gS32, gM1_32, gM2_32;
+  bool lo = false;          // some pairs start in the FP32 phase
+  DBuf<float> S32, T32;
   GemmOp gram[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;   // gram: V^T AV and V^T BV in one launch
   KTimer* kt = nullptr;
   std::vector<int> act;                          // host copy of the active flags
@@ -628,6 +640,8 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   W.rb.alloc(std::max<int64_t>(rboff, 1));
   W.lnext.alloc(W.np);
   W.active.alloc(W.np);
+  W.hist.alloc(size_t(4) * W.np);
+  W.hist.zero(st);
   W.kout.alloc(W.np);
   W.nnull.alloc(W.np);
   L.fc.alloc(std::max<int64_t>(fcoff, 1));
@@ -647,12 +661,25 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   // tile shapes: measured on the first set-up of the handle, then reused
   const std::string lk = "L" + std::to_string(li) + ".";
   W.gS.reset(); W.gM1.reset(); W.gM2.reset();
-  W.gS.choice = &c.tune.emplace(lk + "S", -1).first->second;
-  W.gM1.choice = &c.tune.emplace(lk + "Z", -1).first->second;
-  W.gM2.choice = &c.tune.emplace(lk + "Psi", -1).first->second;
-  W.gS.set_act(W.active.p);
-  W.gM1.set_act(W.active.p);
-  W.gM2.set_act(W.active.p);
+  if (W.lo) {
+    // the FP64 products have no work until pairs leave the FP32 phase: they
+    // take the tile shapes the FP32 products measure
+    W.gS.follow = &c.tune.emplace(lk + "S32", -1).first->second;
+    W.gM1.follow = &c.tune.emplace(lk + "Z32", -1).first->second;
+    W.gM2.follow = &c.tune.emplace(lk + "Psi32", -1).first->second;
+  } else {
+    W.gS.choice = &c.tune.emplace(lk + "S", -1).first->second;
+    W.gM1.choice = &c.tune.emplace(lk + "Z", -1).first->second;
+    W.gM2.choice = &c.tune.emplace(lk + "Psi", -1).first->second;
+  }
+  // phases (active[p]): 1 = FP32 products, 2 = FP64 products.  An FP64
+  // product that overwrites (beta 0) runs after the FP32 one on every tile
+  // with an FP64-phase slot; the accumulating Psi product runs each tile once
+  // (in FP32 if any of its slots is in the FP32 phase: it is part of the
+  // preconditioner, which only steers the search).
+  W.gS.set_act(W.active.p, 2);
+  W.gM1.set_act(W.active.p, 2);
+  W.gM2.set_act(W.active.p, 2, W.lo ? 1 : 0);
   for (int s = 0; s < L.nsub; ++s) {
     const int cols = P.sub_npairs[s] * 2 * m;
     if (cols == 0) continue;
@@ -669,6 +696,55 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   W.gS.finalize(st);
   W.gM1.finalize(st);
   W.gM2.finalize(st);
+  if (W.lo) {
+    // FP32 copies: S^s (nG x nG) and the Neumann inverse block (nl x nl)
+    std::vector<int64_t> so(L.nsub + 1, 0), to(L.nsub + 1, 0);
+    for (int s = 0; s < L.nsub; ++s) {
+      const bool used = P.sub_npairs[s] > 0;
+      so[s + 1] = so[s] + (used ? int64_t(L.nG[s]) * L.nG[s] : 0);
+      to[s + 1] = to[s] + (used ? int64_t(L.nl[s]) * L.nl[s] : 0);
+    }
+    W.S32.alloc(size_t(std::max<int64_t>(so[L.nsub], 1)));
+    W.T32.alloc(size_t(std::max<int64_t>(to[L.nsub], 1)));
+    std::vector<CvtDesc> cv;
+    for (int s = 0; s < L.nsub; ++s) {
+      if (P.sub_npairs[s] == 0) continue;
+      const int N = L.augN[s], nI = L.nI[s], nG = L.nG[s], nl = L.nl[s], NN = L.naugN[s];
+      cv.push_back(CvtDesc{L.aug.p + L.aug_off[s] + nI + int64_t(nI) * N, N, nG, nG,
+                           W.S32.p + so[s], nG, 0});
+      cv.push_back(CvtDesc{L.naug.p + L.naug_off[s] + nl + int64_t(nl) * NN, NN, nl, nl,
+                           W.T32.p + to[s], nl, 0});
+    }
+    convert_blocks_f32(cv, st);
+    W.gS32.reset(); W.gM1_32.reset(); W.gM2_32.reset();
+    W.gS32.choice = &c.tune.emplace(lk + "S32", -1).first->second;
+    W.gM1_32.choice = &c.tune.emplace(lk + "Z32", -1).first->second;
+    W.gM2_32.choice = &c.tune.emplace(lk + "Psi32", -1).first->second;
+    for (TunedGemm* g : {&W.gS32, &W.gM1_32, &W.gM2_32}) {
+      g->set_f32();
+      g->set_act(W.active.p, 1);
+    }
+    for (int s = 0; s < L.nsub; ++s) {
+      const int cols = P.sub_npairs[s] * 2 * m;
+      if (cols == 0) continue;
+      const int nG = L.nG[s], nl = L.nl[s];
+      const float* S = W.S32.p + so[s];
+      const float* Tn = W.T32.p + to[s];
+      const int* sp = W.slot_pair.p + slot_off[s];
+      // the FP32 GEMM reads A as plain column-major: the pointers carry floats
+      W.gS32.add(reinterpret_cast<const double*>(S), nG, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl,
+                 nG, cols, nG, nullptr, sp, 2 * m);
+      W.gM1_32.add(reinterpret_cast<const double*>(Tn), nl, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s],
+                   nl, nl, cols, nG, nullptr, sp, 2 * m);
+      if (L.nc[s] > 0)
+        W.gM2_32.add(reinterpret_cast<const double*>(Tn + int64_t(nG) * nl), nl,
+                     W.Zc.p + Zoff[s], L.nc[s], W.Y.p + Yoff[s], nl, nG, cols, L.nc[s], nullptr,
+                     sp, 2 * m);
+    }
+    W.gS32.finalize(st);
+    W.gM1_32.finalize(st);
+    W.gM2_32.finalize(st);
+  }
   // W <- W - X (BX^T W): B-orthogonalise the search directions against X
   W.orth_c = GemmOp();
   W.orth_u = GemmOp();
@@ -794,9 +870,11 @@ void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
     double fl, by;
     apply_work(L, W, fl, by);
     W.kt->begin("pair_apply", st);
+    if (W.lo) W.gS32.run(1.0, 0.0, st);
     W.gS.run(1.0, 0.0, st);
     W.kt->end("pair_apply", st, fl, by);
   } else {
+    if (W.lo) W.gS32.run(1.0, 0.0, st);
     W.gS.run(1.0, 0.0, st);
   }
   lp_from_slab_ab(W.dp.p, W.np, W.Y.p, W.m, col, W.AV.p, W.BV.p, L.diagG.p, W.idx.sh_s.p,
@@ -852,9 +930,13 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   PairWork W;
   const int nev = nsel_max(c.opt);
   W.m = std::max(c.opt.lobpcg_block, nev + 1);
-  if (W.m > 16) throw Error(AMBDDC_E_INVALID_ARG, "lobpcg_block larger than 16 is not supported");
+  if (W.m > 21)
+    throw Error(AMBDDC_E_INVALID_ARG,
+                "LOBPCG block (max(lobpcg_block, constraints per face + 1)) above 21 is not "
+                "supported");
   L.m = W.m;
   W.kt = &c.kt;
+  W.lo = c.opt.precision == 2;
   build_pair_work(c, L, li, W);
   if (W.np == 0) {
     L.omega = 0.0;
@@ -866,9 +948,10 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
   pair_pinv(c, L, W, li);
   const int m = W.m;
   const int nconv = std::min(nev + 1, m);
-  std::vector<int> ones(W.np, 1);
+  std::vector<int> ones(W.np, W.lo ? 1 : 2);
   W.active.upload(ones, st);
   W.act = ones;
+  L.lobpcg_its32 = 0;
   // start block, projected; first Rayleigh-Ritz on X alone
   lp_random(W.dp.p, W.np, W.V.p, m, c.opt.seed + uint64_t(li) * 7919u, st);
   lp_project(W.dp.p, W.np, W.V.p, m, 0, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, nullptr, true, st);
@@ -884,7 +967,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
       apply_ab(L, W, 2, st);
     }
     lp_residual(W.dp.p, W.np, W.V.p, W.AV.p, W.BV.p, W.lam.p, m, nconv, c.opt.lobpcg_tol,
-                W.active.p, W.resn.p, st);
+                LOBPCG_TOL32, W.active.p, W.resn.p, W.hist.p, st);
     // The new flags travel to the host while the stream already runs the
     // next block: every kernel and product below skips converged pairs on
     // the device, so when no pair is left the block is launches without work.
@@ -892,9 +975,11 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
     // W = M R  (eq. bddc_pair: Z^st R + Psi (Psi^T S Psi)^+ Psi^T R, then Pi and deflation)
     lp_to_slab(W.dp.p, W.np, W.V.p, m, 1, false, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
                W.active.p, st);
+    if (W.lo) W.gM1_32.run(1.0, 0.0, st);
     W.gM1.run(1.0, 0.0, st);
     lp_coarse(W.dp.p, W.np, W.Y.p, m, W.Kp.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Zc.p, W.ncp_max,
               W.active.p, st);
+    if (W.lo) W.gM2_32.run(1.0, 1.0, st);
     W.gM2.run(1.0, 1.0, st);
     lp_from_slab_w(W.dp.p, W.np, W.Y.p, m, W.V.p, W.active.p, st);
     lp_project(W.dp.p, W.np, W.V.p, m, 1, L.C.p, DRows{W.idx.dptr.p, W.idx.didx.p, W.idx.dcpos.p}, W.rb.p, W.active.p,
@@ -909,8 +994,12 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
       apply_work(L, W, fl1, by1);
       W.kt->amend("pair_apply", fl1 - fl0, by1 - by0);
     }
-    int nact = 0;
-    for (int x : W.act) nact += x != 0;
+    int nact = 0, n32 = 0;
+    for (int x : W.act) {
+      nact += x != 0;
+      n32 += x == 1;
+    }
+    if (n32 > 0) ++L.lobpcg_its32;
     if (nact == 0) break;
     rayleigh_ritz(L, W, it == 1 ? 1 : 2, true, st);
   }
@@ -1152,6 +1241,7 @@ void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
     c.stats.n_coarse[i] = L.ncoarse;
     c.stats.n_adaptive[i] = L.n_added;
     c.stats.lobpcg_iters[i] = L.lobpcg_its;
+    c.stats.lobpcg_iters_fp32[i] = L.lobpcg_its32;
     c.stats.n_unconverged[i] = L.n_unconv;
     c.stats.omega_tilde[i] = L.omega;
   }
@@ -1164,48 +1254,87 @@ void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
 // PCG
 // ---------------------------------------------------------------------------
 
-int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, double* x,
-             int* its, double* cond) {
+// Device memory of one PCG solve (all pointers on the device): the columns
+// r, z, p, q (n x nrhs each), the dot products, reduction partials, the
+// coefficient histories of the Lanczos estimate and the column flags.
+struct PcgWork {
+  double *r, *z, *p, *q;
+  double* dot;     // 8 nrhs: rz, beta, pq, rr, rzn, ff
+  double* part;    // 256 nrhs reduction partials
+  double *ah, *bh; // ldh x nrhs coefficient histories
+  double* lz;      // 3 nrhs + 2 ldh nrhs: condition estimates and Sturm workspace
+  double* tprev;   // nrhs: true residual at the column's last check
+  int *act, *nal, *meets, *repl, *stall, *cnt;   // nrhs each; cnt: 4
+  int ldh;
+};
+
+// Doubles and ints one PcgWork needs.
+void pcg_work_size(int64_t n, int nrhs, int ldh, int64_t& nd, int64_t& ni) {
+  nd = 4 * n * nrhs + 8 * int64_t(nrhs) + 256 * int64_t(nrhs) + 2 * int64_t(ldh) * nrhs +
+       3 * int64_t(nrhs) + 2 * int64_t(ldh) * nrhs + int64_t(nrhs);
+  ni = 5 * int64_t(nrhs) + 4;
+}
+
+// Carve a PcgWork out of nd doubles at d and ni ints at ip.
+PcgWork pcg_work_carve(double* d, int* ip, int64_t n, int nrhs, int ldh) {
+  PcgWork w{};
+  const size_t nn = size_t(n) * nrhs;
+  w.r = d; d += nn;
+  w.z = d; d += nn;
+  w.p = d; d += nn;
+  w.q = d; d += nn;
+  w.dot = d; d += 8 * nrhs;
+  w.part = d; d += 256 * nrhs;
+  w.ah = d; d += size_t(ldh) * nrhs;
+  w.bh = d; d += size_t(ldh) * nrhs;
+  w.lz = d; d += 3 * size_t(nrhs) + 2 * size_t(ldh) * nrhs;
+  w.tprev = d;
+  w.act = ip; ip += nrhs;
+  w.nal = ip; ip += nrhs;
+  w.meets = ip; ip += nrhs;
+  w.repl = ip; ip += nrhs;
+  w.stall = ip; ip += nrhs;
+  w.cnt = ip;
+  w.ldh = ldh;
+  return w;
+}
+
+// PCG (x0 = 0) with Alg. 1 as preconditioner, columns in lockstep, flags on
+// the device; the host reads four counters per iteration.  A column whose
+// recursive residual meets rtol is checked against its recomputed true
+// residual f - K x: it stops if that meets rtol too; otherwise the true
+// residual replaces the recursive one and the column restarts from it
+// (p = z: the old direction is not conjugate to the new residual), unless
+// the true residual fell by less than half since its previous check, when
+// the column stops as stalled at the FP64 floor of f - K x.  Allocates
+// nothing when `timed` is false (the preconditioner's workspace for nrhs
+// columns must exist).  Returns the number of columns that did not converge
+// (stalled or still active at maxit).
+int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double rtol, int maxit,
+             double* x, int* its, double* cond, bool timed) {
   hipStream_t st = c.st;
   const double t0 = now_s();
   const int n = c.L[0]->ndof;
-  ensure_workspace(c, nrhs);
-  if (c.pcg_cap < nrhs || c.pcg_maxit < maxit) {
-    c.pcg_cap = std::max(c.pcg_cap, nrhs);
-    c.pcg_maxit = std::max(c.pcg_maxit, maxit);
-    const size_t nn = size_t(n) * c.pcg_cap;
-    c.pr.alloc(nn); c.pz.alloc(nn); c.pp.alloc(nn); c.pq.alloc(nn);
-    c.pdot.alloc(8 * c.pcg_cap);
-    c.ppart.alloc(256 * c.pcg_cap);
-    c.pah.alloc(size_t(c.pcg_maxit) * c.pcg_cap);
-    c.pbh.alloc(size_t(c.pcg_maxit) * c.pcg_cap);
-    c.plz.alloc(3 * c.pcg_cap + 2 * size_t(c.pcg_maxit) * c.pcg_cap);
-    c.pact.alloc(c.pcg_cap);
-    c.pnal.alloc(c.pcg_cap);
-  }
   const size_t nn = size_t(n) * nrhs;
-  double* rz = c.pdot.p;              // rz[0:nrhs], beta scratch rz[nrhs:2nrhs]
-  double* pq = c.pdot.p + 2 * nrhs;
-  double* rr = c.pdot.p + 3 * nrhs;
-  double* rzn = c.pdot.p + 4 * nrhs;
-  double* ff = c.pdot.p + 5 * nrhs;
+  const double rtol2 = rtol * rtol;
+  double* rz = w.dot;                 // rz[0:nrhs], beta scratch rz[nrhs:2nrhs]
+  double* pq = w.dot + 2 * nrhs;
+  double* rr = w.dot + 3 * nrhs;
+  double* rzn = w.dot + 4 * nrhs;
+  double* ff = w.dot + 5 * nrhs;
+  int hc[4] = {0, 0, 0, 0};
+  auto read_cnt = [&]() {
+    AMB_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    AMB_HIP(hipStreamSynchronize(st));
+  };
   launch_fill(x, nn, 0.0, st);
-  launch_copy(c.pr.p, f, nn, st);
-  launch_dot_cols(n, nrhs, f, f, c.ppart.p, ff, st);
-  std::vector<double> hff(nrhs), hrr(nrhs);
-  AMB_HIP(hipMemcpyAsync(hff.data(), ff, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-  std::vector<int> act(nrhs, 1), nal(nrhs, 0);
-  for (int k = 0; k < nrhs; ++k) {
-    its[k] = 0;
-  }
-  c.pcg_repl = 0;
-  AMB_HIP(hipStreamSynchronize(st));
-  for (int k = 0; k < nrhs; ++k)
-    if (hff[k] == 0.0) act[k] = 0;
-  c.pact.upload(act, st);
+  launch_copy(w.r, f, nn, st);
+  launch_dot_cols(n, nrhs, f, f, w.part, ff, st);
+  launch_pcg_init_flags(nrhs, ff, w.act, w.nal, w.repl, w.stall, w.tprev, w.cnt, st);
   // algorithmic work of one preconditioner application (timing only)
   double apf = 0.0, apb = 0.0;
-  if (c.kt.any()) {
+  const bool kt = timed && c.kt.any();
+  if (kt) {
     double ent = 0.0;
     for (auto& lp : c.L) {
       const Level& Lv = *lp;
@@ -1216,89 +1345,154 @@ int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, d
     }
     const double top = double(c.top.n) * c.top.n;   // the coarsest inverse stays FP64
     apf = 2.0 * (ent + top) * nrhs;
-    apb = (c.opt.precision == 1 ? 4.0 : 8.0) * ent + 8.0 * top + 48.0 * double(n) * nrhs;
+    apb = (c.opt.precision >= 1 ? 4.0 : 8.0) * ent + 8.0 * top + 48.0 * double(n) * nrhs;
   }
   auto precondition = [&]() {
-    c.kt.begin("bddc_apply", st);
-    apply_level(c, 0, c.pr.p, n, c.pz.p, n, nrhs);
-    c.kt.end("bddc_apply", st, apf, apb);
+    if (kt) c.kt.begin("bddc_apply", st);
+    apply_level(c, 0, w.r, n, w.z, n, nrhs);
+    if (kt) c.kt.end("bddc_apply", st, apf, apb);
   };
   precondition();
-  launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rz, st);
-  launch_copy(c.pp.p, c.pz.p, nn, st);
-  int nact = 0;
-  for (int a : act) nact += a;
-  int it = 0;
-  for (it = 0; it < maxit && nact > 0; ++it) {
-    launch_spmv(c.csr, c.csr_vals.p, c.pp.p, c.pq.p, nrhs, st);
-    launch_dot_cols(n, nrhs, c.pp.p, c.pq.p, c.ppart.p, pq, st);
-    launch_pcg_update_x_r(n, nrhs, rz, pq, c.pact.p, x, c.pr.p, c.pp.p, c.pq.p, c.pah.p, it,
-                          c.pcg_maxit, st);
-    launch_dot_cols(n, nrhs, c.pr.p, c.pr.p, c.ppart.p, rr, st);
-    AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    AMB_HIP(hipStreamSynchronize(st));
-    bool changed = false, cand = false;
-    std::vector<int> meets(nrhs, 0);
-    for (int k = 0; k < nrhs; ++k) {
-      if (!act[k]) continue;
-      nal[k] = it + 1;
-      its[k] = it + 1;
-      if (hrr[k] <= rtol * rtol * hff[k]) meets[k] = cand = true;
-    }
-    if (cand) {
+  launch_dot_cols(n, nrhs, w.r, w.z, w.part, rz, st);
+  launch_copy(w.p, w.z, nn, st);
+  read_cnt();
+  int nact = hc[1];
+  int repl = 0;
+  for (int it = 0; it < maxit && nact > 0; ++it) {
+    launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, st);
+    launch_dot_cols(n, nrhs, w.p, w.q, w.part, pq, st);
+    launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, it, w.ldh, st);
+    launch_dot_cols(n, nrhs, w.r, w.r, w.part, rr, st);
+    launch_pcg_meets(nrhs, rr, ff, rtol2, w.act, w.nal, w.meets, w.cnt, it, st);
+    read_cnt();
+    if (hc[0] > 0) {
       // The recursive residual drifts from f - K x by rounding (most on
-      // ill-conditioned problems), so a column stops only when its true
-      // residual, recomputed here, meets rtol as well; otherwise the true
-      // residual replaces the recursive one and the iteration goes on.
-      launch_spmv(c.csr, c.csr_vals.p, x, c.pq.p, nrhs, st);
-      launch_sub(nn, f, c.pq.p, c.pq.p, st);
-      launch_dot_cols(n, nrhs, c.pq.p, c.pq.p, c.ppart.p, rr, st);
-      AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-      AMB_HIP(hipStreamSynchronize(st));
-      std::vector<int> repl(nrhs, 0);
-      bool any_repl = false;
-      for (int k = 0; k < nrhs; ++k) {
-        if (!meets[k]) continue;
-        if (hrr[k] <= rtol * rtol * hff[k]) {
-          act[k] = 0;
-          changed = true;
-          --nact;
-        } else {
-          repl[k] = 1;
-          any_repl = true;
-          ++c.pcg_repl;
-        }
-      }
-      if (any_repl) {
-        c.pmask.upload(repl, st);
-        launch_copy_cols(n, nrhs, c.pq.p, c.pr.p, c.pmask.p, st);
-      }
+      // ill-conditioned problems): recompute the true residual (q is free
+      // here) and stop only the columns it confirms.
+      launch_spmv(c.csr, c.csr_vals.p, x, w.q, nrhs, st);
+      launch_sub(nn, f, w.q, w.q, st);
+      launch_dot_cols(n, nrhs, w.q, w.q, w.part, rr, st);
+      launch_pcg_true(nrhs, rr, ff, rtol2, w.act, w.meets, w.repl, w.stall, w.tprev, w.cnt, st);
+      launch_copy_cols(n, nrhs, w.q, w.r, w.repl, st);
+      read_cnt();
+      nact = hc[1];
+      repl += hc[2];
+      if (nact == 0) break;
     }
-    if (nact == 0) break;
-    if (changed) c.pact.upload(act, st);
     precondition();
-    launch_dot_cols(n, nrhs, c.pr.p, c.pz.p, c.ppart.p, rzn, st);
-    launch_pcg_update_p(n, nrhs, rzn, rz, c.pact.p, c.pp.p, c.pz.p, c.pbh.p, it, c.pcg_maxit, st);
+    launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, st);
+    launch_pcg_update_p(n, nrhs, rzn, rz, w.act, w.repl, w.p, w.z, w.bh, it, w.ldh, st);
   }
-  // true residual of every column, ||f - K x|| / ||f|| (the recursion above
-  // only tracks the updated residual)
-  launch_spmv(c.csr, c.csr_vals.p, x, c.pq.p, nrhs, st);
-  launch_sub(size_t(n) * nrhs, f, c.pq.p, c.pq.p, st);
-  launch_dot_cols(n, nrhs, c.pq.p, c.pq.p, c.ppart.p, rr, st);
-  AMB_HIP(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-  AMB_HIP(hipStreamSynchronize(st));
-  c.last_res.assign(nrhs, 0.0);
-  for (int k = 0; k < nrhs; ++k)
-    c.last_res[k] = hff[k] > 0.0 ? std::sqrt(hrr[k] / hff[k]) : 0.0;
+  // iterations per column and the true residuals ||f - K x|| / ||f||
+  int hnal[16];
+  double htt[16], hff[16];
+  launch_spmv(c.csr, c.csr_vals.p, x, w.q, nrhs, st);
+  launch_sub(nn, f, w.q, w.q, st);
+  launch_dot_cols(n, nrhs, w.q, w.q, w.part, rr, st);
+  AMB_HIP(hipMemcpyAsync(hnal, w.nal, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+  AMB_HIP(hipMemcpyAsync(htt, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  AMB_HIP(hipMemcpyAsync(hff, ff, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
   if (cond) {
-    c.pnal.upload(nal, st);
-    launch_lanczos_cond(nrhs, c.pnal.p, c.pah.p, c.pbh.p, c.pcg_maxit, c.plz.p, st);
-    AMB_HIP(hipMemcpyAsync(cond, c.plz.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    launch_lanczos_cond(nrhs, w.nal, w.ah, w.bh, w.ldh, w.lz, st);
+    AMB_HIP(hipMemcpyAsync(cond, w.lz, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
   }
   AMB_HIP(hipStreamSynchronize(st));
+  c.n_last_res = nrhs;
+  for (int k = 0; k < nrhs; ++k) {
+    its[k] = hnal[k];
+    c.last_res[k] = hff[k] > 0.0 ? std::sqrt(htt[k] / hff[k]) : 0.0;
+  }
+  c.pcg_repl = repl;
   c.stats.t_phase[7] = now_s() - t0;
-  c.stats.pcg_replacements = c.pcg_repl;
-  return nact;
+  c.stats.pcg_replacements = repl;
+  c.stats.pcg_stalled = hc[3];
+  return nact + hc[3];
+}
+
+int pcg_impl(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, double* x,
+             int* its, double* cond) {
+  ensure_workspace(c, nrhs);
+  const int n = c.L[0]->ndof;
+  if (c.pcg_cap < nrhs || c.pcg_maxit < maxit) {
+    c.pcg_cap = std::max(c.pcg_cap, nrhs);
+    c.pcg_maxit = std::max(c.pcg_maxit, maxit);
+    int64_t nd, ni;
+    pcg_work_size(n, c.pcg_cap, c.pcg_maxit, nd, ni);
+    c.pwd.alloc(size_t(nd));
+    c.pwi.alloc(size_t(ni));
+  }
+  const PcgWork w = pcg_work_carve(c.pwd.p, c.pwi.p, n, nrhs, c.pcg_maxit);
+  return pcg_core(c, w, f, nrhs, rtol, maxit, x, its, cond, true);
+}
+
+// ---------------------------------------------------------------------------
+// PCG scratch of ambddc_solve_noalloc: one fixed device array per GPU
+// ---------------------------------------------------------------------------
+
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_BYTES / sizeof(double)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};   // device address of `scratch` per device id
+
+// The device address of this device's copy of `scratch`, looked up once per
+// device (the array's name in host code is only a stand-in for it).
+void* scratch_address() {
+  int dev = 0;
+  AMB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(AMBDDC_E_DEVICE, "device id out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(AMBDDC_E_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
+int pcg_noalloc(ambddc_ctx& c, const double* f, int nrhs, double rtol, int maxit, double* x,
+                int* its, double* cond) {
+  if (nrhs > 3)
+    throw Error(AMBDDC_E_INVALID_ARG, "ambddc_solve_noalloc takes 1 to 3 right-hand sides");
+  for (auto& lp : c.L)
+    if (lp->nrhs_cap < nrhs)
+      throw Error(AMBDDC_E_INVALID_ARG,
+                  "the preconditioner's workspace holds " + std::to_string(lp->nrhs_cap) +
+                      " right-hand side(s); run ambddc_solve once with " + std::to_string(nrhs) +
+                      " to prepare it");
+  const int n = c.L[0]->ndof;
+  int64_t nd, ni;
+  pcg_work_size(n, nrhs, maxit, nd, ni);
+  const size_t dbytes = (size_t(nd) * sizeof(double) + 255) / 256 * 256;
+  const size_t need = dbytes + size_t(ni) * sizeof(int);
+  if (need > NOALLOC_BYTES)
+    throw Error(AMBDDC_E_INVALID_ARG,
+                "solve needs " + std::to_string(need) + " bytes of scratch (n_free " +
+                    std::to_string(n) + ", nrhs " + std::to_string(nrhs) + ", maxit " +
+                    std::to_string(maxit) + "); the fixed array holds " +
+                    std::to_string(NOALLOC_BYTES));
+  char* base = static_cast<char*>(scratch_address());
+  const PcgWork w = pcg_work_carve(reinterpret_cast<double*>(base),
+                                   reinterpret_cast<int*>(base + dbytes), n, nrhs, maxit);
+  return pcg_core(c, w, f, nrhs, rtol, maxit, x, its, cond, false);
+}
+
+std::string noconv_message(const ambddc_ctx& c, int left) {
+  double worst = 0.0;
+  for (int k = 0; k < c.n_last_res; ++k) worst = std::max(worst, c.last_res[k]);
+  std::string m = std::to_string(left) + " right-hand side(s) did not reach rtol: ";
+  if (c.stats.pcg_stalled > 0)
+    m += std::to_string(c.stats.pcg_stalled) +
+         " stalled (the true residual stopped falling above rtol: the FP64 rounding floor of "
+         "f - K x on this system)";
+  else
+    m += "maxit reached";
+  char buf[64];
+  std::snprintf(buf, sizeof(buf), "; largest true residual %.3e", worst);
+  return m + buf;
 }
 
 int guard(const std::function<void()>& fn) {
@@ -1396,8 +1590,8 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     if (dec->levels < 2 || dec->levels > 8 || !dec->elem_to_sub)
       throw Error(AMBDDC_E_INVALID_ARG, "levels must be in 2..8 with an element map");
     if (dec->levels > 2 && !dec->parents) throw Error(AMBDDC_E_INVALID_ARG, "missing parent maps");
-    if (opt->precision != 0 && opt->precision != 1)
-      throw Error(AMBDDC_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (FP32-stored preconditioners)");
+    if (opt->precision < 0 || opt->precision > 2)
+      throw Error(AMBDDC_E_INVALID_ARG, "precision must be 0, 1 or 2");
     if (opt->nev_max < 0 || opt->lobpcg_maxit < 1 || opt->lobpcg_tol <= 0.0 ||
         opt->fixed_per_face < 0)
       throw Error(AMBDDC_E_INVALID_ARG, "bad LOBPCG options");
@@ -1559,9 +1753,24 @@ ambddc_status ambddc_solve(ambddc_handle h, const double* rhs, int32_t nrhs, dou
     const int left = pcg_impl(*h, rhs, nrhs, rtol, maxit, x, its.data(), cd.data());
     if (iterations) std::copy(its.begin(), its.end(), iterations);
     if (cond) std::copy(cd.begin(), cd.end(), cond);
-    if (left > 0)
-      throw Error(AMBDDC_E_NO_CONVERGENCE,
-                  std::to_string(left) + " right-hand side(s) did not reach rtol in maxit");
+    if (left > 0) throw Error(AMBDDC_E_NO_CONVERGENCE, noconv_message(*h, left));
+  });
+  return ambddc_status(code);
+}
+
+ambddc_status ambddc_solve_noalloc(ambddc_handle h, const double* rhs, int32_t nrhs, double rtol,
+                                   int32_t maxit, double* x, int32_t* iterations, double* cond) {
+  int code = guard([&] {
+    if (!h || !rhs || !x) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
+    if (!h->ready) throw Error(AMBDDC_E_STATE, "solve called before a successful setup");
+    if (nrhs < 1) throw Error(AMBDDC_E_INVALID_ARG, "nrhs must be >= 1");
+    if (maxit < 1 || !(rtol > 0.0)) throw Error(AMBDDC_E_INVALID_ARG, "bad rtol or maxit");
+    int its[16] = {};
+    double cd[16] = {};
+    const int left = pcg_noalloc(*h, rhs, nrhs, rtol, maxit, x, its, cd);
+    if (iterations) std::copy(its, its + nrhs, iterations);
+    if (cond) std::copy(cd, cd + nrhs, cond);
+    if (left > 0) throw Error(AMBDDC_E_NO_CONVERGENCE, noconv_message(*h, left));
   });
   return ambddc_status(code);
 }
@@ -1580,10 +1789,10 @@ ambddc_status ambddc_element_gradient(ambddc_handle h, const double* X, const do
 ambddc_status ambddc_last_residual(ambddc_handle h, int32_t nrhs, double* res) {
   return ambddc_status(hguard(h, [&] {
     if (!h || !res) throw Error(AMBDDC_E_INVALID_ARG, "null argument");
-    if (nrhs != int(h->last_res.size()))
+    if (nrhs != h->n_last_res)
       throw Error(AMBDDC_E_STATE, "nrhs differs from the last solve (" +
-                                      std::to_string(h->last_res.size()) + ")");
-    std::copy(h->last_res.begin(), h->last_res.end(), res);
+                                      std::to_string(h->n_last_res) + ")");
+    std::copy(h->last_res, h->last_res + nrhs, res);
   }));
 }
 

@@ -77,12 +77,14 @@ class Handle:
                  initial="c+e", keep_edges=False, fixed_per_face=0):
         """precision 0: FP64 throughout; 1: the PCG preconditioner's dense
         subdomain operators are kept in FP32 (widened to FP64 on load),
-        everything else in FP64.  initial: "c+e" (default), "c+e+f" (or
+        everything else in FP64; 2: as 1, and the pair LOBPCG runs its
+        operator products in FP32 on MFMA until each pair's residual reaches
+        1e-5 (or stalls), then polishes in FP64.  initial: "c+e" (default), "c+e+f" (or
         face_averages=True) or "c"; keep_edges: adaptive rows keep their
         entries on shared edges and corners; fixed_per_face = k > 0: k
         eigenvector constraints per face regardless of tau ("3eigv": 3)."""
-        if precision not in (0, 1):
-            raise ValueError("precision must be 0 or 1")
+        if precision not in (0, 1, 2):
+            raise ValueError("precision must be 0, 1 or 2")
         lib = _lib.load()
         self._lib = lib
         self._coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -168,6 +170,27 @@ class Handle:
             tr = list(res)
         return SolveResult(xs, list(its), list(cond), tr)
 
+    def solve_noalloc(self, rhs, x, rtol=1e-10, maxit=1000, raise_on_noconv=True):
+        """ambddc_solve_noalloc: rhs and x are float64 GPU tensors of the same
+        shape, (n_free,) or (nrhs, n_free), nrhs <= 3; the library allocates
+        no device memory in this call."""
+        r2 = rhs if rhs.dim() == 2 else rhs.view(1, -1)
+        x2 = x if x.dim() == 2 else x.view(1, -1)
+        if x2.shape != r2.shape:
+            raise ValueError("x must have the shape of rhs")
+        nrhs = r2.shape[0]
+        its = (C.c_int32 * nrhs)()
+        cond = (C.c_double * nrhs)()
+        code = self._lib.ambddc_solve_noalloc(self._h, _dev_ptr(r2), nrhs, float(rtol),
+                                              int(maxit), _dev_ptr(x2), its, cond)
+        if code != 0 and (raise_on_noconv or code != 4):
+            _lib.check(code)
+        res = (C.c_double * nrhs)()
+        tr = None
+        if self._lib.ambddc_last_residual(self._h, nrhs, res) == 0:
+            tr = list(res)
+        return SolveResult(x, list(its), list(cond), tr)
+
     def setup_log10(self, theta, nu=None, check=True):
         """Set-up with coefficients 10^theta computed on the device."""
         self.setup_count += 1
@@ -206,9 +229,10 @@ class Handle:
         return dict(levels=L, n_free=s.n_free, n_sub=list(s.n_sub[:L]),
                     n_pairs=list(s.n_pairs[:L]), n_coarse=list(s.n_coarse[:L]),
                     n_adaptive=list(s.n_adaptive[:L]), lobpcg_iters=list(s.lobpcg_iters[:L]),
+                    lobpcg_iters_fp32=list(s.lobpcg_iters_fp32[:L]),
                     n_unconverged=list(s.n_unconverged[:L]),
                     omega_tilde=list(s.omega_tilde[:L]), t_phase=list(s.t_phase[:8]),
-                    pcg_replacements=s.pcg_replacements)
+                    pcg_replacements=s.pcg_replacements, pcg_stalled=s.pcg_stalled)
 
     def level_info(self, level):
         a = [C.c_int32() for _ in range(4)]

@@ -52,7 +52,9 @@ def check_pair(h, level, p, L, r, prob, log=None, **okw):
     * the selected count and the first unselected eigenvalue;
     * the constraint rows: the support DOFs are identical, the rows
       orthonormal, and their span equals the oracle's (sine of the largest
-      principal angle <= 1e-6).  Where the selection cuts a cluster of
+      principal angle <= 1e-6, or 1e-7 / gap when the relative eigenvalue
+      gap at the cut is below 0.1: the eigenvectors of a residual-1e-7
+      LOBPCG are only that accurate).  Where the selection cuts a cluster of
       eigenvalues (relative gap <= 1e-3 at the cut) only the span of the
       whole cluster is fixed: then the rows must lie inside the span of the
       oracle's rows built from every eigenvector up to the cluster's end.
@@ -83,7 +85,10 @@ def check_pair(h, level, p, L, r, prob, log=None, **okw):
         k = r["k"]
         gap = (lam[k - 1] - lam[k]) / lam[k - 1] if k < len(lam) else 1.0
         if gap > 1e-3:
-            assert subspace_gap(rows, r["rows"]) <= 1e-6, (level, p)
+            # an eigenvector converged to relative residual 1e-7 is accurate
+            # to about 1e-7 / gap: the spans agree to 1e-6 unless the gap at
+            # the cut is below 0.1
+            assert subspace_gap(rows, r["rows"]) <= max(1e-6, 1e-7 / gap), (level, p, gap)
         else:
             j = k
             while j < len(lam) and lam[j - 1] - lam[j] <= 1e-3 * lam[j - 1]:
@@ -97,3 +102,21 @@ def check_pair(h, level, p, L, r, prob, log=None, **okw):
                     f"against the span of {j} eigenvectors")
             assert np.abs(out).max() <= 1e-6, (level, p, np.abs(out).max())
     return gp["k"]
+
+
+_FLOORS = {}
+
+
+def residual_floor(key, prob):
+    """||f - K x|| / ||f|| (FP64, per column, max) of the oracle's sparse direct
+    solution: what an FP64 solution of this system attains, as measured by
+    the same residual formula the tests use."""
+    if key not in _FLOORS:
+        import oracle as O
+        from oracle import fem
+        K = fem.assemble_global(prob)
+        xd = O.direct_solve(prob)
+        f = prob.rhs
+        _FLOORS[key] = float((np.linalg.norm(f - K @ xd.reshape(f.shape), axis=0) /
+                              np.linalg.norm(f, axis=0)).max())
+    return _FLOORS[key]

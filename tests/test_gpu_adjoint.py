@@ -4,10 +4,10 @@ FP64 oracle, central finite differences and the scaling identity.
 Workload C5: Poisson 32^3, 4x4x4 subdomains, theta ~ N(2,1) per element,
 8 unit point sources; x_obs from the perturbed theta_obs by the oracle's
 direct solve.  Tolerances: J and the gradient within 1e-8 (relative to
-max|g|) of the oracle's direct-solve gradient (PCG at rtol 1e-13), with the FP64 preconditioner
+max|g|) of the oracle's direct-solve gradient (PCG at rtol 1e-11), with the FP64 preconditioner
 and with its operators stored in FP32 (PCG on FP64 residuals refines the
 solutions to the same accuracy); central
-differences (h = 1e-4, the GPU solver at rtol 1e-13) within 1e-4 relative
+differences (h = 1e-4, the GPU solver at rtol 1e-11) within 1e-4 relative
 plus 1e-6 max|g| absolute; the scaling identity
 sum_e g_e = -ln10 sum_k (x_k - x_obs,k)^T x_k, exact since
 K(theta + c) = 10^c K(theta), within 1e-9 relative.
@@ -71,7 +71,7 @@ def test_autograd_gradient_matches_oracle(name, precision):
     from paper_1301_0191_amd.adjoint import misfit
     th = torch.from_numpy(theta).to(dev).requires_grad_(True)
     xo = torch.from_numpy(np.ascontiguousarray(x_obs.T)).to(dev)
-    J = misfit(th, h, F, xo, rtol=1e-13)
+    J = misfit(th, h, F, xo, rtol=1e-11)
     J.backward()
     g = th.grad.cpu().numpy()
     log("  J", float(J.detach()), J_or, " max|g|", np.abs(g_or).max())
@@ -87,7 +87,7 @@ def test_gradient_central_differences_c5():
     from paper_1301_0191_amd.adjoint import misfit
     xo = torch.from_numpy(np.ascontiguousarray(x_obs.T)).to(dev)
     th = torch.from_numpy(theta).to(dev).requires_grad_(True)
-    J = misfit(th, h, F, xo, rtol=1e-13)
+    J = misfit(th, h, F, xo, rtol=1e-11)
     J.backward()
     g = th.grad.cpu().numpy()
     gmax = np.abs(g).max()
@@ -97,8 +97,8 @@ def test_gradient_central_differences_c5():
         tp[e] += step
         tm = theta.copy()
         tm[e] -= step
-        Jp = float(misfit(torch.from_numpy(tp).to(dev), h, F, xo, rtol=1e-13))
-        Jm = float(misfit(torch.from_numpy(tm).to(dev), h, F, xo, rtol=1e-13))
+        Jp = float(misfit(torch.from_numpy(tp).to(dev), h, F, xo, rtol=1e-11))
+        Jm = float(misfit(torch.from_numpy(tm).to(dev), h, F, xo, rtol=1e-11))
         d = (Jp - Jm) / (2 * step)
         assert abs(d - g[e]) <= 1e-4 * abs(g[e]) + 1e-6 * gmax, (e, d, g[e])
     h.close()
@@ -110,9 +110,9 @@ def test_gradient_scaling_identity_c5():
     torch, h, dev, F = _gpu(prob)
     xo = torch.from_numpy(np.ascontiguousarray(x_obs.T)).to(dev)
     h.setup_log10(torch.from_numpy(theta).to(dev))
-    X = h.solve(F, rtol=1e-13).x
+    X = h.solve(F, rtol=1e-11).x
     J, R = h.misfit(X, xo)
-    Lam = h.solve(R, rtol=1e-13).x
+    Lam = h.solve(R, rtol=1e-11).x
     g = h.element_gradient(X, Lam).cpu().numpy()
     Xh, Rh = X.cpu().numpy(), R.cpu().numpy()
     assert np.abs(Rh - (Xh - x_obs.T)).max() == 0.0
@@ -131,9 +131,9 @@ def test_backward_after_another_forward_on_the_same_handle():
     from paper_1301_0191_amd.adjoint import misfit
     xo = torch.from_numpy(np.ascontiguousarray(x_obs.T)).to(dev)
     th1 = torch.from_numpy(theta).to(dev).requires_grad_(True)
-    J1 = misfit(th1, h, F, xo, rtol=1e-13)
+    J1 = misfit(th1, h, F, xo, rtol=1e-11)
     th2 = torch.from_numpy(theta + 0.3).to(dev).requires_grad_(True)
-    J2 = misfit(th2, h, F, xo, rtol=1e-13)
+    J2 = misfit(th2, h, F, xo, rtol=1e-11)
     J1.backward()
     g = th1.grad.cpu().numpy()
     assert float(J1) == pytest.approx(J_or, rel=1e-9)

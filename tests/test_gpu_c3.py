@@ -32,15 +32,22 @@ def log(*a):
     print(*a, flush=True)
 
 
-def test_c3_sampled_pairs_and_true_residual():
-    log("CASE c3 full size")
+_LEVEL = {}
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+def test_c3_sampled_pairs_and_true_residual(precision):
+    log("CASE c3 full size, precision", precision)
     prob = W.CONFIGS["c3"](0)
-    h = gpu_handle(prob)
+    h = gpu_handle(prob, precision=precision)
     st = h.stats()
     assert st["n_sub"] == [216] and st["n_pairs"] == [540]
     assert st["n_unconverged"] == [0]
-    log("  gpu set-up done; oracle level 1")
-    L = build_level(level1_input(prob))
+    log("  gpu set-up done; LOBPCG", st["lobpcg_iters"], "FP32", st["lobpcg_iters_fp32"],
+        "adaptive", st["n_adaptive"], "omega", st["omega_tilde"])
+    if "L" not in _LEVEL:
+        _LEVEL["L"] = build_level(level1_input(prob))
+    L = _LEVEL["L"]
     sizes = [L.n_G[s] + L.n_G[t] for s, t, _ in L.pairs]
     sample = sorted(set(list(range(0, 540, 54)) + [int(np.argmax(sizes))]))
     n_sel = 0
