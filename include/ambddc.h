@@ -271,15 +271,18 @@ ambddc_status ambddc_get_schur(ambddc_handle h, int32_t level, int32_t sub, doub
 ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int32_t* s, int32_t* t,
                                int32_t* n_face);
 
-/* Result of the pair eigenproblem: lam_host[lobpcg_block] (descending),
- * resid_host[lobpcg_block] relative residuals
- * |A x - lam B x| / (|A x| + max(|lam|, 1e-6 lam_1) |B x|),
- * number of selected constraints k (after the QR rank test), the first
- * unselected eigenvalue, LOBPCG iterations and a converged flag.  Any output
- * pointer may be NULL. */
-ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, double* lam_host,
-                                     double* resid_host, int32_t* k, double* lam_next,
-                                     int32_t* iters, int32_t* converged);
+/* Result of the pair eigenproblem: *block = the LOBPCG block size m of the
+ * level (max(lobpcg_block, constraints per face + 1)); lam_host[m]
+ * (descending) and resid_host[m], relative residuals
+ * |A x - lam B x| / (|A x| + max(|lam|, 1e-6 lam_1) |B x|), written when
+ * cap >= m (cap = entries the two arrays hold; E_INVALID_ARG otherwise, so
+ * query m first with both NULL); number of selected constraints k (after the
+ * QR rank test), the first unselected eigenvalue, LOBPCG iterations and a
+ * converged flag.  Any output pointer may be NULL. */
+ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, int32_t cap,
+                                     int32_t* block, double* lam_host, double* resid_host,
+                                     int32_t* k, double* lam_next, int32_t* iters,
+                                     int32_t* converged);
 
 /* Adaptive constraint rows of the face of `pair`: rows_host[k*n_face],
  * row-major (row l = l-th orthonormal row), and the level DOF ids they are

@@ -86,8 +86,9 @@ _SIGS = {
     "ambddc_get_schur": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "ambddc_pair_info": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-    "ambddc_get_pair_result": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
-                                         C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+    "ambddc_get_pair_result": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_int32), C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ambddc_get_face_constraints": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                               C.c_void_p]),

@@ -322,9 +322,9 @@ void lp_from_slab_w(const PairDev* P, int np, const double* Y, int m, double* V,
 // until its first nconv columns have converged to tol; converged columns are
 // soft-locked), 1 = FP32 products (no column converges or locks; the pair
 // moves to phase 2 once the largest residual of its first nconv columns is
-// <= tol32, or has not halved over the last three iterations: the FP32
-// products stall there).  hist: 4 doubles per pair (the last three of those
-// largest residuals, newest first, and their count).  One wave per column
+// <= tol32, or has made no new best at least twice below the previous best
+// for three iterations: the FP32 products stall there).  hist: 4 doubles per
+// pair (best residual, iterations since it halved, -, iterations).  One wave per column
 // (wave reductions, no barrier inside a column).
 constexpr int RES_THREADS = 1024;
 
@@ -384,13 +384,17 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const PairDev* P, doub
   }
   double r = 0.0;
   for (int c = 0; c < min(nconv, 32); ++c) r = fmax(r, relc[c]);
+  // stalled: no new best residual at least twice below the previous best
+  // for three iterations (robust to the oscillation of a rounding floor)
   double* h = hist + 4 * (size_t)blockIdx.x;
-  const bool stalled = h[3] >= 3.0 && r > 0.5 * h[2];
-  if (r <= tol32 || stalled || !(r == r)) active[blockIdx.x] = 2;
-  h[2] = h[1];
-  h[1] = h[0];
-  h[0] = r;
+  if (h[3] == 0.0 || r < 0.5 * h[0]) {
+    h[0] = r;
+    h[1] = 0.0;
+  } else {
+    h[1] += 1.0;
+  }
   h[3] += 1.0;
+  if (r <= tol32 || h[1] >= 3.0 || !(r == r)) active[blockIdx.x] = 2;
 }
 
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,

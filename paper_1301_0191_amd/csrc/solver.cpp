@@ -1898,14 +1898,18 @@ ambddc_status ambddc_pair_info(ambddc_handle h, int32_t level, int32_t pair, int
   }));
 }
 
-ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, double* lam,
-                                     double* resid, int32_t* k, double* lam_next, int32_t* iters,
-                                     int32_t* converged) {
+ambddc_status ambddc_get_pair_result(ambddc_handle h, int32_t level, int32_t pair, int32_t cap,
+                                     int32_t* block, double* lam, double* resid, int32_t* k,
+                                     double* lam_next, int32_t* iters, int32_t* converged) {
   return ambddc_status(hguard(h, [&] {
     if (!h || level < 0 || level >= int(h->L.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad level");
     const Level& L = *h->L[level];
     if (pair < 0 || pair >= int(L.plan.pairs.size())) throw Error(AMBDDC_E_INVALID_ARG, "bad pair");
     if (L.pair_k.empty()) throw Error(AMBDDC_E_STATE, "no adaptive results on this level");
+    if (block) *block = L.m;
+    if ((lam || resid) && cap < L.m)
+      throw Error(AMBDDC_E_INVALID_ARG, "result arrays hold " + std::to_string(cap) +
+                                            " entries; the block has " + std::to_string(L.m));
     if (lam) std::copy(L.pair_lam.begin() + size_t(pair) * L.m,
                        L.pair_lam.begin() + size_t(pair + 1) * L.m, lam);
     if (resid) std::copy(L.pair_res.begin() + size_t(pair) * L.m,

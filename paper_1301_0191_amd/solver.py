@@ -261,12 +261,15 @@ class Handle:
                                               C.byref(nf)))
         return s.value, t.value, nf.value
 
-    def pair_result(self, level, pair, block=16):
-        lam = np.zeros(block, dtype=np.float64)
-        res = np.zeros(block, dtype=np.float64)
+    def pair_result(self, level, pair):
+        m = C.c_int32()
+        _lib.check(self._lib.ambddc_get_pair_result(self._h, level, pair, 0, C.byref(m), None,
+                                                    None, None, None, None, None))
+        lam = np.zeros(m.value, dtype=np.float64)
+        res = np.zeros(m.value, dtype=np.float64)
         k, it, cv = C.c_int32(), C.c_int32(), C.c_int32()
         ln = C.c_double()
-        _lib.check(self._lib.ambddc_get_pair_result(self._h, level, pair,
+        _lib.check(self._lib.ambddc_get_pair_result(self._h, level, pair, m.value, None,
                                                     lam.ctypes.data_as(C.c_void_p),
                                                     res.ctypes.data_as(C.c_void_p), C.byref(k),
                                                     C.byref(ln), C.byref(it), C.byref(cv)))

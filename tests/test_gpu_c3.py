@@ -10,7 +10,7 @@ oracle cannot run the whole method in test time.
   a selection that cuts a cluster against the span of the whole cluster).
 * Properties that hold at any size: the library stops a column only when
   its recomputed true residual meets rtol (residual replacement), so after
-  a solve to rtol 5e-11 the true FP64 residual ||f - K x|| / ||f|| with K
+  a solve to rtol 9e-11 the true FP64 residual ||f - K x|| / ||f|| with K
   assembled by the oracle is <= 1e-10 (the target; the margin covers the
   rounding of the two residual evaluations) and agrees with the residual
   the library reports; the condition estimate is >= 1; every pair
@@ -60,7 +60,7 @@ def test_c3_sampled_pairs_and_true_residual(precision):
     log("  pairs with constraints in the sample:", n_sel)
     torch = pytest.importorskip("torch")
     rhs = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda:0")
-    out = h.solve(rhs, rtol=5e-11, maxit=2000)
+    out = h.solve(rhs, rtol=9e-11, maxit=2000)
     X = out.x.cpu().numpy().T
     K = fem.assemble_global(prob)
     f = prob.rhs
@@ -68,7 +68,7 @@ def test_c3_sampled_pairs_and_true_residual(precision):
     log("  its", out.iterations, "cond", out.cond, "true residual", res, "library's",
         out.true_residual, "residual replacements", h.stats()["pcg_replacements"])
     assert (res <= 1e-10).all()
-    assert (np.asarray(out.true_residual) <= 5e-11).all()
+    assert (np.asarray(out.true_residual) <= 9e-11).all()
     assert np.allclose(out.true_residual, res, rtol=0.5, atol=1e-11)
     assert out.cond[0] >= 1.0 - 1e-9
     h.close()

@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "box_mesh", "box_decomposition", "make_problem",
-    "config_c1", "config_c2", "config_c3", "config_c4", "config_c5",
+    "config_c1", "config_c2", "config_c3", "config_c4", "config_c5", "cube_tab5",
     "tiny_poisson", "tiny_elasticity", "CONFIGS",
 ]
 
@@ -299,6 +299,34 @@ def config_c5(seed: int = 0) -> Problem:
                    None, e2s, [], dmask, rhs, levels=2, tau=10.0,
                    extra={"theta": theta, "theta_obs": theta_obs, "sources": src,
                           "fd_elems": fd})
+
+
+def cube_tab5(tau2: float = 4.0, n: int = 64, sub: int = 4, group: int = 4,
+              seed: int = 0) -> Problem:
+    """Homogeneous elasticity cube of Section 8.1's level comparison (Tab. 5).
+
+    n^3 Q1 elements (64^3: 823,875 nodal DOFs), cubic level-1 subdomains of
+    sub^3 elements (4,096 of 4^3), grouped group^3 per level-2 subdomain (64);
+    E = 1, nu = 0.3 (the paper does not state them), body force (0, 0, -1)
+    as a consistent nodal load (own weight).  Support: the vertical face
+    x = 0 is clamped (the paper fixes one vertical edge; fixing a line alone
+    leaves the rotation about it free).  Three levels; tau = sqrt(tau2) on
+    both substructured levels, so that the indicator target of the product
+    is tau2.  The random generator is not used (the problem is fixed).
+    """
+    del seed
+    coords, elem_nodes = box_mesh(n, n, n)
+    e2s, nb = box_decomposition((n, n, n), [uniform_cuts(n, n // sub)] * 3)
+    parent, _ = group_boxes(nb, (group, group, group))
+    dmask = dirichlet_face(coords, 3, 0)
+    vol = (1.0 / n) ** 3
+    load = np.zeros((coords.shape[0], 3))
+    np.add.at(load[:, 2], elem_nodes.ravel(), -vol / 8.0)
+    rhs = load.ravel()[dmask == 0][:, None]
+    ne = n ** 3
+    return _finish(f"tab5_elasticity{n}_tau2_{tau2:g}", (n, n, n), coords, elem_nodes, 3,
+                   np.ones(ne), np.full(ne, 0.3), e2s, [parent], dmask, rhs, levels=3,
+                   tau=float(np.sqrt(tau2)), extra={"tau2": tau2})
 
 
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4,
