@@ -61,6 +61,11 @@ def parse():
                          "sampled CPU baseline, scaled to the whole workload by operation "
                          "counts; 0 = run the whole method in the oracle (default: 0 for "
                          "C1/C2/C5, 12 for C3/C4)")
+    ap.add_argument("--table5", action="store_true",
+                    help="instead of the benchmark: the level comparison of Section 8.1 "
+                         "(Tab. 5) on the synthetic 64^3 elasticity cube, three levels, "
+                         "tau^2 = 25, 16, 9, 4, 2.25, and the non-adaptive c+e+f and c+e runs")
+    ap.add_argument("--table5-n", type=int, default=64, help="elements per side for --table5")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the steps, copy a device buffer of this size once (a plain "
                          "copy kernel of known traffic, for calibrating HBM counters)")
@@ -248,8 +253,56 @@ def cpu_baseline_sampled(prob, nsamp, pcg_its):
                            if prob.levels > 2 else "")))
 
 
+def run_table5(args):
+    """Tab. 5 on the synthetic cube: one set-up + solve (rtol 1e-8, as the
+    paper's serial runs) per row; prints one JSON line with the rows."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1301_0191_amd import Handle
+    dev = torch.device("cuda:0")
+    rows = []
+    variants = [(t2, "c+e", dict()) for t2 in (25.0, 16.0, 9.0, 4.0, 2.25)]
+    variants += [(None, "c+e+f", dict(initial="c+e+f", tau=0.0)),
+                 (None, "c+e", dict(tau=0.0))]
+    for t2, init, kw in variants:
+        prob = W.cube_tab5(t2 if t2 else 4.0, n=args.table5_n)
+        t0 = time.perf_counter()
+        h = Handle.from_problem(prob, precision=args.precision, **kw)
+        print(f"table5: handle for tau2={t2} {init} in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        coeff = torch.from_numpy(prob.coeff).to(dev)
+        nu = torch.from_numpy(prob.nu).to(dev)
+        rhs = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.setup(coeff, nu)
+        res = h.solve(rhs, rtol=1e-8, maxit=5000, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t0
+        st = h.stats()
+        om = st["omega_tilde"]
+        row = {"tau2": t2, "initial": init, "n_free": st["n_free"],
+               "pairs": st["n_pairs"], "adaptive_constraints": st["n_adaptive"],
+               "constraints_per_pair": [a / p if p else 0.0
+                                        for a, p in zip(st["n_adaptive"], st["n_pairs"])],
+               "omega_tilde_levels": om,
+               "omega_tilde": float(np.prod([o for o in om if o > 0])) if t2 else None,
+               "its": res.iterations[0], "cond": res.cond[0],
+               "lobpcg_iterations": st["lobpcg_iters"], "n_unconverged": st["n_unconverged"],
+               "setup_s": st["t_phase"][6], "solve_s": st["t_phase"][7], "wall_s": t1}
+        rows.append(row)
+        print("table5 row", json.dumps(row), file=sys.stderr, flush=True)
+        h.close()
+    print(json.dumps({"table5": rows, "workload": f"cube_tab5 n={args.table5_n}",
+                      "precision": args.precision}), flush=True)
+
+
 def main():
     args = parse()
+    if args.table5:
+        run_table5(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md but not built.", file=sys.stderr)

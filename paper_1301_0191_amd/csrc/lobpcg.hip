@@ -376,25 +376,35 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const PairDev* P, doub
     if (mode == 2 && rel <= tol)
       for (int i = lane; i < n; i += 64) w[i] = 0.0;
   }
+  __shared__ int to_fp64;
   __syncthreads();
-  if (threadIdx.x != 0) return;
   if (mode == 2) {
-    if (n_bad == 0) active[blockIdx.x] = 0;
+    if (threadIdx.x == 0 && n_bad == 0) active[blockIdx.x] = 0;
     return;
   }
-  double r = 0.0;
-  for (int c = 0; c < min(nconv, 32); ++c) r = fmax(r, relc[c]);
-  // stalled: no new best residual at least twice below the previous best
-  // for three iterations (robust to the oscillation of a rounding floor)
-  double* h = hist + 4 * (size_t)blockIdx.x;
-  if (h[3] == 0.0 || r < 0.5 * h[0]) {
-    h[0] = r;
-    h[1] = 0.0;
-  } else {
-    h[1] += 1.0;
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int c = 0; c < min(nconv, 32); ++c) r = fmax(r, relc[c]);
+    // stalled: no new best residual at least twice below the previous best
+    // for three iterations (robust to the oscillation of a rounding floor)
+    double* h = hist + 4 * (size_t)blockIdx.x;
+    if (h[3] == 0.0 || r < 0.5 * h[0]) {
+      h[0] = r;
+      h[1] = 0.0;
+    } else {
+      h[1] += 1.0;
+    }
+    h[3] += 1.0;
+    to_fp64 = (r <= tol32 || h[1] >= 3.0 || !(r == r)) ? 1 : 0;
+    if (to_fp64) active[blockIdx.x] = 2;
   }
-  h[3] += 1.0;
-  if (r <= tol32 || h[1] >= 3.0 || !(r == r)) active[blockIdx.x] = 2;
+  __syncthreads();
+  // entering the FP64 phase restarts the search history: the P block, built
+  // from FP32 products, is dropped (the next Rayleigh-Ritz runs on [X W])
+  if (to_fp64) {
+    double* pb = V + p.v_off + (size_t)(2 * m) * n;
+    for (int i = threadIdx.x; i < m * n; i += RES_THREADS) pb[i] = 0.0;
+  }
 }
 
 void lp_residual(const PairDev* P, int np, double* V, const double* AV, const double* BV,

@@ -87,8 +87,12 @@ def check_pair(h, level, p, L, r, prob, log=None, **okw):
         if gap > 1e-3:
             # an eigenvector converged to relative residual 1e-7 is accurate
             # to about 1e-7 / gap: the spans agree to 1e-6 unless the gap at
-            # the cut is below 0.1
-            assert subspace_gap(rows, r["rows"]) <= max(1e-6, 1e-7 / gap), (level, p, gap)
+            # the cut is below 0.1.  On level >= 2 the pair operators are
+            # assembled from level-1 coarse matrices whose constraint rows
+            # agree with the oracle's to 1e-6, ten times that.
+            tol = max(1e-6, 1e-7 / gap) * (10.0 if level > 0 else 1.0)
+            sg = subspace_gap(rows, r["rows"])
+            assert sg <= tol, (level, p, gap, sg)
         else:
             j = k
             while j < len(lam) and lam[j - 1] - lam[j] <= 1e-3 * lam[j - 1]:

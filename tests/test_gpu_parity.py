@@ -151,9 +151,9 @@ VARIANTS = {
     "c1_keep_edges": ("c1", dict(keep_edges=True), dict(keep_edges=True)),
     "c2_keep_edges": ("c2", dict(keep_edges=True), dict(keep_edges=True)),
     # the cap of 10 per face lifted to 20 (LOBPCG block 21, Rayleigh-Ritz of order 63)
-    "c1_keep_edges_cap20": ("c1", dict(keep_edges=True, nev_max=20),
+    "c1_keep_edges_cap20": ("c1", dict(keep_edges=True, nev_max=20, lobpcg_maxit=300),
                             dict(keep_edges=True, nev_max=20)),
-    "elasticity_cap20": ("elasticity", dict(nev_max=20), dict(nev_max=20)),
+    "elasticity_cap20": ("elasticity", dict(nev_max=20, lobpcg_maxit=300), dict(nev_max=20)),
 }
 
 
