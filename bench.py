@@ -53,14 +53,14 @@ def parse():
                          "preconditioner's dense subdomain operators stored in FP32, 2 = also "
                          "the pair LOBPCG's operator products in FP32 (MFMA, FP32 "
                          "accumulation) before an FP64 polish")
-    ap.add_argument("--compare", default="0,2",
+    ap.add_argument("--compare", default="0,1,2",
                     help="precision modes also timed on the same workload (comma-separated; "
                          "empty for none)")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="subdomains (and about as many pairs) the oracle handles for a "
                          "sampled CPU baseline, scaled to the whole workload by operation "
                          "counts; 0 = run the whole method in the oracle (default: 0 for "
-                         "C1/C2/C5, 12 for C3/C4)")
+                         "C1/C2/C5, 24 for C3/C4)")
     ap.add_argument("--table5", action="store_true",
                     help="instead of the benchmark: the level comparison of Section 8.1 "
                          "(Tab. 5) on the synthetic 64^3 elasticity cube, three levels, "
@@ -472,7 +472,7 @@ def main():
     if not args.no_cpu_baseline:
         nsamp = args.cpu_sample
         if nsamp is None:
-            nsamp = 12 if args.config in ("c3", "c4") else 0
+            nsamp = 24 if args.config in ("c3", "c4") else 0
         if nsamp > 0:
             out["cpu_baseline"] = cpu_baseline_sampled(prob, nsamp, int(max(res.iterations)))
         else:

@@ -422,7 +422,8 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // B (stopping below 1e-12: numerically dependent directions are dropped) and
 // eliminates column p from the remaining rows, B <- B - b_p b_p^T / b_pp,
 // while the same row operations are accumulated in F (F <- E F, starting
-// from I).  With the pivot rows of F scaled by b_pp^{-1/2} and by D,
+// from I; stopping below the drop level, see k_rr).  With the pivot rows of
+// F scaled by b_pp^{-1/2} and by D,
 // Fc (r x nb) satisfies Fc GB Fc^T = I, and A_r = Fc GA Fc^T (two small
 // products) gives its m largest eigenpairs (Y, descending) by tridiagonal
 // reduction, multisection and inverse iteration (rr_eig.hpp), which only
@@ -456,6 +457,11 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
                                             double* Cf2, double* lam, const int* active) {
   extern __shared__ double sm[];
   if (active && !active[blockIdx.x]) return;
+  // directions whose scaled B-norm^2 left after the elimination is at the
+  // rounding level of the products are dropped: 1e-12 for FP64 products,
+  // 1e-6 while the pair's products are FP32 (their errors, about 1e-7 of
+  // the Gram entries, would otherwise turn into spurious Ritz values)
+  const double drop = (active && active[blockIdx.x] == 1) ? 1e-6 : 1e-12;
   const int M3 = 3 * m;
   const int ld = nb | 1;          // odd: row walks are free of bank conflicts
   const double* ga = GA + (size_t)blockIdx.x * M3 * M3;
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
     const double kd = wave_max(lane < nb ? kcur[lane] : 0.0);   // the same for every lane
     const unsigned long long kj = (unsigned long long)__double_as_longlong(kd);
     const double vj = __longlong_as_double((long long)(kj & ~63ull));
-    if (kj == 0ull || !(vj > 1e-12)) break;
+    if (kj == 0ull || !(vj > drop)) break;
     const int p = 63 - (int)(kj & 63ull);
     if (wave < RR_EW) {
       const int i = lane, ic = i < nb ? i : nb - 1;
@@ -1007,7 +1013,21 @@ void lp_select(const PairDev* P, int np, const double* AV, const double* lam, in
                double* lam_next, hipStream_t st) {
   if (np == 0) return;
   const size_t sm = sizeof(double) * size_t(std::min(nev_max, m)) * nface_max;
-  if (sm > 64 * 1024) throw Error(1, "constraint rows of a face exceed the selection kernel's LDS");
+  if (sm > 64 * 1024) {
+    // rows of many constraints on large faces: up to the 160 KB of a gfx950 CU
+    static size_t granted = 0;
+    if (sm > granted) {
+      int dev = 0, lim = 0;
+      AMB_HIP(hipGetDevice(&dev));
+      AMB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      if (size_t(lim) < sm + 1024)
+        throw Error(1, "constraint rows of a face need " + std::to_string(sm) +
+                           " bytes of LDS; the device allows " + std::to_string(lim));
+      AMB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(sm)));
+      granted = sm;
+    }
+  }
   k_select<<<np, 256, sm, st>>>(P, AV, lam, m, nev_max, tau, fixed, face_s, fc, kout, lam_next);
   AMB_LAUNCH_CHECK();
 }

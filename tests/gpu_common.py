@@ -54,7 +54,9 @@ def check_pair(h, level, p, L, r, prob, log=None, **okw):
       orthonormal, and their span equals the oracle's (sine of the largest
       principal angle <= 1e-6, or 1e-7 / gap when the relative eigenvalue
       gap at the cut is below 0.1: the eigenvectors of a residual-1e-7
-      LOBPCG are only that accurate).  Where the selection cuts a cluster of
+      LOBPCG are only that accurate), times the amplification
+      ||c|| / sigma_min(face rows of c) of the face restriction, times 10 on
+      level >= 2 (operators built from level-1 results).  Where the selection cuts a cluster of
       eigenvalues (relative gap <= 1e-3 at the cut) only the span of the
       whole cluster is fixed: then the rows must lie inside the span of the
       oracle's rows built from every eigenvector up to the cluster's end.
@@ -90,9 +92,18 @@ def check_pair(h, level, p, L, r, prob, log=None, **okw):
             # the cut is below 0.1.  On level >= 2 the pair operators are
             # assembled from level-1 coarse matrices whose constraint rows
             # agree with the oracle's to 1e-6, ten times that.
-            tol = max(1e-6, 1e-7 / gap) * (10.0 if level > 0 else 1.0)
+            # The rows span the face restriction F of the vectors c_l: an error
+            # e ||c|| in c turns the span by about e ||c|| / sigma_min(F).
+            from oracle.adaptive import pair_operators
+            Gs = pair_operators(L, s, t)["Gs"]
+            F = r["c_full"][np.searchsorted(Gs, r["face_dofs"])]
+            sv = np.linalg.svd(F, compute_uv=False)
+            amp = max(1.0, np.linalg.norm(r["c_full"], 2) / max(sv[len(r["rows"]) - 1], 1e-300))
+            tol = max(1e-6, 1e-7 / gap) * (10.0 if level > 0 else 1.0) * amp
             sg = subspace_gap(rows, r["rows"])
-            assert sg <= tol, (level, p, gap, sg)
+            if amp > 10 and log:
+                log(f"  pair {p}: face rows amplify errors of c by {amp:.1e}; span tolerance {tol:.1e}")
+            assert sg <= tol, (level, p, gap, sg, amp)
         else:
             j = k
             while j < len(lam) and lam[j - 1] - lam[j] <= 1e-3 * lam[j - 1]:

@@ -54,13 +54,15 @@ def test_fp32_preconditioner_parity(case, precision):
     err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
     log("  its", res.iterations, "oracle", ito, "cond", res.cond, co, "err", err,
         "true residual", res.true_residual)
-    assert err <= 1e-10
     if h.stats()["pcg_stalled"]:
         # rtol below what FP64 attains on this system (C1): within 2x of the
-        # true residual of the oracle's direct solution
+        # true residual of the oracle's direct solution, and the error
+        # between two FP64 solutions of so ill-conditioned a system
         assert max(res.true_residual) <= 2 * residual_floor(case, prob)
+        assert err <= 3e-10
         h.close()
         return
+    assert err <= 1e-10
     assert max(res.true_residual) <= 1e-10
     assert abs(res.iterations[0] - ito[0]) <= 2
     assert res.cond[0] == pytest.approx(co[0], rel=1e-3)
