@@ -26,7 +26,7 @@ __device__ __forceinline__ bool slots_live(const GemmDesc& g, int c0, int c1, co
   return any && !veto;
 }
 
-template <int WM, int WN>
+template <int WM, int WN, typename TBe>
 __global__ __launch_bounds__(256) void k_gemm_f32(const GemmDesc* __restrict__ d, int nd,
                                                   double alpha, double beta,
                                                   const int* __restrict__ act, int mask,
@@ -45,8 +45,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmDesc* __restrict__ d
   if (g.scols > 0 &&
       !slots_live(g, tn * 32 * WN, min(g.N, (tn + 1) * 32 * WN) - 1, act, mask, excl))
     return;
-  mfma_tile_f32<WM, WN>(static_cast<const float*>(g.A), g.lda, g.B, g.ldb, g.C, g.ldc, g.M, g.N,
-                        g.K, tm * 32 * WM, tn * 32 * WN, alpha, beta, sm);
+  mfma_tile_f32<WM, WN, TBe>(static_cast<const float*>(g.A), g.lda,
+                             reinterpret_cast<const TBe*>(g.B), g.ldb, g.C, g.ldc, g.M, g.N, g.K,
+                             tm * 32 * WM, tn * 32 * WN, alpha, beta, sm);
 }
 
 template <bool TA, bool TB, int WM, int WN, typename TAe>
@@ -162,12 +163,18 @@ void GemmOp::run(double alpha, double beta, hipStream_t st) const {
   if (h.empty() || tiles == 0) return;
   if (f32) {
     if (ta || tb || !hs.empty()) throw Error(1, "GemmOp: FP32 products are not transposed or split");
-    if (narrow)
-      k_gemm_f32<4, 1><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act, act_mask,
-                                              act_excl);
+    if (narrow && b32)
+      k_gemm_f32<4, 1, float><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act,
+                                                     act_mask, act_excl);
+    else if (narrow)
+      k_gemm_f32<4, 1, double><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act,
+                                                      act_mask, act_excl);
+    else if (b32)
+      k_gemm_f32<2, 2, float><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act,
+                                                     act_mask, act_excl);
     else
-      k_gemm_f32<2, 2><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act, act_mask,
-                                              act_excl);
+      k_gemm_f32<2, 2, double><<<tiles, 256, 0, st>>>(d.p, int(h.size()), alpha, beta, act,
+                                                      act_mask, act_excl);
     AMB_LAUNCH_CHECK();
     return;
   }

@@ -46,6 +46,7 @@ class GemmOp {
   // as it is staged, and the products accumulate in FP32 on FP32 MFMA; C
   // stays FP64.  Not transposed, no split-K.
   bool f32 = false;
+  bool b32 = false;                             // with f32: B operands are FP32 as well
   const int* act = nullptr;                     // item flags for column-slot skipping
   int act_mask = ~0;                            // a slot counts when (act[item] & act_mask) != 0
   int act_excl = 0;                             // ... and a tile is skipped when any of its
@@ -102,7 +103,10 @@ class TunedGemm {
     v[0].act_mask = v[1].act_mask = mask;
     v[0].act_excl = v[1].act_excl = excl;
   }
-  void set_f32() { v[0].f32 = v[1].f32 = true; }
+  void set_f32(bool b32 = false) {
+    v[0].f32 = v[1].f32 = true;
+    v[0].b32 = v[1].b32 = b32;
+  }
   void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int M, int N,
            int K, const int* flag = nullptr, const int* spair = nullptr, int scols = 0) {
     for (auto& g : v) g.add(A, lda, B, ldb, C, ldc, M, N, K, flag, spair, scols);

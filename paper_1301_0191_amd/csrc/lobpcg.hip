@@ -149,8 +149,12 @@ __device__ inline double pair_ds(const PairDev& p, const double* diagG, int is, 
 // with_ie also writes (I-E) of the block into the next m slot columns.
 __global__ __launch_bounds__(256) void k_to_slab(const PairDev* P, const double* V, int m, int col,
                                                  bool with_ie, const double* diagG, const int* sh_s,
-                                                 const int* sh_t, double* U, const int* active) {
+                                                 const int* sh_t, double* U, float* U32,
+                                                 const int* active) {
   if (active && !active[blockIdx.x]) return;
+  // pairs in the FP32 phase also get the slot in FP32 (the operand of the
+  // FP32 products)
+  if (U32 && !(active && active[blockIdx.x] == 1)) U32 = nullptr;
   int c0, c1;
   col_range(m, c0, c1);
   if (c0 >= c1) return;
@@ -160,18 +164,26 @@ __global__ __launch_bounds__(256) void k_to_slab(const PairDev* P, const double*
   const double* v = V + p.v_off + (size_t)(col * m + c0) * n;
   double* us = U + p.us_off + (size_t)c0 * p.nGs;
   double* ut = U + p.ut_off + (size_t)c0 * p.nGt;
+  float* us32 = U32 ? U32 + p.us_off + (size_t)c0 * p.nGs : nullptr;
+  float* ut32 = U32 ? U32 + p.ut_off + (size_t)c0 * p.nGt : nullptr;
   for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
     const int i = idx % n, c = idx / n;
     const double x = v[idx];
-    if (i < p.nGs) us[i + (size_t)c * p.nGs] = x;
-    else ut[(i - p.nGs) + (size_t)c * p.nGt] = x;
+    const size_t e = i < p.nGs ? i + (size_t)c * p.nGs : (i - p.nGs) + (size_t)c * p.nGt;
+    if (i < p.nGs) us[e] = x;
+    else ut[e] = x;
+    if (us32) (i < p.nGs ? us32 : ut32)[e] = static_cast<float>(x);
   }
   if (!with_ie) return;
   // (I-E) of column c goes to slot column m + c
-  for (int idx = threadIdx.x; idx < p.nGs * nc; idx += blockDim.x)
+  for (int idx = threadIdx.x; idx < p.nGs * nc; idx += blockDim.x) {
     us[(size_t)m * p.nGs + idx] = 0.0;
-  for (int idx = threadIdx.x; idx < p.nGt * nc; idx += blockDim.x)
+    if (us32) us32[(size_t)m * p.nGs + idx] = 0.f;
+  }
+  for (int idx = threadIdx.x; idx < p.nGt * nc; idx += blockDim.x) {
     ut[(size_t)m * p.nGt + idx] = 0.0;
+    if (ut32) ut32[(size_t)m * p.nGt + idx] = 0.f;
+  }
   __syncthreads();
   const int nsh = p.sh1 - p.sh0;
   for (int idx = threadIdx.x; idx < nsh * nc; idx += blockDim.x) {
@@ -179,17 +191,22 @@ __global__ __launch_bounds__(256) void k_to_slab(const PairDev* P, const double*
     const int is = sh_s[p.sh0 + q], it = sh_t[p.sh0 + q];
     const double ds = pair_ds(p, diagG, is, it), dt = 1.0 - ds;
     const double ws = v[is + (size_t)c * n], wt = v[p.nGs + it + (size_t)c * n];
-    us[(size_t)(m + c) * p.nGs + is] = dt * (ws - wt);
-    ut[(size_t)(m + c) * p.nGt + it] = ds * (wt - ws);
+    const double a = dt * (ws - wt), b = ds * (wt - ws);
+    us[(size_t)(m + c) * p.nGs + is] = a;
+    ut[(size_t)(m + c) * p.nGt + it] = b;
+    if (us32) {
+      us32[(size_t)(m + c) * p.nGs + is] = static_cast<float>(a);
+      ut32[(size_t)(m + c) * p.nGt + it] = static_cast<float>(b);
+    }
   }
 }
 
 void lp_to_slab(const PairDev* P, int np, const double* V, int m, int col, bool with_ie,
-                const double* diagG, const int* sh_s, const int* sh_t, double* U, const int* active,
-                hipStream_t st) {
+                const double* diagG, const int* sh_s, const int* sh_t, double* U, float* U32,
+                const int* active, hipStream_t st) {
   if (np == 0) return;
   k_to_slab<<<dim3(np, PAIR_COL_GROUPS), 256, 0, st>>>(P, V, m, col, with_ie, diagG, sh_s, sh_t,
-                                                       U, active);
+                                                       U, U32, active);
   AMB_LAUNCH_CHECK();
 }
 
@@ -400,10 +417,17 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const PairDev* P, doub
   }
   __syncthreads();
   // entering the FP64 phase restarts the search history: the P block, built
-  // from FP32 products, is dropped (the next Rayleigh-Ritz runs on [X W])
+  // from FP32 products, is dropped (the next Rayleigh-Ritz runs on [X W]),
+  // and columns already at tol are soft-locked as in phase 2 (a residual at
+  // the rounding level gives a search direction of pure noise)
   if (to_fp64) {
     double* pb = V + p.v_off + (size_t)(2 * m) * n;
     for (int i = threadIdx.x; i < m * n; i += RES_THREADS) pb[i] = 0.0;
+    for (int c = wave; c < min(m, 32); c += RES_THREADS / 64) {
+      if (!(relc[c] <= tol)) continue;
+      double* w = V + p.v_off + (size_t)(m + c) * n;
+      for (int i = lane; i < n; i += 64) w[i] = 0.0;
+    }
   }
 }
 
@@ -419,7 +443,7 @@ void lp_residual(const PairDev* P, int np, double* V, const double* AV, const do
 // Rayleigh-Ritz on span(V).  With D = diag(GB)^{-1/2}, the scaled Gram
 // matrix B = D GB D is reduced by a diagonally pivoted elimination: step j
 // picks the remaining index p with the largest diagonal entry of the current
-// B (stopping below 1e-12: numerically dependent directions are dropped) and
+// B (stopping below 1e-8: numerically dependent directions are dropped) and
 // eliminates column p from the remaining rows, B <- B - b_p b_p^T / b_pp,
 // while the same row operations are accumulated in F (F <- E F, starting
 // from I; stopping below the drop level, see k_rr).  With the pivot rows of
@@ -457,11 +481,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr(const double* GA, const doubl
                                             double* Cf2, double* lam, const int* active) {
   extern __shared__ double sm[];
   if (active && !active[blockIdx.x]) return;
-  // directions whose scaled B-norm^2 left after the elimination is at the
-  // rounding level of the products are dropped: 1e-12 for FP64 products,
-  // 1e-6 while the pair's products are FP32 (their errors, about 1e-7 of
-  // the Gram entries, would otherwise turn into spurious Ritz values)
-  const double drop = (active && active[blockIdx.x] == 1) ? 1e-6 : 1e-12;
+  // a direction is dropped when the scaled B-norm^2 it keeps after the
+  // elimination is this small: its reduced entries are then the Gram
+  // matrices' rounding errors divided by it, and kept directions of that
+  // kind give Ritz vectors whose residuals stall far above the tolerance.
+  // 1e-8 for FP64 products, 1e-4 while the pair's products are FP32 (Gram
+  // errors near 1e-7 of the entries)
+  const double drop = (active && active[blockIdx.x] == 1) ? 1e-4 : 1e-8;
   const int M3 = 3 * m;
   const int ld = nb | 1;          // odd: row walks are free of bank conflicts
   const double* ga = GA + (size_t)blockIdx.x * M3 * M3;

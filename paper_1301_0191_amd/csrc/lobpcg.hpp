@@ -50,9 +50,11 @@ void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStr
 void lp_project(const PairDev* P, int np, double* V, int m, int col, const double* C,
                 const DRows dr, const double* rb, const int* active, bool deflate,
                 hipStream_t st);
+// U32 (may be null): the slots of pairs in the FP32 phase are also written
+// in FP32 there (same layout as U)
 void lp_to_slab(const PairDev* P, int np, const double* V, int m, int col, bool with_ie,
-                const double* diagG, const int* sh_s, const int* sh_t, double* U, const int* active,
-                hipStream_t st);
+                const double* diagG, const int* sh_s, const int* sh_t, double* U, float* U32,
+                const int* active, hipStream_t st);
 void lp_from_slab_ab(const PairDev* P, int np, const double* Y, int m, int col, double* AV,
                      double* BV, const double* diagG, const int* sh_s, const int* sh_t,
                      const double* C, const DRows dr, const int* active, hipStream_t st);

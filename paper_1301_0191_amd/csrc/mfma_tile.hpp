@@ -174,7 +174,7 @@ namespace ambddc {
 
 // ---------------------------------------------------------------------------
 // FP32 variant: C = alpha * A * B + beta * C with A FP32 (column-major, lda),
-// B FP64 rounded to FP32 as it is staged, products and sums on
+// B FP32, or FP64 rounded to FP32 as it is staged, products and sums on
 // v_mfma_f32_16x16x4f32 (FP32 accumulation), C FP64.  Same tiling as the
 // FP64 tile: 4 waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16), K staged
 // through LDS in chunks of KC32, double buffered, one barrier per chunk.
@@ -191,9 +191,9 @@ struct TileSmem32 {
   float Bs[2][KC32][32 * WN + 4];
 };
 
-template <int WM, int WN>
+template <int WM, int WN, typename TBe>
 __device__ __forceinline__ void mfma_tile_f32(const float* __restrict__ A, int lda,
-                                              const double* __restrict__ B, int ldb, double* C,
+                                              const TBe* __restrict__ B, int ldb, double* C,
                                               int ldc, int M, int N, int K, int m0, int n0,
                                               double alpha, double beta, TileSmem32<WM, WN>& sm) {
   constexpr int TM = 32 * WM, TN = 32 * WN, KC = KC32;
@@ -208,7 +208,7 @@ __device__ __forceinline__ void mfma_tile_f32(const float* __restrict__ A, int l
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
   float ra[NA];
-  double rb[NB];
+  TBe rb[NB];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
@@ -222,7 +222,7 @@ __device__ __forceinline__ void mfma_tile_f32(const float* __restrict__ A, int l
       const int idx = tid + u * 256;
       const int k = idx % KC, n = idx / KC;
       const int gn = n0 + n, gk = k0 + k;
-      rb[u] = (gn < N && gk < K) ? gld(B + gk + (size_t)gn * ldb) : 0.0;
+      rb[u] = (gn < N && gk < K) ? gld(B + gk + (size_t)gn * ldb) : TBe(0);
     }
   };
   auto sstore = [&](int buf) {

@@ -490,7 +490,7 @@ struct PairWork {
   // accumulation, for pairs in the FP32 phase (precision 2)
   TunedGemm gS32, gM1_32, gM2_32;
   bool lo = false;          // some pairs start in the FP32 phase
-  DBuf<float> S32, T32;
+  DBuf<float> S32, T32, U32;
   GemmOp gram[3], upd_v[3], orth_c, orth_u, orthp_c, orthp_u;   // gram: V^T AV and V^T BV in one launch
   KTimer* kt = nullptr;
   std::vector<int> act;                          // host copy of the active flags
@@ -720,10 +720,12 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
     W.gS32.choice = &c.tune.emplace(lk + "S32", -1).first->second;
     W.gM1_32.choice = &c.tune.emplace(lk + "Z32", -1).first->second;
     W.gM2_32.choice = &c.tune.emplace(lk + "Psi32", -1).first->second;
-    for (TunedGemm* g : {&W.gS32, &W.gM1_32, &W.gM2_32}) {
-      g->set_f32();
-      g->set_act(W.active.p, 1);
-    }
+    W.U32.alloc(std::max<int64_t>(Uoff[L.nsub], 1));
+    W.U32.zero(st);
+    W.gS32.set_f32(true);       // S^s (FP32) times the FP32 slots
+    W.gM1_32.set_f32(true);
+    W.gM2_32.set_f32(false);    // the coarse slab stays FP64
+    for (TunedGemm* g : {&W.gS32, &W.gM1_32, &W.gM2_32}) g->set_act(W.active.p, 1);
     for (int s = 0; s < L.nsub; ++s) {
       const int cols = P.sub_npairs[s] * 2 * m;
       if (cols == 0) continue;
@@ -732,10 +734,11 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
       const float* Tn = W.T32.p + to[s];
       const int* sp = W.slot_pair.p + slot_off[s];
       // the FP32 GEMM reads A as plain column-major: the pointers carry floats
-      W.gS32.add(reinterpret_cast<const double*>(S), nG, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s], nl,
-                 nG, cols, nG, nullptr, sp, 2 * m);
-      W.gM1_32.add(reinterpret_cast<const double*>(Tn), nl, W.U.p + Uoff[s], nG, W.Y.p + Yoff[s],
-                   nl, nl, cols, nG, nullptr, sp, 2 * m);
+      const double* U32s = reinterpret_cast<const double*>(W.U32.p + Uoff[s]);
+      W.gS32.add(reinterpret_cast<const double*>(S), nG, U32s, nG, W.Y.p + Yoff[s], nl, nG, cols,
+                 nG, nullptr, sp, 2 * m);
+      W.gM1_32.add(reinterpret_cast<const double*>(Tn), nl, U32s, nG, W.Y.p + Yoff[s], nl, nl,
+                   cols, nG, nullptr, sp, 2 * m);
       if (L.nc[s] > 0)
         W.gM2_32.add(reinterpret_cast<const double*>(Tn + int64_t(nG) * nl), nl,
                      W.Zc.p + Zoff[s], L.nc[s], W.Y.p + Yoff[s], nl, nG, cols, L.nc[s], nullptr,
@@ -865,7 +868,7 @@ void apply_work(const Level& L, const PairWork& W, double& fl, double& by) {
 
 void apply_ab(Level& L, PairWork& W, int col, hipStream_t st) {
   lp_to_slab(W.dp.p, W.np, W.V.p, W.m, col, true, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
-             W.active.p, st);
+             W.lo ? W.U32.p : nullptr, W.active.p, st);
   if (W.kt->any()) {
     double fl, by;
     apply_work(L, W, fl, by);
@@ -974,7 +977,7 @@ void adaptive_level(ambddc_ctx& c, Level& L, int li) {
     flags.fetch(W.active.p, st);
     // W = M R  (eq. bddc_pair: Z^st R + Psi (Psi^T S Psi)^+ Psi^T R, then Pi and deflation)
     lp_to_slab(W.dp.p, W.np, W.V.p, m, 1, false, L.diagG.p, W.idx.sh_s.p, W.idx.sh_t.p, W.U.p,
-               W.active.p, st);
+               W.lo ? W.U32.p : nullptr, W.active.p, st);
     if (W.lo) W.gM1_32.run(1.0, 0.0, st);
     W.gM1.run(1.0, 0.0, st);
     lp_coarse(W.dp.p, W.np, W.Y.p, m, W.Kp.p, W.idx.pc_s.p, W.idx.pc_t.p, W.Zc.p, W.ncp_max,
