@@ -304,8 +304,8 @@ def main():
         run_table5(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); "
+              "a multi-GPU path is not built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -165,8 +165,13 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* decomp
  * statistics (n_unconverged) and their current Ritz values are used. */
 ambddc_status ambddc_setup(ambddc_handle h, const double* coeff_dev, const double* nu_dev);
 
-/* PCG with the Multilevel BDDC preconditioner (Alg. 1), x0 = 0, stopping when
- * ||f - K x||_2 / ||f||_2 <= rtol per column (FP64 residual).  The
+/* PCG with the Multilevel BDDC preconditioner (Alg. 1), stopping when
+ * ||f - K x||_2 / ||f||_2 <= rtol per column (FP64 residual).  x0 is the
+ * level-1 interior solution [K_II^-1 f_I; 0], so every residual is zero on
+ * the level-1 interiors and the iterates stay in the discrete harmonic
+ * space of Section 2: PCG on the interface problem of the Schur complement,
+ * the problem BDDC preconditions (Section 5).  Alg. 1's level-1 interior
+ * pre-correction is then zero and skipped.  The
  * iteration updates the residual recursively; when that meets rtol, the true
  * residual f - K x is recomputed, and a column stops only if it meets rtol
  * too; otherwise it restarts from the true residual (residual replacement),

@@ -26,7 +26,7 @@ from .fem import (element_matrix_poisson, element_matrix_elasticity, element_mat
 from .substructure import build_level, level1_input, LevelInput, Level
 from .adaptive import pair_eigenproblem, enrich_level
 from .bddc import (Hierarchy, setup_hierarchy, bddc_apply, pcg, lanczos_cond,
-                   direct_solve, solve_problem)
+                   direct_solve, solve_problem, interior_solution)
 from .adjoint import misfit_gradient
 
 __all__ = [
@@ -34,5 +34,5 @@ __all__ = [
     "assemble_global", "rigid_modes", "build_level", "level1_input", "LevelInput",
     "Level", "pair_eigenproblem", "enrich_level", "Hierarchy", "setup_hierarchy",
     "bddc_apply", "pcg", "lanczos_cond", "direct_solve", "solve_problem",
-    "misfit_gradient",
+    "interior_solution", "misfit_gradient",
 ]

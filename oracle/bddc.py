@@ -166,15 +166,18 @@ def lanczos_cond(alphas, betas):
     return float(ev[-1] / ev[0]), float(ev[0]), float(ev[-1])
 
 
-def pcg(K, f, M, rtol=1e-10, maxit=1000):
-    """Preconditioned CG from x0 = 0; stops when ||f - K x|| / ||f|| <= rtol
-    (recursive residual).  Returns x, iterations, alphas, betas, history."""
+def pcg(K, f, M, rtol=1e-10, maxit=1000, x0=None):
+    """Preconditioned CG from x0 (default 0); stops when ||f - K x|| / ||f||
+    <= rtol (recursive residual).  Returns x, iterations, alphas, betas,
+    history."""
     f = np.asarray(f, dtype=np.float64)
-    x = np.zeros_like(f)
-    r = f.copy()
+    x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64)
+    r = f - K @ x if x0 is not None else f.copy()
     nf = np.linalg.norm(f)
     if nf == 0:
         return x, 0, [], [], [0.0]
+    if np.linalg.norm(r) <= rtol * nf:
+        return x, 0, [], [], [np.linalg.norm(r) / nf]
     z = M(r)
     p = z.copy()
     rz = r @ z
@@ -206,8 +209,28 @@ def direct_solve(prob, rhs=None, Ke=None):
     return lu.solve(np.asarray(rhs, dtype=np.float64))
 
 
-def solve_problem(prob, rtol=1e-10, maxit=1000, adaptive=True, H=None, rhs=None, **kw):
-    """Set up the hierarchy and run PCG for every right-hand-side column."""
+def interior_solution(H, f):
+    """x = [K_II^-1 f_I; 0] on level 1: every subdomain's interior problem
+    solved with the right-hand side's interior values, zero on the interface.
+    f - K x is then zero on the interiors, i.e. the residual of a discrete
+    harmonic correction problem (the splitting U = U_I + W^ of Section 2), so
+    PCG from this x0 runs on the interface problem of the Schur complement,
+    which BDDC preconditions (Section 5)."""
+    L = H.levels[0]
+    x = np.zeros_like(np.asarray(f, dtype=np.float64))
+    for s in range(L.inp.n_sub):
+        nI = L.n_I[s]
+        if nI:
+            I = L.sub_dofs[s][:nI]
+            x[I] = sla.cho_solve(L.KII_chol[s], f[I])
+    return x
+
+
+def solve_problem(prob, rtol=1e-10, maxit=1000, adaptive=True, H=None, rhs=None,
+                  start="zero", **kw):
+    """Set up the hierarchy and run PCG for every right-hand-side column, from
+    x0 = 0 (start="zero") or from the level-1 interior solution
+    (start="interior", see interior_solution)."""
     if H is None:
         H = setup_hierarchy(prob, adaptive=adaptive, **kw)
     K = H.levels[0].Kglob
@@ -216,7 +239,8 @@ def solve_problem(prob, rtol=1e-10, maxit=1000, adaptive=True, H=None, rhs=None,
     X = np.zeros_like(F)
     its, conds = [], []
     for j in range(F.shape[1]):
-        x, it, al, be, _ = pcg(K, F[:, j], lambda v: bddc_apply(H, v), rtol, maxit)
+        x0 = interior_solution(H, F[:, j]) if start == "interior" else None
+        x, it, al, be, _ = pcg(K, F[:, j], lambda v: bddc_apply(H, v), rtol, maxit, x0=x0)
         X[:, j] = x
         its.append(it)
         conds.append(lanczos_cond(al, be)[0])

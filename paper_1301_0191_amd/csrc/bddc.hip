@@ -84,7 +84,8 @@ __global__ void k_iface_res(int nG, const int* gdof, const int* inc_ptr, const i
   const double d = delta[k];
   for (int c = 0; c < nrhs; ++c) {
     double v = r[j + c * ldr];
-    for (int q = inc_ptr[j]; q < inc_ptr[j + 1]; ++q) v += y[g2y[inc_pos[q]] + c * ldy];
+    if (y)
+      for (int q = inc_ptr[j]; q < inc_ptr[j + 1]; ++q) v += y[g2y[inc_pos[q]] + c * ldy];
     out[k + c * ldo] = d * v;
   }
 }
@@ -340,7 +341,8 @@ __global__ void k_pcg_xr(int n, int nrhs, const double* rz, const double* pq, co
                          int it, int maxit) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
-  const double a = active[c] ? rz[c] / pq[c] : 0.0;
+  // a zero direction (a residual that is exactly zero) takes no step
+  const double a = active[c] && pq[c] != 0.0 ? rz[c] / pq[c] : 0.0;
   if (i == 0 && active[c]) ahist[it + (size_t)c * maxit] = a;
   if (i >= n) return;
   const size_t k = i + (size_t)c * n;
@@ -364,7 +366,7 @@ __global__ void k_pcg_beta(int nrhs, const double* rz_new, double* rz, double* b
   if (c >= nrhs) return;
   const bool restart = repl && repl[c];
   if (restart) repl[c] = 0;
-  const double b = active[c] && !restart ? rz_new[c] / rz[c] : 0.0;
+  const double b = active[c] && !restart && rz[c] != 0.0 ? rz_new[c] / rz[c] : 0.0;
   beta[c] = b;
   if (active[c]) {
     bhist[it + (size_t)c * maxit] = b;
@@ -673,6 +675,43 @@ void launch_move(int n, const int64_t* sidx, const double* src, int64_t lds, con
                  double* dst, int64_t ldd, int nrhs, hipStream_t st) {
   if (n == 0) return;
   k_move<<<ceil_div(n, 256), 256, 0, st>>>(n, sidx, src, lds, didx, dst, ldd, nrhs);
+  AMB_LAUNCH_CHECK();
+}
+
+// dst[idx[k], r] = 0 for every column (mask null) or the columns with mask[r].
+__global__ void k_zero_rows(int n, const int64_t* idx, double* dst, int64_t ldd, int nrhs,
+                            const int* mask) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t b = idx[k];
+  for (int r = 0; r < nrhs; ++r)
+    if (!mask || mask[r]) dst[b + r * ldd] = 0.0;
+}
+
+void launch_zero_rows(int n, const int64_t* idx, double* dst, int64_t ldd, int nrhs,
+                      const int* mask, hipStream_t st) {
+  if (n == 0) return;
+  k_zero_rows<<<ceil_div(n, 256), 256, 0, st>>>(n, idx, dst, ldd, nrhs, mask);
+  AMB_LAUNCH_CHECK();
+}
+
+// dst[didx[k], r] += src[sidx[k], r] for the columns r with mask[r] != 0.
+__global__ void k_move_add_masked(int n, const int64_t* sidx, const double* src, int64_t lds,
+                                  const int64_t* didx, double* dst, int64_t ldd, int nrhs,
+                                  const int* mask) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = sidx[k], b = didx[k];
+  for (int r = 0; r < nrhs; ++r)
+    if (mask[r]) dst[b + r * ldd] += src[a + r * lds];
+}
+
+void launch_move_add_masked(int n, const int64_t* sidx, const double* src, int64_t lds,
+                            const int64_t* didx, double* dst, int64_t ldd, int nrhs,
+                            const int* mask, hipStream_t st) {
+  if (n == 0) return;
+  k_move_add_masked<<<ceil_div(n, 256), 256, 0, st>>>(n, sidx, src, lds, didx, dst, ldd, nrhs,
+                                                      mask);
   AMB_LAUNCH_CHECK();
 }
 

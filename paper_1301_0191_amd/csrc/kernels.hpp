@@ -50,6 +50,7 @@ void launch_scatter(int n, const int64_t* idx, const double* src, int64_t lds, d
 void launch_weights(int nG, const int* gdof, const int* inc_ptr, const int* inc_pos,
                     const double* diag, double* delta, hipStream_t st);
 // r_B restricted and weighted: out[k] = delta[k] * (r[gdof[k]] + sum_{copies} y[g2y[c]])
+// (y may be null: a residual that is zero on the interiors needs no correction)
 void launch_interface_residual(int nG, const int* gdof, const int* inc_ptr, const int* inc_pos,
                                const int64_t* g2y, const double* delta, const double* r,
                                int64_t ldr, const double* y, int64_t ldy, double* out,
@@ -110,6 +111,13 @@ void launch_pcg_true(int nrhs, const double* tt, const double* ff, double rtol2,
 void launch_fill(double* p, size_t n, double v, hipStream_t st);
 void launch_move(int n, const int64_t* sidx, const double* src, int64_t lds, const int64_t* didx,
                  double* dst, int64_t ldd, int nrhs, hipStream_t st);
+// dst[idx[k], r] = 0 for every column (mask null) or the columns with mask[r] != 0
+void launch_zero_rows(int n, const int64_t* idx, double* dst, int64_t ldd, int nrhs,
+                      const int* mask, hipStream_t st);
+// dst[didx[k], r] += src[sidx[k], r] for the columns with mask[r] != 0
+void launch_move_add_masked(int n, const int64_t* sidx, const double* src, int64_t lds,
+                            const int64_t* didx, double* dst, int64_t ldd, int nrhs,
+                            const int* mask, hipStream_t st);
 void launch_rigid_level1(int n_nodes, int dof, const double* coords, const int* free_of_full,
                          int ndof, double* rigid, hipStream_t st);
 void launch_coarse_rigid(int n2, int nrb, const int* sub_of, const int* row_of, const int64_t* c_off,

@@ -263,11 +263,16 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
   }
   if (c.opt.precision >= 1) {
     // Alg. 1's dense operators are only read by the preconditioner: keep them
-    // in FP32 (the FP64 blocks stay for the Schur complements and set-up)
-    L.g1.pack_a_f32(L.g1_32, st);
+    // in FP32 (the FP64 blocks stay for the Schur complements and set-up).
+    // On level 1 the PCG iterates in the discrete harmonic space, which the
+    // interior solve of x0 (g1) and the interior post-correction (g4) must
+    // keep to FP64 rounding: a residual component on the interiors is never
+    // corrected there, so those two stay FP64.
+    const bool level1 = &L == c.L[0].get();
+    if (!level1) L.g1.pack_a_f32(L.g1_32, st);
     L.g2.pack_a_f32(L.g2_32, st);
     L.g3.pack_a_f32(L.g3_32, st);
-    L.g4.pack_a_f32(L.g4_32, st);
+    if (!level1) L.g4.pack_a_f32(L.g4_32, st);
   }
   L.g1.finalize(st);
   L.g2.finalize(st);
@@ -1112,16 +1117,22 @@ void ensure_workspace(ambddc_ctx& c, int nrhs) {
   }
 }
 
-// Alg. 1 on level li: r (ld ldr) -> u (ld ldu)
+// Alg. 1 on level li: r (ld ldr) -> u (ld ldu).  harmonic: r is zero on the
+// level's interior DOFs (every residual of the PCG below, which starts from
+// the interior solution), so the interior pre-correction u_I and the part of
+// the post-correction it feeds are exactly zero and are not computed.
 void apply_level(ambddc_ctx& c, int li, const double* r, int64_t ldr, double* u, int64_t ldu,
-                 int nrhs) {
+                 int nrhs, bool harmonic = false) {
   hipStream_t st = c.st;
   Level& L = *c.L[li];
   // interior pre-correction and updated residual on the interface
-  launch_gather(int(L.nI_tot), L.Imap.p, r, ldr, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
-  L.g1.run(1.0, 0.0, nrhs, st);
+  if (!harmonic) {
+    launch_gather(int(L.nI_tot), L.Imap.p, r, ldr, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
+    L.g1.run(1.0, 0.0, nrhs, st);
+  }
   launch_interface_residual(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.g2y1.p, L.delta.p,
-                            r, ldr, L.w_y1.p, L.y1_tot, L.w_rBs.p, L.nG_tot, nrhs, st);
+                            r, ldr, harmonic ? nullptr : L.w_y1.p, L.y1_tot, L.w_rBs.p, L.nG_tot,
+                            nrhs, st);
   // substructure corrections and coarse right-hand side
   L.g2.run(1.0, 0.0, nrhs, st);
   if (L.ncoarse > 0) {
@@ -1135,8 +1146,32 @@ void apply_level(ambddc_ctx& c, int li, const double* r, int64_t ldr, double* u,
   // averaging, interior post-correction, combination
   launch_average(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.g2y2.p, L.delta.p, L.w_y2.p,
                  L.y2_tot, L.w_uBs.p, L.nG_tot, u, ldu, nrhs, st);
-  L.g4.run(1.0, -1.0, nrhs, st);
+  L.g4.run(1.0, harmonic ? 0.0 : -1.0, nrhs, st);
   launch_move(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, u, ldu, nrhs, st);
+}
+
+// x = [K_II^{-1} f_I; 0] on level 0 (every subdomain's interior solve, the
+// rows of y1 that the pre-correction writes): f - K x is zero on the
+// interiors up to rounding.
+void interior_solve(ambddc_ctx& c, const double* f, double* x, int nrhs) {
+  hipStream_t st = c.st;
+  Level& L = *c.L[0];
+  const int64_t n = L.ndof;
+  launch_fill(x, size_t(n) * nrhs, 0.0, st);
+  launch_gather(int(L.nI_tot), L.Imap.p, f, n, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
+  L.g1.run(-1.0, 0.0, nrhs, st);
+  launch_move(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, x, n, nrhs, st);
+}
+
+// x_I += K_II^{-1} r_I on level 0 for the columns with mask != 0.
+void interior_correct(ambddc_ctx& c, const double* r, double* x, int nrhs, const int* mask) {
+  hipStream_t st = c.st;
+  Level& L = *c.L[0];
+  const int64_t n = L.ndof;
+  launch_gather(int(L.nI_tot), L.Imap.p, r, n, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
+  L.g1.run(-1.0, 0.0, nrhs, st);
+  launch_move_add_masked(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, x, n, nrhs, mask,
+                         st);
 }
 
 void next_level(ambddc_ctx& c, int li) {
@@ -1302,7 +1337,7 @@ PcgWork pcg_work_carve(double* d, int* ip, int64_t n, int nrhs, int ldh) {
   return w;
 }
 
-// PCG (x0 = 0) with Alg. 1 as preconditioner, columns in lockstep, flags on
+// PCG (x0 = [K_II^{-1} f_I; 0]) with Alg. 1 as preconditioner, columns in lockstep, flags on
 // the device; the host reads four counters per iteration.  A column whose
 // recursive residual meets rtol is checked against its recomputed true
 // residual f - K x: it stops if that meets rtol too; otherwise the true
@@ -1330,29 +1365,47 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
     AMB_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
     AMB_HIP(hipStreamSynchronize(st));
   };
-  launch_fill(x, nn, 0.0, st);
-  launch_copy(w.r, f, nn, st);
+  // x0 = the interior solution, so that every residual of the iteration is
+  // zero on the level-1 interiors (discrete harmonic iterates: PCG on the
+  // interface problem of the Schur complement, which is the problem the
+  // BDDC preconditioner is built for)
+  // The recursive residual keeps its interior part exactly zero (K p of a
+  // harmonic p is zero there in exact arithmetic; its rounding, about eps
+  // kappa(K_II), is dropped): it is the interface residual.  The true
+  // residual, interiors included, is what stops a column.
+  Level& L1 = *c.L[0];
+  interior_solve(c, f, x, nrhs);
+  launch_spmv(c.csr, c.csr_vals.p, x, w.r, nrhs, st);
+  launch_sub(nn, f, w.r, w.r, st);
+  launch_zero_rows(int(L1.nI_tot), L1.Imap.p, w.r, n, nrhs, nullptr, st);
   launch_dot_cols(n, nrhs, f, f, w.part, ff, st);
   launch_pcg_init_flags(nrhs, ff, w.act, w.nal, w.repl, w.stall, w.tprev, w.cnt, st);
   // algorithmic work of one preconditioner application (timing only)
   double apf = 0.0, apb = 0.0;
   const bool kt = timed && c.kt.any();
   if (kt) {
-    double ent = 0.0;
-    for (auto& lp : c.L) {
-      const Level& Lv = *lp;
+    // level 1 reads K_II^{-1} K_IG (FP64 in every precision), Z and Psi (no
+    // pre-correction: harmonic residuals); deeper levels also K_II^{-1} and
+    // K_GI K_II^{-1}
+    const double esz = c.opt.precision >= 1 ? 4.0 : 8.0;
+    double ent = 0.0, byt = 0.0;
+    for (size_t li = 0; li < c.L.size(); ++li) {
+      const Level& Lv = *c.L[li];
       for (int s = 0; s < Lv.nsub; ++s) {
         const double nI = Lv.nI[s], nG = Lv.nG[s], ncs = Lv.nc[s];
-        ent += nI * nI + 2.0 * nI * nG + nG * nG + 2.0 * nG * ncs;
+        const double pre = li == 0 ? 0.0 : nI * nI + nI * nG;
+        const double post = nI * nG, sub = nG * nG + 2.0 * nG * ncs;
+        ent += pre + post + sub;
+        byt += esz * (pre + sub) + (li == 0 ? 8.0 : esz) * post;
       }
     }
     const double top = double(c.top.n) * c.top.n;   // the coarsest inverse stays FP64
     apf = 2.0 * (ent + top) * nrhs;
-    apb = (c.opt.precision >= 1 ? 4.0 : 8.0) * ent + 8.0 * top + 48.0 * double(n) * nrhs;
+    apb = byt + 8.0 * top + 48.0 * double(n) * nrhs;
   }
   auto precondition = [&]() {
     if (kt) c.kt.begin("bddc_apply", st);
-    apply_level(c, 0, w.r, n, w.z, n, nrhs);
+    apply_level(c, 0, w.r, n, w.z, n, nrhs, true);
     if (kt) c.kt.end("bddc_apply", st, apf, apb);
   };
   precondition();
@@ -1363,6 +1416,7 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
   int repl = 0;
   for (int it = 0; it < maxit && nact > 0; ++it) {
     launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, st);
+    launch_zero_rows(int(L1.nI_tot), L1.Imap.p, w.q, n, nrhs, nullptr, st);
     launch_dot_cols(n, nrhs, w.p, w.q, w.part, pq, st);
     launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, it, w.ldh, st);
     launch_dot_cols(n, nrhs, w.r, w.r, w.part, rr, st);
@@ -1372,11 +1426,19 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
       // The recursive residual drifts from f - K x by rounding (most on
       // ill-conditioned problems): recompute the true residual (q is free
       // here) and stop only the columns it confirms.
+      // The iteration never corrects the interiors (harmonic residuals), so
+      // the rounding of the interior updates accumulates there (about eps
+      // kappa(K_II) per step): the checked columns first re-solve their
+      // interiors from the true residual, x_I += K_II^{-1} (f - K x)_I.
+      launch_spmv(c.csr, c.csr_vals.p, x, w.q, nrhs, st);
+      launch_sub(nn, f, w.q, w.q, st);
+      interior_correct(c, w.q, x, nrhs, w.meets);
       launch_spmv(c.csr, c.csr_vals.p, x, w.q, nrhs, st);
       launch_sub(nn, f, w.q, w.q, st);
       launch_dot_cols(n, nrhs, w.q, w.q, w.part, rr, st);
       launch_pcg_true(nrhs, rr, ff, rtol2, w.act, w.meets, w.repl, w.stall, w.tprev, w.cnt, st);
       launch_copy_cols(n, nrhs, w.q, w.r, w.repl, st);
+      launch_zero_rows(int(L1.nI_tot), L1.Imap.p, w.r, n, nrhs, w.repl, st);
       read_cnt();
       nact = hc[1];
       repl += hc[2];

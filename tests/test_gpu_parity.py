@@ -9,8 +9,8 @@ Tolerances (FP64 path):
   constraint spans: sine of the largest principal angle <= 1e-6, or, where
   the selection cuts a cluster of eigenvalues, the rows inside the span of
   the whole cluster (gpu_common.check_pair);
-* solution: ||x - x_direct|| / ||x_direct|| <= 1e-10 (the north-star
-  target) after a solve to rtol 1e-10 on the true residual.  Where FP64
+* solution: ||x - x_direct|| / ||x_direct|| <= 1e-10 (the target
+  accuracy) after a solve to rtol 1e-10 on the true residual.  Where FP64
   cannot reach that residual (C1: the oracle's own direct solution has a
   true residual of 7e-9, its 1e6 channels make K ill-conditioned) the solve
   stops as stalled and its true residual must be within 2x of that floor.
@@ -78,7 +78,7 @@ def test_nonadaptive_pcg(case):
     prob = TINY[case]()
     h = gpu_handle(prob, tau=0.0)
     X, its, cond = gpu_solve(h, prob.rhs, rtol=1e-10)
-    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, adaptive=False)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, adaptive=False, start="interior")
     xd = O.direct_solve(prob)
     err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
     log("  its", its, "oracle", ito, "err", err)
@@ -180,7 +180,7 @@ def test_constraint_variants(variant):
         Kc = h.coarse_element(0, s)
         assert np.linalg.norm(Kc - L.Kc[s]) <= 1e-8 * np.linalg.norm(L.Kc[s]), s
     its, cond = check_solution(h, prob, case)
-    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, H=H)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, H=H, start="interior")
     log("  oracle its", ito, "cond", co, "omega", st["omega_tilde"])
     if not h.stats()["pcg_stalled"]:
         assert abs(its[0] - ito[0]) <= 2
@@ -222,7 +222,7 @@ def test_three_level_parity(case):
         assert st["n_adaptive"][lv] == H.stats["n_adaptive"][lv], lv
         check_pairs(h, prob, H, level=lv)
     its, cond = check_solution(h, prob, "three-level-" + case)
-    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, H=H)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, H=H, start="interior")
     log("  oracle its", ito, "cond", co)
     assert abs(its[0] - ito[0]) <= max(2, 0.05 * ito[0])
     assert cond[0] == pytest.approx(co[0], rel=1e-3)

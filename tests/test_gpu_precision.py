@@ -49,7 +49,7 @@ def test_fp32_preconditioner_parity(case, precision):
     F = torch.from_numpy(np.ascontiguousarray(prob.rhs.reshape(prob.rhs.shape[0], -1).T)).to("cuda:0")
     res = h.solve(F, rtol=1e-10, raise_on_noconv=False)
     X = res.x.cpu().numpy().T
-    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, H=H)
+    Xo, ito, co, _ = O.solve_problem(prob, rtol=1e-10, H=H, start="interior")
     xd = O.direct_solve(prob).reshape(X.shape)
     err = np.linalg.norm(X - xd) / np.linalg.norm(xd)
     log("  its", res.iterations, "oracle", ito, "cond", res.cond, co, "err", err,

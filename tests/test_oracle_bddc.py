@@ -14,6 +14,13 @@
 * PCG with BDDC: solution equals the direct solve, lambda_min(M K) >= 1,
   one subdomain gives the exact inverse, the Lanczos estimate agrees with
   the dense spectrum of M K.
+* PCG from the level-1 interior solution x0 = [K_II^-1 f_I; 0]: the residual
+  is zero on the interiors, Alg. 1 maps it to a discrete harmonic correction
+  (K z zero on the interiors, Section 2) without a pre-correction, every
+  PCG residual stays zero there, the solution equals the direct solve, the
+  iteration count is that of x0 = 0 within two, the Lanczos estimate is a
+  lower bound of the dense spectrum's condition number within 1%, and one
+  subdomain needs no iteration (x0 is the solution).
 """
 import numpy as np
 import pytest
@@ -22,8 +29,8 @@ import scipy.linalg as sla
 import workloads as W
 from oracle import fem
 from oracle.adaptive import enrich_level, pair_eigenproblem, pair_operators, pair_rigid
-from oracle.bddc import (bddc_apply, direct_solve, lanczos_cond, pcg, setup_hierarchy,
-                         solve_problem)
+from oracle.bddc import (bddc_apply, direct_solve, interior_solution, lanczos_cond, pcg,
+                         setup_hierarchy, solve_problem)
 from oracle.substructure import build_level, level1_input, coarse_basis
 
 
@@ -209,6 +216,76 @@ def test_lanczos_estimate_matches_dense_spectrum():
     cond, lmin, lmax = lanczos_cond(al, be)
     assert lmin >= ev[0] * (1 - 1e-8) and lmax <= ev[-1] * (1 + 1e-8)
     assert cond == pytest.approx(ev[-1] / ev[0], rel=1e-3)
+
+
+def _interior_mask(H):
+    L = H.levels[0]
+    m = np.zeros(L.inp.n_dof, dtype=bool)
+    for s in range(L.inp.n_sub):
+        m[L.sub_dofs[s][:L.n_I[s]]] = True
+    return m
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.tiny_poisson(shape=(8, 8, 8), subs=(2, 2, 2), seed=9),
+    lambda: W.tiny_elasticity(shape=(4, 4, 4), subs=(2, 2, 2), seed=10),
+    lambda: W.make_problem((8, 8, 8), (4, 4, 4), group=(2, 2, 2), coeff="lognormal",
+                           seed=11, rhs="normal"),
+])
+def test_interior_start_keeps_residuals_harmonic(maker):
+    prob = maker()
+    H = setup_hierarchy(prob)
+    K = H.levels[0].Kglob
+    f = prob.rhs.reshape(prob.rhs.shape[0], -1)[:, 0]
+    nf = np.linalg.norm(f)
+    mI = _interior_mask(H)
+    assert mI.any() and not mI.all()
+    x = interior_solution(H, f)
+    r = f - K @ x
+    assert np.linalg.norm(r[mI]) <= 1e-12 * nf
+    # Alg. 1 of a residual that is zero on the interiors: no pre-correction,
+    # a discrete harmonic result
+    z = bddc_apply(H, r)
+    rc = r.copy()
+    rc[mI] = 0.0
+    np.testing.assert_allclose(bddc_apply(H, rc), z, rtol=0, atol=1e-12 * np.linalg.norm(z))
+    Kz = K @ z
+    assert np.linalg.norm(Kz[mI]) <= 1e-10 * np.linalg.norm(Kz)
+    # CG recurrences (written out): the residuals stay zero on the interiors
+    p = z.copy()
+    rz = r @ z
+    for _ in range(8):
+        q = K @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        assert np.linalg.norm(r[mI]) <= 1e-10 * max(np.linalg.norm(r), 1e-300)
+        z = bddc_apply(H, r)
+        rzn = r @ z
+        p = z + (rzn / rz) * p
+        rz = rzn
+    # the whole solve from this start
+    X, its, _, _ = solve_problem(prob, rtol=1e-12, H=H, start="interior")
+    xd = direct_solve(prob)
+    assert np.linalg.norm(X - xd) / np.linalg.norm(xd) < 1e-9
+    _, its0, _, _ = solve_problem(prob, rtol=1e-12, H=H)
+    assert abs(its[0] - its0[0]) <= 2
+
+
+def test_interior_start_lanczos_and_single_subdomain():
+    prob = W.tiny_poisson(shape=(6, 6, 6), subs=(2, 2, 2), seed=14, coeff="blocks")
+    H = setup_hierarchy(prob, adaptive=False)
+    K, M, ev = dense_preconditioned(H)
+    f = np.random.default_rng(0).standard_normal(K.shape[0])
+    x0 = interior_solution(H, f)
+    x, it, al, be, _ = pcg(H.levels[0].Kglob, f, lambda v: bddc_apply(H, v), 1e-14, 500, x0=x0)
+    cond, lmin, lmax = lanczos_cond(al, be)
+    assert lmin >= ev[0] * (1 - 1e-8) and lmax <= ev[-1] * (1 + 1e-8)
+    assert ev[-1] / ev[0] * (1 - 1e-2) <= cond <= ev[-1] / ev[0] * (1 + 1e-8)
+    one = W.make_problem((4, 4, 4), (1, 1, 1), coeff="lognormal", seed=13)
+    X, its, _, _ = solve_problem(one, rtol=1e-12, start="interior")
+    assert its[0] == 0
+    np.testing.assert_allclose(X, direct_solve(one), rtol=1e-10)
 
 
 def _explicit_alg1(H, dtype):
