@@ -241,24 +241,49 @@ void launch_diag_mean(int nsub, const int64_t* off, const int* ld, const int* n0
 
 __global__ void k_extract_kc(const int64_t* naug_off, const int* naug_ld, const int* nG,
                              const int* nc, const int64_t* kc_off, const double* rho,
-                             const double* naug, double* kc) {
+                             const int* nrho, const double* naug, double* kc) {
   const int s = blockIdx.y;
   const int m = nc[s];
+  const int mr = nrho ? nrho[s] : m;
   const int base = nG[s] + m + nG[s];
   const double* a = naug + naug_off[s];
   const int l = naug_ld[s];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m * m; i += gridDim.x * blockDim.x) {
     const int r = i % m, c = i / m;
-    kc[kc_off[s] + i] = a[(base + r) + (size_t)(base + c) * l] - (r == c ? rho[s] : 0.0);
+    kc[kc_off[s] + i] = a[(base + r) + (size_t)(base + c) * l] - (r == c && r < mr ? rho[s] : 0.0);
   }
 }
 
 void launch_extract_kc(int nsub, const int64_t* naug_off, const int* naug_ld, const int* nG,
-                       const int* nc, const int64_t* kc_off, const double* rho, const double* naug,
-                       double* kc, hipStream_t st) {
+                       const int* nc, const int64_t* kc_off, const double* rho, const int* nrho,
+                       const double* naug, double* kc, hipStream_t st) {
   if (nsub == 0) return;
   dim3 g(4, nsub);
-  k_extract_kc<<<g, 256, 0, st>>>(naug_off, naug_ld, nG, nc, kc_off, rho, naug, kc);
+  k_extract_kc<<<g, 256, 0, st>>>(naug_off, naug_ld, nG, nc, kc_off, rho, nrho, naug, kc);
+  AMB_LAUNCH_CHECK();
+}
+
+// Border of the bordered inverse: T[0:nl, nl:nl+k] = -W, T[nl:, 0:nl] = -W^T,
+// T[nl:, nl:] = -Tsc (one descriptor per matrix, blockIdx.y).
+__global__ void k_border_fill(const BorderDesc* d) {
+  const BorderDesc g = d[blockIdx.y];
+  const int nl = g.nl, k = g.k;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl * k; i += gridDim.x * blockDim.x) {
+    const int r = i % nl, j = i / nl;
+    const double v = -g.W[r + (size_t)j * g.ldw];
+    g.T[r + (size_t)(nl + j) * g.ldt] = v;
+    g.T[(nl + j) + (size_t)r * g.ldt] = v;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k * k; i += gridDim.x * blockDim.x) {
+    const int r = i % k, j = i / k;
+    g.T[(nl + r) + (size_t)(nl + j) * g.ldt] = -g.Tsc[r + (size_t)j * g.lds];
+  }
+}
+
+void launch_border_fill(const BorderDesc* d, int n, hipStream_t st) {
+  if (n == 0) return;
+  dim3 g(16, n);
+  k_border_fill<<<g, 256, 0, st>>>(d);
   AMB_LAUNCH_CHECK();
 }
 

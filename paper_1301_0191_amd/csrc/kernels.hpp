@@ -81,10 +81,20 @@ void launch_scale_sqrt_sub(int nsub, const int64_t* off, const int64_t* cnt, con
                            const double* src, double* dst, hipStream_t st);
 void launch_diag_mean(int nsub, const int64_t* off, const int* ld, const int* n0, const int* n,
                       const double* A, double* out, hipStream_t st);
-// K_c^s = trailing(n_G: , n_G:) - rho I  copied compact
+// K_c^s = trailing(n_G: , n_G:) - rho E  copied compact, E the identity on
+// the first nrho[s] constraint rows (all rows when nrho is null)
 void launch_extract_kc(int nsub, const int64_t* naug_off, const int* naug_ld, const int* nG,
-                       const int* nc, const int64_t* kc_off, const double* rho, const double* naug,
-                       double* kc, hipStream_t st);
+                       const int* nc, const int64_t* kc_off, const double* rho, const int* nrho,
+                       const double* naug, double* kc, hipStream_t st);
+// The border of a bordered symmetric inverse T (ld ldt) of order nl + k:
+// T[0:nl, nl:] = -W, T[nl:, 0:nl] = -W^T, T[nl:, nl:] = -Tsc.
+struct BorderDesc {
+  double* T;
+  const double* W;
+  const double* Tsc;
+  int ldt, ldw, lds, nl, k;
+};
+void launch_border_fill(const BorderDesc* d, int n, hipStream_t st);
 void launch_copy_block(int nsub, const int64_t* src_off, const int* src_ld, const int* r0,
                        const int* rows, const int* cols, const int64_t* dst_off, const int* dst_ld,
                        const double* src, double* dst, hipStream_t st);

@@ -453,8 +453,8 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
 }
 
 // constraint matrices, constrained Neumann operators, coarse basis (Section 5)
-void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
-  hipStream_t st = c.st;
+// C^s: initial rows 1 or 1/m, adaptive rows from the face constraint rows
+void fill_constraints(Level& L, hipStream_t st) {
   L.C.zero(st);
   launch_fill_values(int(L.cfill_pos.n), L.cfill_pos.p, L.cfill_val.p, L.C.p, st);
   if (L.cadapt_pos.n) {
@@ -463,6 +463,11 @@ void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
     launch_gather(int(L.cadapt_pos.n), L.cadapt_src.p, L.fc.p, 0, tmp.p, 0, 1, 1.0, st);
     launch_fill_values(int(L.cadapt_pos.n), L.cadapt_pos.p, tmp.p, L.C.p, st);
   }
+}
+
+void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
+  hipStream_t st = c.st;
+  fill_constraints(L, st);
   L.naug.zero(st);
   launch_neumann_fill(L.neu.p, L.nsub, L.neu_cols, st);
   launch_scale_sqrt_sub(L.nsub, L.d_c_off.p, L.d_c_cnt.p, L.rho.p, L.C.p, L.Cs.p, st);
@@ -471,7 +476,131 @@ void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
   check_ldlt(L.ldl_naug, st, "constrained Neumann factorisation", li);
   L.sym_naug.run(st);
   launch_extract_kc(L.nsub, L.d_naug_off.p, L.d_naugN.p, L.d_nG.p, L.d_nc.p, L.d_kc_off.p, L.rho.p,
-                    L.naug.p, L.kc.p, st);
+                    nullptr, L.naug.p, L.kc.p, st);
+}
+
+// The constrained Neumann inverses of a level before its adaptive rows are
+// added (the trailing blocks T = -X^{-1} of the augmented matrices), kept to
+// border them with the new rows.
+struct NeumannPrev {
+  DBuf<double> naug;
+  std::vector<int> nc, nl;
+  std::vector<int64_t> naug_off;
+};
+
+NeumannPrev keep_neumann(Level& L) {
+  NeumannPrev o;
+  o.naug = std::move(L.naug);
+  o.nc = L.nc;
+  o.nl = L.nl;
+  o.naug_off = L.naug_off;
+  return o;
+}
+
+// Constrained Neumann inverses after adaptive rows C_a (k per subdomain,
+// appended after the existing rows) are added, by bordering the previous
+// ones instead of factorising again.  With X the previous saddle-point
+// matrix [[S + rho C^T C, C^T], [C, 0]] and b = [C_a^T; 0], the new matrix
+// is [[X, b], [b^T, 0]]; with Y = X^{-1} b and the SPD k x k matrix
+// S_c = b^T Y, its inverse is [[X^{-1} - Y S_c^{-1} Y^T, Y S_c^{-1}],
+// [S_c^{-1} Y^T, -S_c^{-1}]].  The rho term then acts on the previous rows
+// only: Z and Psi (the displacement rows of the inverse) do not depend on
+// it, and K_c takes the rho correction on those rows only.  Work per
+// subdomain about 2 n_l^2 k instead of a factorisation of order 2 n_l.
+void neumann_bordered(ambddc_ctx& c, Level& L, int li, NeumannPrev& old) {
+  hipStream_t st = c.st;
+  const int ns = L.nsub;
+  fill_constraints(L, st);
+  std::vector<int64_t> src_off(ns), dst_off(ns), yoff(ns + 1, 0), aoff(ns + 1, 0);
+  std::vector<int> src_ld(ns), r0(ns), rows(ns), dst_ld(ns);
+  for (int s = 0; s < ns; ++s) {
+    const int k = L.nc[s] - old.nc[s], nl = old.nl[s], nl2 = L.nl[s];
+    if (k < 0 || nl2 != nl + k) throw Error(AMBDDC_E_INVALID_ARG, "constraint rows removed");
+    src_off[s] = old.naug_off[s];
+    src_ld[s] = 2 * nl;
+    r0[s] = nl;
+    rows[s] = nl;
+    dst_off[s] = L.naug_off[s] + nl2 + int64_t(nl2) * (2 * nl2);
+    dst_ld[s] = 2 * nl2;
+    yoff[s + 1] = yoff[s] + int64_t(nl) * k;
+    aoff[s + 1] = aoff[s] + int64_t(2 * k) * (2 * k);
+  }
+  {
+    DBuf<int64_t> so, dof;
+    DBuf<int> sl, rr, nr, dl;
+    so.upload(src_off, st);
+    dof.upload(dst_off, st);
+    sl.upload(src_ld, st);
+    rr.upload(r0, st);
+    nr.upload(rows, st);
+    dl.upload(dst_ld, st);
+    launch_copy_block(ns, so.p, sl.p, rr.p, nr.p, nr.p, dof.p, dl.p, old.naug.p, L.naug.p, st);
+  }
+  DBuf<double> Y, Wm, Sa;
+  Y.alloc(size_t(std::max<int64_t>(yoff[ns], 1)));
+  Wm.alloc(size_t(std::max<int64_t>(yoff[ns], 1)));
+  Sa.alloc(size_t(std::max<int64_t>(aoff[ns], 1)));
+  Sa.zero(st);
+  GemmOp gy, gs, gw, gt;
+  gy.tb = true;
+  gt.tb = true;
+  LdltOp lsc;
+  SymOp ssc;
+  std::vector<BorderDesc> bd;
+  std::vector<int64_t> ioff;
+  std::vector<int> ild, ik, izero;
+  for (int s = 0; s < ns; ++s) {
+    const int k = L.nc[s] - old.nc[s], nl = old.nl[s], nl2 = L.nl[s], nG = L.nG[s];
+    if (k == 0) continue;
+    const double* Told = old.naug.p + old.naug_off[s] + nl + int64_t(nl) * (2 * nl);
+    const double* Ca = L.C.p + L.c_off[s] + old.nc[s];
+    double* Ys = Y.p + yoff[s];
+    double* Ws = Wm.p + yoff[s];
+    double* Ss = Sa.p + aoff[s];
+    double* Tsc = Ss + k + int64_t(k) * (2 * k);
+    double* Tn = L.naug.p + dst_off[s];
+    gy.add(Told, 2 * nl, Ca, L.nc[s], Ys, nl, nl, k, nG);        // Y = -T[:, :nG] C_a^T
+    gs.add(Ca, L.nc[s], Ys, nl, Ss, 2 * k, k, k, nG);            // S_c = C_a Y[:nG]
+    lsc.add(Ss, 2 * k, 2 * k, k, k);                             // [[S_c, I], [I, 0]] -> -S_c^{-1}
+    ssc.add(Ss, 2 * k, k, k);
+    gw.add(Ys, nl, Tsc, 2 * k, Ws, nl, nl, k, k);                // W = -Y (-S_c^{-1})
+    gt.add(Ws, nl, Ys, nl, Tn, 2 * nl2, nl, nl, k);              // T += W Y^T
+    bd.push_back(BorderDesc{Tn, Ws, Tsc, 2 * nl2, nl, 2 * k, nl, k});
+    ioff.push_back(aoff[s]);
+    ild.push_back(2 * k);
+    ik.push_back(k);
+    izero.push_back(0);
+  }
+  if (!bd.empty()) {
+    gy.finalize(st);
+    gs.finalize(st);
+    gw.finalize(st);
+    gt.finalize(st);
+    lsc.finalize(st);
+    ssc.finalize(st);
+    DBuf<int64_t> io;
+    DBuf<int> il, ikk, iz;
+    DBuf<BorderDesc> db;
+    io.upload(ioff, st);
+    il.upload(ild, st);
+    ikk.upload(ik, st);
+    iz.upload(izero, st);
+    db.upload(bd, st);
+    gy.run(-1.0, 0.0, st);
+    gs.run(1.0, 0.0, st);
+    launch_aug_identity(int(bd.size()), io.p, il.p, ikk.p, iz.p, ikk.p, st, Sa.p);
+    lsc.run(st);
+    check_ldlt(lsc, st, "constrained Neumann border (new constraint rows)", li);
+    ssc.run(st);
+    gw.run(-1.0, 0.0, st);
+    gt.run(1.0, 1.0, st);
+    launch_border_fill(db.p, int(bd.size()), st);
+  }
+  DBuf<int> nrho;
+  nrho.upload(old.nc, st);
+  launch_extract_kc(ns, L.d_naug_off.p, L.d_naugN.p, L.d_nG.p, L.d_nc.p, L.d_kc_off.p, L.rho.p,
+                    nrho.p, L.naug.p, L.kc.p, st);
+  AMB_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace
@@ -1256,9 +1385,10 @@ void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
       AMB_HIP(hipStreamSynchronize(st));
       double td = now_s();
       tph[2] += td - tcc;
+      NeumannPrev prev = keep_neumann(L);
       add_adaptive_constraints(L.plan, L.pair_k);
       build_constraint_maps(c, L);
-      numeric_neumann(c, L, li);
+      neumann_bordered(c, L, li, prev);
       AMB_HIP(hipStreamSynchronize(st));
       tph[4] += now_s() - td;
     }
