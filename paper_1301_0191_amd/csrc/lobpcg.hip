@@ -60,6 +60,9 @@ void lp_random(const PairDev* P, int np, double* V, int m, uint64_t seed, hipStr
 // row's support in parallel, sums with DPP inside the group, and updates the
 // support, with no barrier.  The rigid-mode deflation needs whole columns and
 // starts after a barrier.
+constexpr int DEFL_RB = 6;     // rigid modes of a pair (3D elasticity)
+constexpr int DEFL_COLS = 6;   // columns per workgroup: ceil(m / PAIR_COL_GROUPS), m <= 21
+
 __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, const double* C,
                              const DRows dr, const double* rb, bool deflate, double* sm) {
   const int n = p.nGs + p.nGt;
@@ -92,6 +95,59 @@ __device__ void pair_project(const PairDev& p, double* v, int ldv, int ncol, con
     double* coef = sm;   // [nrb * ncol]
     const double* R = rb + p.rb_off;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    if (p.nrb <= DEFL_RB && ncol <= DEFL_COLS) {
+      // one pass over the rows: every thread accumulates all nrb x ncol
+      // products of its rows, so R and v are each read once per phase
+      double acc[DEFL_RB][DEFL_COLS];
+#pragma unroll
+      for (int r = 0; r < DEFL_RB; ++r)
+#pragma unroll
+        for (int c = 0; c < DEFL_COLS; ++c) acc[r][c] = 0.0;
+      for (int i = tid; i < n; i += nt) {
+        double vi[DEFL_COLS];
+#pragma unroll
+        for (int c = 0; c < DEFL_COLS; ++c) vi[c] = c < ncol ? v[i + (size_t)c * ldv] : 0.0;
+#pragma unroll
+        for (int r = 0; r < DEFL_RB; ++r) {
+          if (r >= p.nrb) break;
+          const double ri = R[i + (size_t)r * n];
+#pragma unroll
+          for (int c = 0; c < DEFL_COLS; ++c) acc[r][c] += ri * vi[c];
+        }
+      }
+      // wave sums, then the waves' partial sums in a fixed order
+      double* part = sm + DEFL_RB * DEFL_COLS;   // [nw][DEFL_RB * DEFL_COLS]
+#pragma unroll
+      for (int r = 0; r < DEFL_RB; ++r)
+#pragma unroll
+        for (int c = 0; c < DEFL_COLS; ++c) {
+          const double t = wave_sum(acc[r][c]);
+          if (lane == 0) part[wave * DEFL_RB * DEFL_COLS + r * DEFL_COLS + c] = t;
+        }
+      __syncthreads();
+      if (tid < DEFL_RB * DEFL_COLS) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += part[w * DEFL_RB * DEFL_COLS + tid];
+        coef[tid] = t;   // coef[r * DEFL_COLS + c]
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += nt) {
+        double corr[DEFL_COLS];
+#pragma unroll
+        for (int c = 0; c < DEFL_COLS; ++c) corr[c] = 0.0;
+#pragma unroll
+        for (int r = 0; r < DEFL_RB; ++r) {
+          if (r >= p.nrb) break;
+          const double ri = R[i + (size_t)r * n];
+#pragma unroll
+          for (int c = 0; c < DEFL_COLS; ++c) corr[c] += coef[r * DEFL_COLS + c] * ri;
+        }
+#pragma unroll
+        for (int c = 0; c < DEFL_COLS; ++c)
+          if (c < ncol) v[i + (size_t)c * ldv] -= corr[c];
+      }
+      return;
+    }
     for (int idx = wave; idx < p.nrb * ncol; idx += nw) {
       const int r = idx / ncol, c = idx % ncol;
       const double* vc = v + (size_t)c * ldv;
