@@ -709,6 +709,216 @@ int LdltOp::failed(hipStream_t st) {
 }
 
 // --------------------------------------------------------------------------
+// Right-side triangular solve X L = B (TrsmOp)
+// --------------------------------------------------------------------------
+
+// Step t, block column jb = nb - 1 - t of every active matrix:
+// B[:, jb] -= X[:, jb+1..] L[jb+1.., jb], one 64 x 64 MFMA tile per workgroup.
+__global__ __launch_bounds__(256) void k_trsm_update(const TrsmDesc* __restrict__ d,
+                                                     const int* __restrict__ act,
+                                                     const int* __restrict__ pre, int nact, int t) {
+  __shared__ TileSmem<2, 2> sm;
+  const int a = find_active(pre, nact, blockIdx.x);
+  const TrsmDesc g = d[act[a]];
+  const int l = blockIdx.x - pre[a];
+  constexpr int TB = TrsmOp::TB;
+  const int nb = (g.nI + TB - 1) / TB;
+  const int jb = nb - 1 - t;
+  const int c0 = jb * TB, w = min(TB, g.nI - c0), k0 = c0 + w;
+  double* B = g.A + g.nI;                       // rows nI.., column 0
+  mfma_tile<false, false, 2, 2>(B + (size_t)k0 * g.lda, g.lda, g.A + k0 + (size_t)c0 * g.lda,
+                                g.lda, B + (size_t)c0 * g.lda, g.lda, g.nG, w, g.nI - k0, l * 64, 0,
+                                -1.0, 1.0, -1, sm);
+}
+
+// Step t: every row x of B[:, jb] solves x L[jb, jb] = b (back substitution
+// over the block's columns); L's block in LDS, the row in registers.
+__global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__ d,
+                                                    const int* __restrict__ act,
+                                                    const int* __restrict__ pre, int nact, int t) {
+  constexpr int TB = TrsmOp::TB;
+  __shared__ double Ld[TB][TB + 1];
+  const int a = find_active(pre, nact, blockIdx.x);
+  const TrsmDesc g = d[act[a]];
+  const int chunk = blockIdx.x - pre[a];
+  const int nb = (g.nI + TB - 1) / TB;
+  const int jb = nb - 1 - t;
+  const int c0 = jb * TB, w = min(TB, g.nI - c0);
+  for (int i = threadIdx.x; i < TB * TB; i += 256) {
+    const int r = i % TB, c = i / TB;
+    Ld[r][c] = (r < w && c < w && r >= c) ? g.A[(c0 + r) + (size_t)(c0 + c) * g.lda] : 0.0;
+  }
+  __syncthreads();
+  const int row = chunk * 256 + threadIdx.x;
+  if (row >= g.nG) return;
+  double* b = g.A + g.nI + row + (size_t)c0 * g.lda;
+  double x[TB];
+#pragma unroll
+  for (int j = 0; j < TB; ++j) x[j] = j < w ? b[(size_t)j * g.lda] : 0.0;
+#pragma unroll
+  for (int k = TB - 1; k >= 0; --k) {
+    if (k < w) {
+      double v = x[k];
+#pragma unroll
+      for (int i = k + 1; i < TB; ++i) v -= x[i] * Ld[i][k];
+      x[k] = v / Ld[k][k];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TB; ++j)
+    if (j < w) b[(size_t)j * g.lda] = x[j];
+}
+
+void TrsmOp::finalize(hipStream_t st) {
+  steps.clear();
+  int maxb = 0;
+  for (const auto& g : h) maxb = std::max(maxb, ceil_div(g.nI, TB));
+  std::vector<int> a, up, sp;
+  for (int t = 0; t < maxb; ++t) {
+    Step f{t, int(a.size()), 0, 0, 0};
+    for (size_t i = 0; i < h.size(); ++i) {
+      const auto& g = h[i];
+      const int nb = ceil_div(g.nI, TB);
+      if (nb <= t) continue;
+      a.push_back(int(i));
+      up.push_back(f.upd_total);
+      sp.push_back(f.sol_total);
+      const int jb = nb - 1 - t;
+      const int k0 = std::min(g.nI, (jb + 1) * TB);
+      if (k0 < g.nI) f.upd_total += ceil_div(g.nG, 64);
+      f.sol_total += ceil_div(g.nG, 256);
+      ++f.nact;
+    }
+    steps.push_back(f);
+  }
+  d.upload(h, st);
+  act.upload(a, st);
+  upd_pre.upload(up, st);
+  sol_pre.upload(sp, st);
+}
+
+void TrsmOp::run(hipStream_t st) const {
+  for (const Step& f : steps) {
+    if (f.nact == 0) continue;
+    if (f.upd_total > 0)
+      k_trsm_update<<<f.upd_total, 256, 0, st>>>(d.p, act.p + f.off, upd_pre.p + f.off, f.nact,
+                                                 f.t);
+    k_trsm_solve<<<f.sol_total, 256, 0, st>>>(d.p, act.p + f.off, sol_pre.p + f.off, f.nact, f.t);
+  }
+  AMB_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
+// x <- K_II^{-1} x with the partial Cholesky factor (forward, then backward)
+// --------------------------------------------------------------------------
+
+constexpr int TRSV_THREADS = 1024;
+
+// One workgroup per matrix, all R right-hand sides together (L is read once
+// per pass).  Block q of 64 rows: the 16 waves take every 16th solved column
+// (lanes = the block's rows, eight columns in flight per wave) and meet in
+// LDS; wave 0 then solves the 64 x 64 diagonal block, one lane per row.
+template <int R>
+__global__ __launch_bounds__(TRSV_THREADS) void k_trsv_chol(const TrsvDesc* __restrict__ d) {
+  constexpr int B = 64, NW = TRSV_THREADS / 64, U = 8;
+  __shared__ double Ld[B][B + 1];
+  __shared__ double part[2][NW][B];   // one right-hand side at a time, double buffered
+  __shared__ double zb[R][B];
+  const TrsvDesc g = d[blockIdx.x];
+  double* x = g.x;
+  const int64_t ldx = g.ldx;
+  const int n = g.nI, lda = g.lda;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = (n + B - 1) / B;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q < nb; ++q) {
+      // forward: block q from the top, L[r0.., c] for the solved c < r0;
+      // backward: block q from the bottom, L^T[r0.., c] = L[c, r0..] (the
+      // upper triangle holds L^T) for the solved c >= r0 + w
+      const int jb = pass == 0 ? q : nb - 1 - q;
+      const int r0 = jb * B, w = min(B, n - r0);
+      const int ca = pass == 0 ? 0 : r0 + w, cb = pass == 0 ? r0 : n;
+      double acc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = 0.0;
+      const double* arow = g.A + r0 + min(lane, w - 1);
+      int c = ca + wave;
+      for (; c + (U - 1) * NW < cb; c += U * NW) {
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = arow[(size_t)(c + u * NW) * lda];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double* xr = x + (size_t)r * ldx + c;
+          double t = 0.0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) t += a[u] * xr[u * NW];
+          acc[r] += t;
+        }
+      }
+      for (; c < cb; c += NW) {
+        const double a = arow[(size_t)c * lda];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += a * x[(size_t)r * ldx + c];
+      }
+      for (int i = threadIdx.x; i < B * B; i += TRSV_THREADS) {
+        const int rr = i % B, cc = i / B;
+        Ld[rr][cc] = (rr < w && cc < w && rr >= cc) ? g.A[(r0 + rr) + (size_t)(r0 + cc) * lda] : 0.0;
+      }
+      // the waves' partial sums, one right-hand side per round: wave r % NW
+      // adds them up (in wave order) while the others write the next round
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        part[r & 1][wave][lane] = acc[r];
+        __syncthreads();
+        if (wave == r % NW) {
+          double t = 0.0;
+          for (int k = 0; k < NW; ++k) t += part[r & 1][k][lane];
+          zb[r][lane] = t;
+        }
+      }
+      __syncthreads();
+      // diagonal block: L y = z (forward) or L^T y = z (backward); waves
+      // 0..R-1 take one right-hand side each, one lane per row
+      if (wave < R) {
+        const int r = wave;
+        double z = 0.0;
+        if (lane < w) z = x[(size_t)r * ldx + r0 + lane] - zb[r][lane];
+        if (pass == 0) {
+          for (int k = 0; k < w; ++k) {
+            const double yk = __shfl(z / Ld[k][k], k);
+            if (lane > k && lane < w) z -= Ld[lane][k] * yk;
+            if (lane == k) z = yk;
+          }
+        } else {
+          for (int k = w - 1; k >= 0; --k) {
+            const double yk = __shfl(z / Ld[k][k], k);
+            if (lane < k) z -= Ld[k][lane] * yk;
+            if (lane == k) z = yk;
+          }
+        }
+        if (lane < w) x[(size_t)r * ldx + r0 + lane] = z;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+void launch_trsv_chol(const TrsvDesc* d, int n, int nrhs, hipStream_t st) {
+  if (n == 0 || nrhs == 0) return;
+  switch (nrhs) {
+#define AMB_CASE(R) case R: k_trsv_chol<R><<<n, TRSV_THREADS, 0, st>>>(d); break;
+    AMB_CASE(1) AMB_CASE(2) AMB_CASE(3) AMB_CASE(4) AMB_CASE(5) AMB_CASE(6) AMB_CASE(7)
+    AMB_CASE(8) AMB_CASE(9) AMB_CASE(10) AMB_CASE(11) AMB_CASE(12) AMB_CASE(13) AMB_CASE(14)
+    AMB_CASE(15) AMB_CASE(16)
+#undef AMB_CASE
+    default: throw Error(1, "trsv: nrhs must be in 1..16");
+  }
+  AMB_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
 // lower -> upper copy on a square block [n0, n0+n)^2
 // --------------------------------------------------------------------------
 

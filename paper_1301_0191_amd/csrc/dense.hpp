@@ -201,6 +201,47 @@ class LdltOp {
   int failed(hipStream_t st);       // returns failing matrix index or -1
 };
 
+// In-place right-side triangular solve X L = B for a batch of matrices
+// after their partial Cholesky: L (nI x nI, lower, in the leading block of
+// A) and B (nG x nI, the block rows nI..nI+nG, columns 0..nI of A, i.e.
+// K_GI L^{-T}) are overwritten by X = B L^{-1} = K_GI K_II^{-1}.  Blocks of TB
+// columns from the right: each step updates one block column with the
+// columns already solved (an MFMA GEMM, K up to nI) and solves it with the
+// TB x TB diagonal block of L (one thread per row).
+struct TrsmDesc {
+  double* A;
+  int lda, nI, nG;
+};
+
+class TrsmOp {
+ public:
+  static constexpr int TB = 64;
+  std::vector<TrsmDesc> h;
+  DBuf<TrsmDesc> d;
+  struct Step {
+    int t, off, nact, upd_total, sol_total;
+  };
+  std::vector<Step> steps;
+  DBuf<int> act, upd_pre, sol_pre;
+  void add(double* A, int lda, int nI, int nG) {
+    if (nI > 0 && nG > 0) h.push_back(TrsmDesc{A, lda, nI, nG});
+  }
+  void finalize(hipStream_t st);
+  void run(hipStream_t st) const;
+};
+
+// Batched x <- K_II^{-1} x with the partial Cholesky factor of every matrix
+// (L lower in the leading nI x nI block of A and L^T in its upper triangle):
+// one workgroup per matrix for all (up to 16) right-hand sides, forward then
+// backward substitution in blocks of 64 rows.
+struct TrsvDesc {
+  const double* A;
+  int lda, nI;
+  double* x;        // nI x nrhs, leading dimension ldx
+  int64_t ldx;
+};
+void launch_trsv_chol(const TrsvDesc* d, int n, int nrhs, hipStream_t st);
+
 class SymOp {
  public:
   struct Desc { double* A; int lda, n0, n; int start; };

@@ -21,6 +21,16 @@ struct Level {
   LdltOp ldl_aug;
   SymOp sym_aug;
   GemvOp g1, g4;
+  // plain: the level-1 block is [[K_II, K_IG], [K_GI, K_GG]] without the
+  // identity augmentation; after the factorisation its Gamma x I block holds
+  // K_GI K_II^{-1} (trsm) and the interior block L and L^T (sym_L), and
+  // interior solves are triangular solves (trsv) instead of the dense K_II^{-1}
+  bool plain = false;
+  TrsmOp trsm;
+  SymOp sym_L;
+  DBuf<TrsvDesc> trsv;
+  int n_trsv = 0;
+  DBuf<int64_t> Iiota;
 
   // constraint-dependent part
   std::vector<int> nc, nl, naugN;

@@ -133,9 +133,10 @@ int nsel_max(const ambddc_options& o) { return o.fixed_per_face > 0 ? o.fixed_pe
 // ---------------------------------------------------------------------------
 
 void build_level_maps(ambddc_ctx& c, Level& L, const double* emat,
-                      const std::vector<int64_t>& emat_off) {
+                      const std::vector<int64_t>& emat_off, bool plain) {
   hipStream_t st = c.st;
   const LevelPlan& P = L.plan;
+  L.plain = plain;
   L.nsub = P.in.n_sub;
   L.ndof = P.in.n_dof;
   L.nrb = P.in.n_rb;
@@ -147,7 +148,7 @@ void build_level_maps(ambddc_ctx& c, Level& L, const double* emat,
     L.nI[s] = P.subs[s].nI;
     L.nG[s] = P.subs[s].nG;
     L.ns[s] = L.nI[s] + L.nG[s];
-    L.augN[s] = L.ns[s] + L.nI[s];
+    L.augN[s] = plain ? L.ns[s] : L.ns[s] + L.nI[s];
     L.aug_off[s + 1] = L.aug_off[s] + int64_t(L.augN[s]) * L.augN[s];
     L.Ioff[s + 1] = L.Ioff[s] + L.nI[s];
     L.Goff[s + 1] = L.Goff[s] + L.nG[s];
@@ -205,19 +206,33 @@ void build_level_maps(ambddc_ctx& c, Level& L, const double* emat,
   L.delta.alloc(L.nG_tot);
   L.rho.alloc(ns);
   (void)g2y2;
-  // batched partial factorisation of Aug^s = [[K, I_I^T], [I_I, 0]]: nI positive pivots
+  // batched partial factorisation of Aug^s = [[K, I_I^T], [I_I, 0]] (or of
+  // K alone on a plain level): nI positive pivots
   L.ldl_aug = LdltOp();
   L.sym_aug = SymOp();
+  L.trsm = TrsmOp();
+  L.sym_L = SymOp();
   L.g1 = GemvOp();
   L.g4 = GemvOp();
   for (int s = 0; s < ns; ++s) {
     double* A = L.aug.p + L.aug_off[s];
     const int N = L.augN[s];
     L.ldl_aug.add(A, N, N, L.nI[s], L.nI[s]);
-    L.sym_aug.add(A, N, L.nI[s], L.nG[s] + L.nI[s]);
+    L.sym_aug.add(A, N, L.nI[s], plain ? L.nG[s] : L.nG[s] + L.nI[s]);
+    if (plain) {
+      L.trsm.add(A, N, L.nI[s], L.nG[s]);
+      L.sym_L.add(A, N, 0, L.nI[s]);
+    }
   }
   L.ldl_aug.finalize(st);
   L.sym_aug.finalize(st);
+  if (plain) {
+    L.trsm.finalize(st);
+    L.sym_L.finalize(st);
+    std::vector<int64_t> iota(std::max<int64_t>(L.nI_tot, 1));
+    for (int64_t i = 0; i < int64_t(iota.size()); ++i) iota[i] = i;
+    L.Iiota.upload(iota, st);
+  }
 }
 
 void alloc_workspace(Level& L, int nrhs) {
@@ -243,15 +258,23 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
   L.g2 = GemvOp();
   L.g3 = GemvOp();
   L.g4 = GemvOp();
+  std::vector<TrsvDesc> tv;
   for (int s = 0; s < L.nsub; ++s) {
     const int N = L.augN[s], nI = L.nI[s], nG = L.nG[s], nsl = L.ns[s];
     double* A = L.aug.p + L.aug_off[s];
-    // [g; -K_II^{-1} r_I] = M^T r_I,  M = Aug[ns:ns+nI, nI:nI+nG+nI]
-    L.g1.add(A + nsl + int64_t(nI) * N, N, nI, nG + nI, L.w_xI.p + L.Ioff[s], int(L.nI_tot),
-             L.w_y1.p + L.y1off[s], int(L.y1_tot));
-    // interior:  Tr[nG:, 0:nG] u_B = (Aug[nI:nI+nG, ns:ns+nI])^T u_B
-    L.g4.add(A + nI + int64_t(nsl) * N, N, nG, nI, L.w_uBs.p + L.Goff[s], int(L.nG_tot),
-             L.w_y1.p + L.y1off[s] + nG, int(L.y1_tot));
+    if (L.plain) {
+      // interior solves by the factor; K_II^{-1} K_IG u_B = (Aug[nI:nI+nG, 0:nI])^T u_B
+      if (nI > 0) tv.push_back(TrsvDesc{A, N, nI, L.w_xI.p + L.Ioff[s], L.nI_tot});
+      L.g4.add(A + nI, N, nG, nI, L.w_uBs.p + L.Goff[s], int(L.nG_tot),
+               L.w_y1.p + L.y1off[s] + nG, int(L.y1_tot));
+    } else {
+      // [g; -K_II^{-1} r_I] = M^T r_I,  M = Aug[ns:ns+nI, nI:nI+nG+nI]
+      L.g1.add(A + nsl + int64_t(nI) * N, N, nI, nG + nI, L.w_xI.p + L.Ioff[s], int(L.nI_tot),
+               L.w_y1.p + L.y1off[s], int(L.y1_tot));
+      // interior:  Tr[nG:, 0:nG] u_B = (Aug[nI:nI+nG, ns:ns+nI])^T u_B = -K_II^{-1} K_IG u_B
+      L.g4.add(A + nI + int64_t(nsl) * N, N, nG, nI, L.w_uBs.p + L.Goff[s], int(L.nG_tot),
+               L.w_y1.p + L.y1off[s] + nG, int(L.y1_tot));
+    }
     const int nl = L.nl[s], NN = L.naugN[s];
     double* B = L.naug.p + L.naug_off[s];
     // [-Z r; -Psi^T r] = (Trn[0:nG, 0:nl])^T r
@@ -261,15 +284,17 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
     L.g3.add(B + nl + nG + int64_t(nl) * NN, NN, L.nc[s], nG, L.w_ucl.p + L.cloff[s],
              int(std::max<int64_t>(L.cl_tot, 1)), L.w_y2.p + L.y2off[s], int(L.y2_tot));
   }
+  L.n_trsv = int(tv.size());
+  if (L.plain) L.trsv.upload(tv, st);
   if (c.opt.precision >= 1) {
     // Alg. 1's dense operators are only read by the preconditioner: keep them
     // in FP32 (the FP64 blocks stay for the Schur complements and set-up).
     // On level 1 the PCG iterates in the discrete harmonic space, which the
-    // interior solve of x0 (g1) and the interior post-correction (g4) must
-    // keep to FP64 rounding: a residual component on the interiors is never
-    // corrected there, so those two stay FP64.
+    // interior solves of x0 and the interior post-correction (g4) must keep
+    // to FP64 rounding: a residual component on the interiors is never
+    // corrected there, so those stay FP64.
     const bool level1 = &L == c.L[0].get();
-    if (!level1) L.g1.pack_a_f32(L.g1_32, st);
+    if (!level1 && !L.plain) L.g1.pack_a_f32(L.g1_32, st);
     L.g2.pack_a_f32(L.g2_32, st);
     L.g3.pack_a_f32(L.g3_32, st);
     if (!level1) L.g4.pack_a_f32(L.g4_32, st);
@@ -421,7 +446,7 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
   L.aug.zero(st);
   launch_assemble(L.am, L.emat, L.d_aug_off.p, L.d_augN.p, L.aug.p, st);
   // identity coupling Aug[ns + i, i] = Aug[i, ns + i] = 1, i < nI
-  {
+  if (!L.plain) {
     std::vector<int> zero(L.nsub, 0);
     DBuf<int> dz;
     dz.upload(zero, st);
@@ -438,10 +463,12 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
     }
     c.kt.begin("schur", st);
     L.ldl_aug.run(st);
+    if (L.plain) L.trsm.run(st);   // K_GI K_II^{-1} from the factor
     c.kt.end("schur", st, f, b);
   }
   check_ldlt(L.ldl_aug, st, "interior factorisation", li);
   L.sym_aug.run(st);
+  if (L.plain) L.sym_L.run(st);
   // rho_s = mean diag(S^s)
   {
     std::vector<int> n0(L.nsub);
@@ -1275,7 +1302,8 @@ void apply_level(ambddc_ctx& c, int li, const double* r, int64_t ldr, double* u,
   // averaging, interior post-correction, combination
   launch_average(int(L.nG_tot), L.Gdof.p, L.incptr.p, L.incpos.p, L.g2y2.p, L.delta.p, L.w_y2.p,
                  L.y2_tot, L.w_uBs.p, L.nG_tot, u, ldu, nrhs, st);
-  L.g4.run(1.0, harmonic ? 0.0 : -1.0, nrhs, st);
+  if (L.plain && !harmonic) throw Error(AMBDDC_E_STATE, "interior pre-correction on a plain level");
+  L.g4.run(L.plain ? -1.0 : 1.0, harmonic ? 0.0 : -1.0, nrhs, st);
   launch_move(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, u, ldu, nrhs, st);
 }
 
@@ -1288,6 +1316,11 @@ void interior_solve(ambddc_ctx& c, const double* f, double* x, int nrhs) {
   const int64_t n = L.ndof;
   launch_fill(x, size_t(n) * nrhs, 0.0, st);
   launch_gather(int(L.nI_tot), L.Imap.p, f, n, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
+  if (L.plain) {
+    launch_trsv_chol(L.trsv.p, L.n_trsv, nrhs, st);
+    launch_move(int(L.nI_tot), L.Iiota.p, L.w_xI.p, L.nI_tot, L.Imap.p, x, n, nrhs, st);
+    return;
+  }
   L.g1.run(-1.0, 0.0, nrhs, st);
   launch_move(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, x, n, nrhs, st);
 }
@@ -1298,6 +1331,12 @@ void interior_correct(ambddc_ctx& c, const double* r, double* x, int nrhs, const
   Level& L = *c.L[0];
   const int64_t n = L.ndof;
   launch_gather(int(L.nI_tot), L.Imap.p, r, n, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
+  if (L.plain) {
+    launch_trsv_chol(L.trsv.p, L.n_trsv, nrhs, st);
+    launch_move_add_masked(int(L.nI_tot), L.Iiota.p, L.w_xI.p, L.nI_tot, L.Imap.p, x, n, nrhs,
+                           mask, st);
+    return;
+  }
   L.g1.run(-1.0, 0.0, nrhs, st);
   launch_move_add_masked(int(L.nI_tot), L.I2y1.p, L.w_y1.p, L.y1_tot, L.Imap.p, x, n, nrhs, mask,
                          st);
@@ -1312,7 +1351,7 @@ void next_level(ambddc_ctx& c, int li) {
   e = build_level_plan(N->plan, c.opt.initial_constraints, c.opt.keep_edges != 0);
   if (!e.empty()) throw Error(AMBDDC_E_INVALID_ARG, e);
   std::vector<int64_t> koff(L.kc_off.begin(), L.kc_off.end() - 1);
-  build_level_maps(c, *N, L.kc.p, koff);
+  build_level_maps(c, *N, L.kc.p, koff, false);
   // coarse values of the level-li rigid modes
   N->rigid.alloc(size_t(N->ndof) * N->nrb);
   {
@@ -1882,7 +1921,7 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     L0->plan = c->plan0;
     std::vector<int64_t> eoff(mesh->n_elems);
     for (int e2 = 0; e2 < mesh->n_elems; ++e2) eoff[e2] = int64_t(e2) * ne * ne;
-    build_level_maps(*c, *L0, c->Ke.p, eoff);
+    build_level_maps(*c, *L0, c->Ke.p, eoff, true);
     L0->rigid.alloc(size_t(L0->ndof) * L0->nrb);
     {
       DBuf<int> fof;

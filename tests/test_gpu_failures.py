@@ -112,7 +112,7 @@ def test_oversized_problem_reports_oom():
     log("CASE E_OOM")
     torch_cuda()
     from paper_1301_0191_amd import AmbddcError, Handle
-    prob = W.make_problem((100, 50, 50), (2, 1, 1), seed=0)
+    prob = W.make_problem((120, 60, 60), (2, 1, 1), seed=0)   # 2 x 412 GB dense blocks
     with pytest.raises(AmbddcError, match="E_OOM"):
         Handle.from_problem(prob)
     # the library is still usable afterwards
