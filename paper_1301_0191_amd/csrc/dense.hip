@@ -272,9 +272,13 @@ void convert_blocks_f32(const std::vector<CvtDesc>& blocks, hipStream_t st) {
 // GEMV (transposed, several right-hand sides): one wave per output column
 // --------------------------------------------------------------------------
 
+// The column is read in 16-byte pairs (after one leading element when the
+// column starts on an odd double), U pairs per lane in flight, so the wave
+// keeps 4 KB of loads outstanding instead of waiting on every 512 bytes.
 template <int R>
 __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, int nd, double alpha,
                                                 double beta) {
+  constexpr int U = 4;
   const int wg = blockIdx.x;
   int lo = 0, hi = nd - 1;
   while (lo < hi) {
@@ -285,14 +289,43 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
   const int col = (wg - g.wg_start) * 4 + (threadIdx.x >> 6);
   if (col >= g.M) return;
   const int lane = threadIdx.x & 63;
-  const double* a = static_cast<const double*>(g.A) + (size_t)col * g.lda;
+  const double* __restrict__ a = static_cast<const double*>(g.A) + (size_t)col * g.lda;
+  const double* __restrict__ x = g.X;
+  const size_t ldx = g.ldx;
+  const int K = g.K;
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  for (int i = lane; i < g.K; i += 64) {
-    const double av = a[i];
+  const int head = (K > 0 && ((reinterpret_cast<uintptr_t>(a) >> 3) & 1)) ? 1 : 0;
+  if (head && lane == 0) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
+    for (int r = 0; r < R; ++r) acc[r] += a[0] * x[r * ldx];
+  }
+  const double2* __restrict__ a2 = reinterpret_cast<const double2*>(a + head);
+  const double* __restrict__ xh = x + head;
+  const int n2 = (K - head) >> 1;
+  int p = lane;
+  for (; p + 64 * (U - 1) < n2; p += 64 * U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = a2[p + 64 * u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = 2 * (p + 64 * u);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        acc[r] += v[u].x * xh[i + r * ldx] + v[u].y * xh[i + 1 + r * ldx];
+    }
+  }
+  for (; p < n2; p += 64) {
+    const double2 v = a2[p];
+    const int i = 2 * p;
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += v.x * xh[i + r * ldx] + v.y * xh[i + 1 + r * ldx];
+  }
+  if (lane == 0 && ((K - head) & 1)) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += a[K - 1] * x[K - 1 + r * ldx];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -308,6 +341,156 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
     double* y = g.Y + col + (size_t)lane * g.ldy;
     *y = alpha * v + (beta != 0.0 ? beta * (*y) : 0.0);
   }
+}
+
+// --------------------------------------------------------------------------
+// Symmetric GEMV from the tiles on or below the diagonal
+// --------------------------------------------------------------------------
+
+// Partials of one descriptor: tile (J, I), I >= J, at tri(J, I) = J nb -
+// J (J - 1) / 2 + (I - J) holds A_IJ x_J (A_JJ x_J for I = J); the column
+// sums sum_{I > J} A_IJ^T x_I follow at tri count + J.  Each is 3 x 64.
+__device__ __forceinline__ int64_t symv_tri(int nb, int J, int I) {
+  return int64_t(J) * nb - int64_t(J) * (J - 1) / 2 + (I - J);
+}
+
+// One workgroup per (descriptor, block column J); wave w owns the 16 columns
+// J*64 + 16w.., lane l the row I*64 + l of every tile I >= J.
+template <int R>
+__global__ __launch_bounds__(256) void k_symv_part(const SymvDesc* __restrict__ d,
+                                                   const int2* __restrict__ work,
+                                                   double* __restrict__ part) {
+  __shared__ double red[2][4][R][64];
+  __shared__ double xs[R][64];   // x at the block column (zero past n)
+  const int2 wk = work[blockIdx.x];
+  const SymvDesc g = d[wk.x];
+  const int J = wk.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c0 = J * 64 + w * 16;
+  const double* __restrict__ x = g.X;
+  const size_t ldx = g.ldx;
+  if (w < R) xs[w][lane] = (J * 64 + lane < g.n) ? x[J * 64 + lane + w * ldx] : 0.0;
+  __syncthreads();
+  double cs[16][R];
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+#pragma unroll
+    for (int r = 0; r < R; ++r) cs[k][r] = 0.0;
+  double* P = part + g.part_off;
+  const int tri_n = g.nb * (g.nb + 1) / 2;
+  const int kmax = min(16, max(0, g.n - c0));   // valid columns of this wave
+  for (int I = J; I < g.nb; ++I) {
+    const int row = I * 64 + lane;
+    const bool rv = row < g.n;
+    double z[16];
+    const double* __restrict__ a = g.A + row + (size_t)c0 * g.lda;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) z[k] = (rv && k < kmax) ? a[(size_t)k * g.lda] : 0.0;
+    double rp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v += z[k] * xs[r][w * 16 + k];
+      rp[r] = v;
+    }
+    if (I > J) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double xr = rv ? x[row + r * ldx] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cs[k][r] += z[k] * xr;
+      }
+    }
+    const int b = I & 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) red[b][w][r][lane] = rp[r];
+    __syncthreads();
+    // one wave adds the four column groups' partial rows of this tile; the
+    // buffer is written again two tiles later, after the next barrier
+    if (w == (I & 3)) {
+      double* t = P + symv_tri(g.nb, J, I) * (3 * 64);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        t[r * 64 + lane] =
+            (red[b][0][r][lane] + red[b][1][r][lane]) + (red[b][2][r][lane] + red[b][3][r][lane]);
+    }
+  }
+  // column sums of this wave's 16 columns: reduce over the 64 rows
+  double* t = P + (int64_t(tri_n) + J) * (3 * 64);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double v = cs[k][r];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == k) t[r * 64 + w * 16 + k] = v;
+    }
+}
+
+// y_i = alpha (colsum_J(i) + sum_{J <= I} tile (J, I)) + beta y_i, I = i / 64.
+template <int R>
+__global__ __launch_bounds__(256) void k_symv_sum(const SymvDesc* __restrict__ d, int nd, int rows,
+                                                  const double* __restrict__ part, double alpha,
+                                                  double beta) {
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= rows) return;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].row_start <= gi) lo = mid; else hi = mid - 1;
+  }
+  const SymvDesc g = d[lo];
+  const int i = gi - g.row_start;
+  const int I = i >> 6, l = i & 63;
+  const double* P = part + g.part_off;
+  const int tri_n = g.nb * (g.nb + 1) / 2;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = P[(int64_t(tri_n) + I) * (3 * 64) + r * 64 + l];
+    for (int J = 0; J <= I; ++J) v += P[symv_tri(g.nb, J, I) * (3 * 64) + r * 64 + l];
+    double* y = g.Y + i + (size_t)r * g.ldy;
+    *y = alpha * v + (beta != 0.0 ? beta * (*y) : 0.0);
+  }
+}
+
+void SymvOp::finalize(hipStream_t st) {
+  std::vector<int2> wk;
+  int64_t off = 0;
+  rows = 0;
+  for (size_t q = 0; q < h.size(); ++q) {
+    SymvDesc& g = h[q];
+    g.nb = ceil_div(g.n, 64);
+    g.row_start = rows;
+    g.part_off = off;
+    rows += g.n;
+    off += (int64_t(g.nb) * (g.nb + 1) / 2 + g.nb) * 3 * 64;
+    for (int J = 0; J < g.nb; ++J) wk.push_back(make_int2(int(q), J));
+  }
+  // the longest block columns first, so that the short ones fill the tail
+  std::stable_sort(wk.begin(), wk.end(), [&](const int2& a, const int2& b) {
+    return h[a.x].nb - a.y > h[b.x].nb - b.y;
+  });
+  nwork = int(wk.size());
+  d.upload(h, st);
+  work.upload(wk, st);
+  part.alloc(size_t(std::max<int64_t>(off, 1)));
+}
+
+void SymvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
+  if (h.empty()) return;
+  if (nrhs < 1 || nrhs > MAX_RHS) throw Error(1, "SymvOp: nrhs must be in 1..3");
+  const int nd = int(h.size());
+  switch (nrhs) {
+#define AMB_CASE(R)                                                                       \
+  case R:                                                                                 \
+    k_symv_part<R><<<nwork, 256, 0, st>>>(d.p, work.p, part.p);                           \
+    AMB_LAUNCH_CHECK();                                                                   \
+    k_symv_sum<R><<<ceil_div(rows, 256), 256, 0, st>>>(d.p, nd, rows, part.p, alpha, beta); \
+    break;
+    AMB_CASE(1) AMB_CASE(2) AMB_CASE(3)
+#undef AMB_CASE
+  }
+  AMB_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------------------------

@@ -160,6 +160,43 @@ class GemvOp {
   bool empty() const { return h.empty(); }
 };
 
+// y = alpha A x + beta y for symmetric n x n blocks (column-major, stored
+// whole), reading only the 64 x 64 tiles on or below the diagonal: each
+// workgroup takes one block column J, forms A_IJ x_J for the tiles I >= J as
+// partial rows and A_IJ^T x_I for I > J as its own column sums, and a second
+// pass adds the partials of every row in a fixed order.  Half the bytes of a
+// GEMV over the whole block; 1..3 right-hand sides.
+struct SymvDesc {
+  const double* A;
+  int lda, n;
+  const double* X;
+  int ldx;
+  double* Y;
+  int ldy;
+  int nb;             // ceil(n / 64)
+  int row_start;      // first row of this block in the rows of the sum pass
+  int64_t part_off;   // partials: nb (nb + 1) / 2 tiles + nb column sums, 3 x 64 each
+};
+
+class SymvOp {
+ public:
+  static constexpr int MAX_RHS = 3;
+  std::vector<SymvDesc> h;
+  void add(const double* A, int lda, int n, const double* X, int ldx, double* Y, int ldy) {
+    if (n <= 0) return;
+    h.push_back(SymvDesc{A, lda, n, X, ldx, Y, ldy, 0, 0, 0});
+  }
+  void finalize(hipStream_t st);
+  void run(double alpha, double beta, int nrhs, hipStream_t st) const;
+  bool empty() const { return h.empty(); }
+
+ private:
+  DBuf<SymvDesc> d;
+  DBuf<int2> work;     // (descriptor, block column), most tiles first
+  DBuf<double> part;
+  int nwork = 0, rows = 0;
+};
+
 // FP32 copies of dense blocks: dst (ld ldd) = src (ld lds), rows x cols.
 struct CvtDesc {
   const double* src;

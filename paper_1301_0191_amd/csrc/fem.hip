@@ -167,41 +167,167 @@ void launch_assemble(const AssemblyMaps& m, const double* emat, const int64_t* t
   AMB_LAUNCH_CHECK();
 }
 
-// Global CSR values: thread per row; every element incident to the row adds
-// its row (= column, symmetric) at the matching column positions.
-__global__ __launch_bounds__(256) void k_csr_values(int n, const int* __restrict__ rowptr,
+// Lanes of one wave that hand LDS values to each other between steps: a
+// wave's LDS accesses complete in program order, and the fences keep the
+// compiler from moving them across the step boundary.
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Whole-column assembly: one wave per (subdomain, local column j).  The
+// column is built in LDS, zeros plus every incident element's column in the
+// fixed incidence order, and written out whole (leading dimension rows), so
+// the dense block needs no separate zero fill and takes no read-modify-write
+// traffic.  The metadata of up to 8 incidences is loaded by 8 lanes at once
+// and their element entries are in flight together before the LDS adds; one
+// element's DOFs are distinct rows.  Elements of at most 64 DOFs.
+__global__ __launch_bounds__(256) void k_assemble_cols(int ncols, int ldmax,
+                                                       const int* __restrict__ col_sub,
+                                                       const int* __restrict__ col_j,
+                                                       const int64_t* __restrict__ inc_ptr,
+                                                       const int* __restrict__ inc_e,
+                                                       const int* __restrict__ inc_a,
+                                                       const int64_t* __restrict__ emat_off,
+                                                       const int* __restrict__ elem_ne,
+                                                       const int64_t* __restrict__ eloc_off,
+                                                       const int* __restrict__ eloc,
+                                                       const double* __restrict__ emat,
+                                                       const int64_t* __restrict__ tgt_off,
+                                                       const int* __restrict__ tgt_ld, double* tgt) {
+  constexpr int QC = 8;
+  extern __shared__ double asm_col[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gc = blockIdx.x * (blockDim.x >> 6) + w;
+  if (gc >= ncols) return;   // whole waves leave together
+  double* cs = asm_col + (size_t)w * ldmax;
+  const int s = col_sub[gc], j = col_j[gc];
+  const int ld = tgt_ld[s];
+  for (int r = lane; r < ld; r += 64) cs[r] = 0.0;
+  const int64_t qa = inc_ptr[gc], qb = inc_ptr[gc + 1];
+  for (int64_t q0 = qa; q0 < qb; q0 += QC) {
+    const int nq = int(min<int64_t>(QC, qb - q0));
+    int ne_t = 0, eo_lo = 0, eo_hi = 0, lo_lo = 0, lo_hi = 0;
+    if (lane < nq) {
+      const int e = inc_e[q0 + lane], a = inc_a[q0 + lane];
+      ne_t = elem_ne[e];
+      const int64_t eo = emat_off[e] + (int64_t)a * ne_t, lo = eloc_off[e];
+      eo_lo = int(uint32_t(eo)); eo_hi = int(uint64_t(eo) >> 32);
+      lo_lo = int(uint32_t(lo)); lo_hi = int(uint64_t(lo) >> 32);
+    }
+    int rr[QC];
+    double vv[QC];
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const int neu = __shfl(ne_t, u);
+      const int64_t eo = int64_t((uint64_t(uint32_t(__shfl(eo_hi, u))) << 32) |
+                                 uint32_t(__shfl(eo_lo, u)));
+      const int64_t lo = int64_t((uint64_t(uint32_t(__shfl(lo_hi, u))) << 32) |
+                                 uint32_t(__shfl(lo_lo, u)));
+      rr[u] = -1;
+      vv[u] = 0.0;
+      if (u < nq && lane < neu) {
+        rr[u] = eloc[lo + lane];
+        vv[u] = emat[eo + lane];
+      }
+    }
+    group_sync();   // the zeros (first chunk) or the previous chunk's adds
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      if (rr[u] >= 0) cs[rr[u]] += vv[u];
+      group_sync();
+    }
+  }
+  group_sync();
+  double* col = tgt + tgt_off[s] + (int64_t)j * ld;
+  for (int r = lane; r < ld; r += 64) col[r] = cs[r];
+}
+
+void launch_assemble_cols(const AssemblyMaps& m, int ldmax, const double* emat,
+                          const int64_t* tgt_off, const int* tgt_ld, double* tgt, hipStream_t st) {
+  if (m.ncols == 0) return;
+  if (m.max_ne > 64) throw Error(1, "assemble_cols: elements of more than 64 DOFs");
+  const size_t per_col = size_t(ldmax) * sizeof(double);
+  if (per_col > 64 * 1024) throw Error(1, "assemble_cols: column longer than the LDS staging allows");
+  int waves = 4;
+  while (waves > 1 && size_t(waves) * per_col > 64 * 1024) --waves;
+  k_assemble_cols<<<ceil_div(m.ncols, waves), 64 * waves, waves * per_col, st>>>(
+      m.ncols, ldmax, m.col_sub.p, m.col_j.p, m.inc_ptr.p, m.inc_e.p, m.inc_a.p, m.emat_off.p,
+      m.elem_ne.p, m.eloc_off.p, m.eloc.p, emat, tgt_off, tgt_ld, tgt);
+  AMB_LAUNCH_CHECK();
+}
+
+// Global CSR values: a group of G lanes per row (G >= DOFs per element).  The
+// row's column indices are staged in LDS beside one accumulator per entry;
+// for every element incident to the row, lane b adds the element-matrix entry
+// of the element's DOF b at the position found by binary search over the
+// staged indices.  One element's DOFs are distinct columns, and the elements
+// are taken in the fixed incidence order, so the sums are deterministic.  A
+// group lives inside one wave (group_sync).
+template <int G>
+__global__ __launch_bounds__(256) void k_csr_values(int n, int maxrow,
+                                                    const int* __restrict__ rowptr,
                                                     const int* __restrict__ cols,
                                                     const int64_t* __restrict__ inc_ptr,
                                                     const int* __restrict__ inc_e,
                                                     const int* __restrict__ inc_a,
                                                     const int* __restrict__ edofs, int ne,
                                                     const double* __restrict__ Ke, double* vals) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int r0 = rowptr[i], r1 = rowptr[i + 1];
-  for (int k = r0; k < r1; ++k) vals[k] = 0.0;
-  for (int64_t q = inc_ptr[i]; q < inc_ptr[i + 1]; ++q) {
-    const int e = inc_e[q], a = inc_a[q];
-    const double* ke = Ke + (size_t)e * ne * ne + (size_t)a * ne;
-    const int* ed = edofs + (size_t)e * ne;
-    for (int b = 0; b < ne; ++b) {
-      const int c = ed[b];
-      if (c < 0) continue;
-      int lo = r0, hi = r1 - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cols[mid] < c) lo = mid + 1; else hi = mid;
-      }
-      vals[lo] += ke[b];
-    }
+  extern __shared__ double csr_sm[];
+  const int rpb = blockDim.x / G;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  double* acc = csr_sm + (size_t)grp * maxrow;
+  int* cl = reinterpret_cast<int*>(csr_sm + (size_t)rpb * maxrow) + (size_t)grp * maxrow;
+  const int i = blockIdx.x * rpb + grp;
+  if (i >= n) return;   // whole groups leave together
+  const int r0 = rowptr[i], len = rowptr[i + 1] - r0;
+  for (int k = lane; k < len; k += G) {
+    acc[k] = 0.0;
+    cl[k] = cols[r0 + k];
   }
+  group_sync();
+  const int64_t q1 = inc_ptr[i + 1];
+  for (int64_t q = inc_ptr[i]; q < q1; ++q) {
+    const int e = inc_e[q], a = inc_a[q];
+    if (lane < ne) {
+      const int c = edofs[(size_t)e * ne + lane];
+      if (c >= 0) {
+        int lo = 0, hi = len - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (cl[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        acc[lo] += Ke[(size_t)e * ne * ne + (size_t)a * ne + lane];
+      }
+    }
+    group_sync();
+  }
+  for (int k = lane; k < len; k += G) vals[r0 + k] = acc[k];
 }
 
 void launch_csr_values(const CsrMaps& m, const int* edofs, int ne, const double* Ke, double* vals,
                        hipStream_t st) {
   if (m.n == 0) return;
-  k_csr_values<<<ceil_div(m.n, 256), 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, m.inc_ptr.p,
-                                                   m.inc_e.p, m.inc_a.p, edofs, ne, Ke, vals);
+  const int G = ne <= 8 ? 8 : ne <= 16 ? 16 : ne <= 32 ? 32 : 64;
+  if (ne > 64) throw Error(1, "csr values: more than 64 DOFs per element");
+  const size_t per_row = size_t(m.maxrow) * (sizeof(double) + sizeof(int));
+  int rpb = 256 / G;
+  while (rpb > 1 && size_t(rpb) * per_row > 64 * 1024) rpb >>= 1;
+  if (size_t(rpb) * per_row > 64 * 1024)
+    throw Error(1, "csr values: row longer than the LDS staging allows");
+  const size_t lds = size_t(rpb) * per_row;
+  const int blocks = ceil_div(m.n, rpb);
+  switch (G) {
+#define AMB_CASE(GG)                                                                          \
+  case GG:                                                                                    \
+    k_csr_values<GG><<<blocks, rpb * GG, lds, st>>>(m.n, m.maxrow, m.rowptr.p, m.cols.p,      \
+                                                    m.inc_ptr.p, m.inc_e.p, m.inc_a.p, edofs, \
+                                                    ne, Ke, vals);                            \
+    break;
+    AMB_CASE(8) AMB_CASE(16) AMB_CASE(32) AMB_CASE(64)
+#undef AMB_CASE
+  }
   AMB_LAUNCH_CHECK();
 }
 

@@ -8,6 +8,7 @@ namespace ambddc {
 // Column-gather assembly of dense subdomain blocks from element matrices.
 struct AssemblyMaps {
   int ncols = 0;
+  int max_ne = 0;                  // largest element matrix order
   DBuf<int> col_sub, col_j;        // per assembled column: subdomain, local column
   DBuf<int64_t> inc_ptr;           // per column: incident (element, local index)
   DBuf<int> inc_e, inc_a;
@@ -19,6 +20,7 @@ struct AssemblyMaps {
 
 struct CsrMaps {
   int n = 0;
+  int maxrow = 0;   // longest row
   int64_t nnz = 0;
   DBuf<int> rowptr, cols;
   DBuf<int64_t> inc_ptr;
@@ -29,6 +31,11 @@ void launch_element_matrices(const double* coords, const int* en, const double* 
                              const double* nu, int n_elem, int dof, double* Ke, hipStream_t st);
 void launch_assemble(const AssemblyMaps& m, const double* emat, const int64_t* tgt_off,
                      const int* tgt_ld, double* tgt, hipStream_t st);
+// Every column of the target blocks written whole (zeros included): the
+// blocks need no fill beforehand; tgt_ld[s] <= ldmax <= 8192, elements of at
+// most 64 DOFs.
+void launch_assemble_cols(const AssemblyMaps& m, int ldmax, const double* emat,
+                          const int64_t* tgt_off, const int* tgt_ld, double* tgt, hipStream_t st);
 void launch_csr_values(const CsrMaps& m, const int* edofs, int ne, const double* Ke, double* vals,
                        hipStream_t st);
 void launch_spmv(const CsrMaps& m, const double* vals, const double* x, double* y, int nrhs,

@@ -11,6 +11,7 @@ struct Level {
   LevelPlan plan;
   int nsub = 0, ndof = 0, nrb = 1;
   std::vector<int> nI, nG, ns, augN;
+  int augN_max = 0;   // largest augN
   std::vector<int64_t> aug_off, Ioff, Goff, y1off;
   int64_t aug_total = 0, nI_tot = 0, nG_tot = 0, y1_tot = 0;
   DBuf<double> aug, diagG, delta, rho, rigid;
@@ -47,6 +48,10 @@ struct Level {
   LdltOp ldl_naug;
   SymOp sym_naug;
   GemvOp g2, g3;
+  // FP64, 1..3 right-hand sides: g2 as the symmetric Z (tiles on or below the
+  // diagonal) plus a GEMV over the coarse columns
+  SymvOp g2z;
+  GemvOp g2c;
   DBuf<double> Cs;                // sqrt(rho_s) C^s
   DBuf<int64_t> d_c_off, d_c_cnt;
   GemmOp gcc;                     // rho C^T C added to the (1,1) Neumann block

@@ -78,6 +78,7 @@ void build_assembly(AssemblyMaps& am, int nelem, const std::vector<int>& elem_tg
       col_j[colbase[s] + j] = j;
     }
   am.ncols = int(ncols);
+  am.max_ne = nelem ? *std::max_element(ene.begin(), ene.end()) : 0;
   am.col_sub.upload(col_sub, st);
   am.col_j.upload(col_j, st);
   am.inc_ptr.upload(cnt, st);
@@ -116,6 +117,13 @@ struct ambddc_ctx {
   int pcg_repl = 0;   // residual replacements in the last solve
   double last_res[16] = {};   // true relative residuals of the last solve
   int n_last_res = 0;
+  // pinned host copy of the PCG counters and the event that follows its copy
+  int* hcnt = nullptr;
+  hipEvent_t ev_cnt = nullptr;
+  ~ambddc_ctx() {
+    if (ev_cnt) (void)hipEventDestroy(ev_cnt);
+    if (hcnt) (void)hipHostFree(hcnt);
+  }
 };
 
 namespace {
@@ -155,6 +163,7 @@ void build_level_maps(ambddc_ctx& c, Level& L, const double* emat,
     L.y1off[s + 1] = L.y1off[s] + L.nG[s] + L.nI[s];
   }
   L.aug_total = L.aug_off[ns];
+  L.augN_max = ns ? *std::max_element(L.augN.begin(), L.augN.end()) : 0;
   L.nI_tot = L.Ioff[ns];
   L.nG_tot = L.Goff[ns];
   L.y1_tot = L.y1off[ns];
@@ -256,6 +265,8 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
   hipStream_t st = c.st;
   L.g1 = GemvOp();
   L.g2 = GemvOp();
+  L.g2z = SymvOp();
+  L.g2c = GemvOp();
   L.g3 = GemvOp();
   L.g4 = GemvOp();
   std::vector<TrsvDesc> tv;
@@ -280,6 +291,13 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
     // [-Z r; -Psi^T r] = (Trn[0:nG, 0:nl])^T r
     L.g2.add(B + nl + int64_t(nl) * NN, NN, nG, nl, L.w_rBs.p + L.Goff[s], int(L.nG_tot),
              L.w_y2.p + L.y2off[s], int(L.y2_tot));
+    if (c.opt.precision == 0) {
+      // Trn[0:nG, 0:nG] = -Z is symmetric
+      L.g2z.add(B + nl + int64_t(nl) * NN, NN, nG, L.w_rBs.p + L.Goff[s], int(L.nG_tot),
+                L.w_y2.p + L.y2off[s], int(L.y2_tot));
+      L.g2c.add(B + nl + int64_t(nl + nG) * NN, NN, nG, nl - nG, L.w_rBs.p + L.Goff[s],
+                int(L.nG_tot), L.w_y2.p + L.y2off[s] + nG, int(L.y2_tot));
+    }
     // -Psi u_c = (Trn[nG:nl, 0:nG])^T u_c
     L.g3.add(B + nl + nG + int64_t(nl) * NN, NN, L.nc[s], nG, L.w_ucl.p + L.cloff[s],
              int(std::max<int64_t>(L.cl_tot, 1)), L.w_y2.p + L.y2off[s], int(L.y2_tot));
@@ -301,6 +319,8 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
   }
   L.g1.finalize(st);
   L.g2.finalize(st);
+  L.g2z.finalize(st);
+  L.g2c.finalize(st);
   L.g3.finalize(st);
   L.g4.finalize(st);
 }
@@ -443,8 +463,13 @@ void check_ldlt(LdltOp& op, hipStream_t st, const char* what, int level) {
 // assemble K^s, weights, Schur complements (Section 2, Section 7)
 void numeric_schur(ambddc_ctx& c, Level& L, int li) {
   hipStream_t st = c.st;
-  L.aug.zero(st);
-  launch_assemble(L.am, L.emat, L.d_aug_off.p, L.d_augN.p, L.aug.p, st);
+  if (L.plain && L.augN_max <= 8192 && L.am.max_ne <= 64) {
+    // every column of the ns x ns blocks is assembled whole
+    launch_assemble_cols(L.am, L.augN_max, L.emat, L.d_aug_off.p, L.d_augN.p, L.aug.p, st);
+  } else {
+    L.aug.zero(st);
+    launch_assemble(L.am, L.emat, L.d_aug_off.p, L.d_augN.p, L.aug.p, st);
+  }
   // identity coupling Aug[ns + i, i] = Aug[i, ns + i] = 1, i < nI
   if (!L.plain) {
     std::vector<int> zero(L.nsub, 0);
@@ -459,6 +484,7 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
     for (int s = 0; s < L.nsub; ++s) {
       const double nI = L.nI[s], nG = L.nG[s];
       f += nI * nI * nI / 3.0 + nI * nI * nG + nI * nG * nG;
+      if (L.plain) f += nI * nI * nG;   // K_GI K_II^{-1} by the triangular solve
       b += 8.0 * (nI + nG) * (nI + nG);
     }
     c.kt.begin("schur", st);
@@ -1290,7 +1316,12 @@ void apply_level(ambddc_ctx& c, int li, const double* r, int64_t ldr, double* u,
                             r, ldr, harmonic ? nullptr : L.w_y1.p, L.y1_tot, L.w_rBs.p, L.nG_tot,
                             nrhs, st);
   // substructure corrections and coarse right-hand side
-  L.g2.run(1.0, 0.0, nrhs, st);
+  if (!L.g2z.empty() && nrhs <= SymvOp::MAX_RHS) {
+    L.g2z.run(1.0, 0.0, nrhs, st);
+    L.g2c.run(1.0, 0.0, nrhs, st);
+  } else {
+    L.g2.run(1.0, 0.0, nrhs, st);
+  }
   if (L.ncoarse > 0) {
     launch_segment_sum(L.ncoarse, L.cptr.p, L.cpos.p, L.w_y2.p, L.y2_tot, L.w_rc.p, L.ncoarse, nrhs,
                        -1.0, st);
@@ -1529,10 +1560,14 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
   double* rr = w.dot + 3 * nrhs;
   double* rzn = w.dot + 4 * nrhs;
   double* ff = w.dot + 5 * nrhs;
-  int hc[4] = {0, 0, 0, 0};
-  auto read_cnt = [&]() {
+  int* hc = c.hcnt;   // pinned: the copy runs in stream order without a staging sync
+  auto fetch_cnt = [&]() {
     AMB_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
-    AMB_HIP(hipStreamSynchronize(st));
+    AMB_HIP(hipEventRecord(c.ev_cnt, st));
+  };
+  auto read_cnt = [&]() {
+    fetch_cnt();
+    AMB_HIP(hipEventSynchronize(c.ev_cnt));
   };
   // x0 = the interior solution, so that every residual of the iteration is
   // zero on the level-1 interiors (discrete harmonic iterates: PCG on the
@@ -1563,9 +1598,13 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
       for (int s = 0; s < Lv.nsub; ++s) {
         const double nI = Lv.nI[s], nG = Lv.nG[s], ncs = Lv.nc[s];
         const double pre = li == 0 ? 0.0 : nI * nI + nI * nG;
+        // Z is symmetric: the FP64 path for up to 3 right-hand sides reads
+        // its lower triangle
+        const double zent = (c.opt.precision == 0 && nrhs <= SymvOp::MAX_RHS)
+                                ? nG * (nG + 1.0) / 2.0 : nG * nG;
         const double post = nI * nG, sub = nG * nG + 2.0 * nG * ncs;
         ent += pre + post + sub;
-        byt += esz * (pre + sub) + (li == 0 ? 8.0 : esz) * post;
+        byt += esz * (pre + sub - nG * nG + zent) + (li == 0 ? 8.0 : esz) * post;
       }
     }
     const double top = double(c.top.n) * c.top.n;   // the coarsest inverse stays FP64
@@ -1590,7 +1629,12 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
     launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, it, w.ldh, st);
     launch_dot_cols(n, nrhs, w.r, w.r, w.part, rr, st);
     launch_pcg_meets(nrhs, rr, ff, rtol2, w.act, w.nal, w.meets, w.cnt, it, st);
-    read_cnt();
+    // The counters travel back while the preconditioner of this residual is
+    // already queued: it stays valid unless a check below replaces columns of r.
+    fetch_cnt();
+    precondition();
+    launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, st);
+    AMB_HIP(hipEventSynchronize(c.ev_cnt));
     if (hc[0] > 0) {
       // The recursive residual drifts from f - K x by rounding (most on
       // ill-conditioned problems): recompute the true residual (q is free
@@ -1612,9 +1656,11 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
       nact = hc[1];
       repl += hc[2];
       if (nact == 0) break;
+      if (hc[2] > 0) {   // replaced residual columns: precondition them again
+        precondition();
+        launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, st);
+      }
     }
-    precondition();
-    launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, st);
     launch_pcg_update_p(n, nrhs, rzn, rz, w.act, w.repl, w.p, w.z, w.bh, it, w.ldh, st);
   }
   // iterations per column and the true residuals ||f - K x|| / ||f||
@@ -1835,6 +1881,9 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     auto c = std::make_unique<ambddc_ctx>();
     c->opt = *opt;
     c->st = static_cast<hipStream_t>(opt->stream);
+    AMB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hcnt), 4 * sizeof(int),
+                          hipHostMallocDefault));
+    AMB_HIP(hipEventCreateWithFlags(&c->ev_cnt, hipEventDisableTiming));
     c->n_nodes = mesh->n_nodes;
     c->n_elems = mesh->n_elems;
     c->dof = mesh->dof_per_node;
@@ -1909,6 +1958,8 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
         }
       c->csr.n = nf;
       c->csr.nnz = int64_t(cols.size());
+      for (int i = 0; i < nf; ++i)
+        c->csr.maxrow = std::max(c->csr.maxrow, rowptr[i + 1] - rowptr[i]);
       c->csr.rowptr.upload(rowptr, st);
       c->csr.cols.upload(cols, st);
       c->csr.inc_ptr.upload(incp, st);
