@@ -157,6 +157,24 @@ void launch_fill_values(int n, const int64_t* pos, const double* val, double* ds
   AMB_LAUNCH_CHECK();
 }
 
+// Adaptive rows of C: one wave per row copies the pair's face row from fc to
+// the row's interface positions (amap: local index of every face DOF).
+__global__ void k_fill_adaptive(int nrows, const AdaptRow* __restrict__ rows,
+                                const int* __restrict__ amap, const double* __restrict__ fc,
+                                double* C) {
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (w >= nrows) return;
+  const AdaptRow a = rows[w];
+  for (int q = lane; q < a.nf; q += 64) C[a.dst + int64_t(amap[a.map + q]) * a.ldc] = fc[a.src + q];
+}
+
+void launch_fill_adaptive(int nrows, const AdaptRow* rows, const int* amap, const double* fc,
+                          double* C, hipStream_t st) {
+  if (nrows == 0) return;
+  k_fill_adaptive<<<ceil_div(nrows, 4), 256, 0, st>>>(nrows, rows, amap, fc, C);
+  AMB_LAUNCH_CHECK();
+}
+
 // Leading (nG+nc) block of [[S + rho C^T C, C^T, I, 0], [C, 0, 0, I], [I, 0, 0, 0], [0, I, 0, 0]]
 // one workgroup per column of the leading block; the identity coupling is
 // written by the same workgroup.

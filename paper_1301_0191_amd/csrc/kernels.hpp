@@ -70,6 +70,13 @@ void launch_average(int nG, const int* gdof, const int* inc_ptr, const int* inc_
 void launch_segment_sum(int n, const int* ptr, const int64_t* pos, const double* src, int64_t lds,
                         double* dst, int64_t ldd, int nrhs, double scale, hipStream_t st);
 // dense constraint matrices from entry lists
+// One adaptive row of C^s: C[dst + amap[map + q] * ldc] = fc[src + q], q < nf.
+struct AdaptRow {
+  int64_t dst, src, map;
+  int ldc, nf;
+};
+void launch_fill_adaptive(int nrows, const AdaptRow* rows, const int* amap, const double* fc,
+                          double* C, hipStream_t st);
 void launch_fill_values(int n, const int64_t* pos, const double* val, double* dst, hipStream_t st);
 // Neumann augmented matrices
 struct NeuDesc {

@@ -39,9 +39,10 @@ struct Level {
   int64_t c_total = 0, naug_total = 0, kc_total = 0, y2_tot = 0, cl_tot = 0;
   int ncoarse = 0;
   DBuf<double> C, naug, kc;
-  DBuf<int64_t> d_naug_off, d_kc_off, cpos, clmap, cfill_pos, cadapt_pos;
+  DBuf<int64_t> d_naug_off, d_kc_off, cpos, clmap, cfill_pos;
   DBuf<double> cfill_val;
-  DBuf<int64_t> cadapt_src;
+  DBuf<AdaptRow> cadapt_rows;   // adaptive rows of C and their face DOF maps
+  DBuf<int> cadapt_map;
   DBuf<int> d_nc, d_nl, d_naugN, cptr;
   DBuf<NeuDesc> neu;
   int neu_cols = 0;

@@ -20,6 +20,12 @@ namespace {
 
 thread_local std::string g_err;
 
+// Position of dof in the ascending range [b, e), or -1.
+int find_sorted(const int* b, const int* e, int dof) {
+  const int* it = std::lower_bound(b, e, dof);
+  return (it != e && *it == dof) ? int(it - b) : -1;
+}
+
 struct LocalIndex {   // sorted (dof, local) pairs of one subdomain
   std::vector<std::pair<int, int>> v;
   void build(const std::vector<int>& dofs) {
@@ -357,32 +363,47 @@ void build_constraint_maps(ambddc_ctx& c, Level& L) {
   L.d_nc.upload(L.nc, st);
   L.d_nl.upload(L.nl, st);
   L.d_naugN.upload(L.naugN, st);
-  // C entries: initial constraints get 1 or 1/m, adaptive ones copy from fc
-  std::vector<int64_t> fpos, apos, asrc;
+  // C entries: initial constraints get 1 or 1/m; adaptive rows copy their
+  // pair's face row from fc (every row of a pair has the pair's face DOFs,
+  // whose local indices are looked up once per subdomain and pair)
+  std::vector<int64_t> fpos;
   std::vector<double> fval;
+  std::vector<AdaptRow> arows;
+  std::vector<int> amap;
   std::vector<int64_t> g2y2(L.nG_tot);
-  std::vector<LocalIndex> gl(ns);
-  for (int s = 0; s < ns; ++s) {
-    std::vector<int> G(P.subs[s].dofs.begin() + L.nI[s], P.subs[s].dofs.end());
-    gl[s].build(G);
+  for (int s = 0; s < ns; ++s)
     for (int i = 0; i < L.nG[s]; ++i) g2y2[L.Goff[s] + i] = L.y2off[s] + i;
-  }
   std::vector<int> cptr(L.ncoarse + 1, 0);
   for (int s = 0; s < ns; ++s) {
     const auto& cs = P.subs[s].cons;
+    const int* G0 = P.subs[s].dofs.data() + L.nI[s];   // interface DOFs, ascending
+    const int* G1 = G0 + L.nG[s];
+    auto local = [&](int dof) {
+      const int i = find_sorted(G0, G1, dof);
+      if (i < 0) throw Error(AMBDDC_E_INVALID_ARG, "constraint DOF outside the interface");
+      return i;
+    };
+    std::vector<std::pair<int, int64_t>> pair_map;   // (pair, offset in amap)
     for (int r = 0; r < L.nc[s]; ++r) {
       const Constraint& K = P.cons[cs[r]];
       cptr[cs[r] + 1]++;
-      for (size_t q = 0; q < K.dofs.size(); ++q) {
-        const int i = gl[s].find(K.dofs[q]);
-        if (i < 0) throw Error(AMBDDC_E_INVALID_ARG, "constraint DOF outside the interface");
-        const int64_t pos = L.c_off[s] + r + int64_t(i) * L.nc[s];
-        if (K.kind == CONS_ADAPT) {
-          apos.push_back(pos);
-          asrc.push_back(L.fc_off[K.pair] + int64_t(K.row) * L.face_nf[K.pair] + int64_t(q));
-        } else {
-          fpos.push_back(pos);
-          fval.push_back(K.kind == CONS_UNIT ? 1.0 : 1.0 / double(K.dofs.size()));
+      if (K.kind == CONS_ADAPT) {
+        int64_t off = -1;
+        for (const auto& pm : pair_map)
+          if (pm.first == K.pair) off = pm.second;
+        if (off < 0) {
+          off = int64_t(amap.size());
+          for (int d : K.dofs) amap.push_back(local(d));
+          pair_map.push_back({K.pair, off});
+        }
+        arows.push_back(AdaptRow{L.c_off[s] + r,
+                                 L.fc_off[K.pair] + int64_t(K.row) * L.face_nf[K.pair], off,
+                                 L.nc[s], int(K.dofs.size())});
+      } else {
+        const double v = K.kind == CONS_UNIT ? 1.0 : 1.0 / double(K.dofs.size());
+        for (int d : K.dofs) {
+          fpos.push_back(L.c_off[s] + r + int64_t(local(d)) * L.nc[s]);
+          fval.push_back(v);
         }
       }
     }
@@ -401,8 +422,8 @@ void build_constraint_maps(ambddc_ctx& c, Level& L) {
   }
   L.cfill_pos.upload(fpos, st);
   L.cfill_val.upload(fval, st);
-  L.cadapt_pos.upload(apos, st);
-  L.cadapt_src.upload(asrc, st);
+  L.cadapt_rows.upload(arows, st);
+  L.cadapt_map.upload(amap, st);
   L.cptr.upload(cptr, st);
   L.cpos.upload(cpos, st);
   L.clmap.upload(clmap, st);
@@ -510,12 +531,7 @@ void numeric_schur(ambddc_ctx& c, Level& L, int li) {
 void fill_constraints(Level& L, hipStream_t st) {
   L.C.zero(st);
   launch_fill_values(int(L.cfill_pos.n), L.cfill_pos.p, L.cfill_val.p, L.C.p, st);
-  if (L.cadapt_pos.n) {
-    DBuf<double> tmp;
-    tmp.alloc(L.cadapt_pos.n);
-    launch_gather(int(L.cadapt_pos.n), L.cadapt_src.p, L.fc.p, 0, tmp.p, 0, 1, 1.0, st);
-    launch_fill_values(int(L.cadapt_pos.n), L.cadapt_pos.p, tmp.p, L.C.p, st);
-  }
+  launch_fill_adaptive(int(L.cadapt_rows.n), L.cadapt_rows.p, L.cadapt_map.p, L.fc.p, L.C.p, st);
 }
 
 void numeric_neumann(ambddc_ctx& c, Level& L, int li) {
@@ -725,11 +741,11 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
   }
   std::vector<int> sh_s, sh_t, pc_s, pc_t, face_s, dptr{0}, didx;
   std::vector<int64_t> dcpos;
-  std::vector<LocalIndex> gl(L.nsub);
-  for (int s = 0; s < L.nsub; ++s) {
-    std::vector<int> G(P.subs[s].dofs.begin() + L.nI[s], P.subs[s].dofs.end());
-    gl[s].build(G);
-  }
+  // local interface index of a DOF (the interface DOFs are ascending)
+  auto gfind = [&](int s, int dof) {
+    const int* G0 = P.subs[s].dofs.data() + L.nI[s];
+    return find_sorted(G0, G0 + L.nG[s], dof);
+  };
   int64_t voff = 0, kpoff = 0, rboff = 0, fcoff = 0;
   W.hp.resize(W.np);
   L.fc_off.assign(W.np, 0);
@@ -765,7 +781,7 @@ void build_pair_work(ambddc_ctx& c, Level& L, int li, PairWork& W) {
     for (size_t r = 0; r < Q.dr_s.size(); ++r) {
       const Constraint& K = P.cons[P.subs[Q.s].cons[Q.dr_s[r]]];
       for (int j : K.dofs) {
-        const int is = gl[Q.s].find(j), it = gl[Q.t].find(j);
+        const int is = gfind(Q.s, j), it = gfind(Q.t, j);
         if (is < 0 || it < 0) throw Error(AMBDDC_E_INVALID_ARG, "shared constraint outside a pair");
         didx.push_back(is);
         dcpos.push_back(L.c_off[Q.s] + Q.dr_s[r] + int64_t(is) * L.nc[Q.s]);
