@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmDesc* __restrict__ d
 }
 
 template <bool TA, bool TB, int WM, int WN, typename TAe>
-__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ d, int nd, double alpha,
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(const GemmDesc* __restrict__ d, int nd, double alpha,
                                               double beta, const int* __restrict__ act, int mask,
                                               int excl) {
   __shared__ TileSmem<WM, WN> sm;
@@ -997,6 +997,14 @@ void TrsmOp::run(hipStream_t st) const {
 
 constexpr int TRSV_THREADS = 1024;
 
+// v of lane l (l uniform across the wave).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b), l));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), l));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // One workgroup per matrix, all R right-hand sides together (L is read once
 // per pass).  Block q of 64 rows: the 16 waves take every 16th solved column
 // (lanes = the block's rows, eight columns in flight per wave) and meet in
@@ -1064,20 +1072,30 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_chol(const TrsvDesc* __re
       __syncthreads();
       // diagonal block: L y = z (forward) or L^T y = z (backward); waves
       // 0..R-1 take one right-hand side each, one lane per row
+      // (each lane holds the reciprocal of its diagonal entry; the solved
+      // value of row k is read from lane k by v_readlane)
       if (wave < R) {
         const int r = wave;
         double z = 0.0;
+        const double dinv = lane < w ? 1.0 / Ld[lane][lane] : 0.0;
         if (lane < w) z = x[(size_t)r * ldx + r0 + lane] - zb[r][lane];
+        // the next step's entry of L is loaded one step ahead
         if (pass == 0) {
+          double ln = Ld[lane][0];
           for (int k = 0; k < w; ++k) {
-            const double yk = __shfl(z / Ld[k][k], k);
-            if (lane > k && lane < w) z -= Ld[lane][k] * yk;
+            const double lk = ln;
+            if (k + 1 < w) ln = Ld[lane][k + 1];
+            const double yk = readlane_f64(z * dinv, k);
+            if (lane > k && lane < w) z -= lk * yk;
             if (lane == k) z = yk;
           }
         } else {
+          double ln = Ld[w - 1][lane];
           for (int k = w - 1; k >= 0; --k) {
-            const double yk = __shfl(z / Ld[k][k], k);
-            if (lane < k) z -= Ld[k][lane] * yk;
+            const double lk = ln;
+            if (k > 0) ln = Ld[k - 1][lane];
+            const double yk = readlane_f64(z * dinv, k);
+            if (lane < k) z -= lk * yk;
             if (lane == k) z = yk;
           }
         }

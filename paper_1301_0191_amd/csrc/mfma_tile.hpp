@@ -1,6 +1,6 @@
 // One workgroup tile of C = alpha * op(A) * diag(sigma) * op(B) + beta * C on
-// CDNA MFMA (v_mfma_f64_16x16x4f64), FP64.  256 threads = 4 waves arranged
-// WM x WN; every wave owns a 32x32 sub-tile (2x2 MFMA blocks).  K is staged
+// CDNA MFMA (v_mfma_f64_16x16x4f64), FP64.  64 WM WN threads = WM x WN waves;
+// every wave owns a 32x32 sub-tile (2x2 MFMA blocks).  K is staged
 // through LDS in chunks of KC so that global reads are coalesced for either
 // operand orientation; the staging is double-buffered: the next chunk is
 // loaded into registers while the current one feeds the MFMAs, then stored
@@ -61,7 +61,8 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
                                           double beta, int sign_split, TileSmem<WM, WN>& sm) {
   using S = TileShape<WM, WN>;
   constexpr int TM = S::TM, TN = S::TN, KC = S::KC;
-  constexpr int NA = KC * TM / 256, NB = KC * TN / 256;   // staged values per thread
+  constexpr int NT = 64 * WM * WN;                       // threads: one wave per 32 x 32
+  constexpr int NA = KC * TM / NT, NB = KC * TN / NT;   // staged values per thread
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -77,7 +78,7 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int idx = tid + u * 256;
+      const int idx = tid + u * NT;
       int m, k;
       if (!TA) { m = idx % TM; k = idx / TM; }
       else { k = idx % KC; m = idx / KC; }
@@ -93,7 +94,7 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = tid + u * 256;
+      const int idx = tid + u * NT;
       int n, k;
       if (TB) { n = idx % TN; k = idx / TN; }
       else { k = idx % KC; n = idx / KC; }
@@ -107,7 +108,7 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
   auto sstore = [&](int buf, int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int idx = tid + u * 256;
+      const int idx = tid + u * NT;
       int m, k;
       if (!TA) { m = idx % TM; k = idx / TM; }
       else { k = idx % KC; m = idx / KC; }
@@ -117,7 +118,7 @@ __device__ __forceinline__ void mfma_tile(const TAe* __restrict__ A, int lda,
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = tid + u * 256;
+      const int idx = tid + u * NT;
       int n, k;
       if (TB) { n = idx % TN; k = idx / TN; }
       else { k = idx % KC; n = idx / KC; }
