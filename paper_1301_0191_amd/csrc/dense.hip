@@ -897,9 +897,15 @@ int LdltOp::failed(hipStream_t st) {
 
 // Step t, block column jb = nb - 1 - t of every active matrix:
 // B[:, jb] -= X[:, jb+1..] L[jb+1.., jb], one 64 x 64 MFMA tile per workgroup.
+// With npc > 1 pieces the sum over K is split: piece 0 updates B in place,
+// piece p > 0 writes -X[:, Kp] L[Kp, jb] to the partial buffer (leading
+// dimension nG), which the solve adds in piece order.
 __global__ __launch_bounds__(256) void k_trsm_update(const TrsmDesc* __restrict__ d,
                                                      const int* __restrict__ act,
-                                                     const int* __restrict__ pre, int nact, int t) {
+                                                     const int* __restrict__ pre,
+                                                     const int* __restrict__ npc,
+                                                     const int64_t* __restrict__ woff,
+                                                     double* __restrict__ part, int nact, int t) {
   __shared__ TileSmem<2, 2> sm;
   const int a = find_active(pre, nact, blockIdx.x);
   const TrsmDesc g = d[act[a]];
@@ -908,19 +914,43 @@ __global__ __launch_bounds__(256) void k_trsm_update(const TrsmDesc* __restrict_
   const int nb = (g.nI + TB - 1) / TB;
   const int jb = nb - 1 - t;
   const int c0 = jb * TB, w = min(TB, g.nI - c0), k0 = c0 + w;
+  const int tiles_m = (g.nG + 63) / 64;
+  const int S = npc[a], chunk = l % tiles_m, piece = l / tiles_m;
+  const int K = g.nI - k0;
+  // piece boundaries on multiples of 64
+  const int kp0 = piece == 0 ? 0 : (int(int64_t(K) * piece / S) & ~63);
+  const int kp1 = piece == S - 1 ? K : (int(int64_t(K) * (piece + 1) / S) & ~63);
   double* B = g.A + g.nI;                       // rows nI.., column 0
-  mfma_tile<false, false, 2, 2>(B + (size_t)k0 * g.lda, g.lda, g.A + k0 + (size_t)c0 * g.lda,
-                                g.lda, B + (size_t)c0 * g.lda, g.lda, g.nG, w, g.nI - k0, l * 64, 0,
-                                -1.0, 1.0, -1, sm);
+  double* C;
+  int ldc;
+  double beta;
+  if (piece == 0) {
+    C = B + (size_t)c0 * g.lda;
+    ldc = g.lda;
+    beta = 1.0;
+  } else {
+    C = part + woff[a] + (int64_t)(piece - 1) * g.nG * TB;
+    ldc = g.nG;
+    beta = 0.0;
+  }
+  mfma_tile<false, false, 2, 2>(B + (size_t)(k0 + kp0) * g.lda, g.lda,
+                                g.A + k0 + kp0 + (size_t)c0 * g.lda, g.lda, C, ldc, g.nG, w,
+                                kp1 - kp0, chunk * 64, 0, -1.0, beta, -1, sm);
 }
 
-// Step t: every row x of B[:, jb] solves x L[jb, jb] = b (back substitution
-// over the block's columns); L's block in LDS, the row in registers.
+// Step t: every row x of B[:, jb] (plus the partial products of the update)
+// solves x L[jb, jb] = b (back substitution over the block's columns); L's
+// block and the reciprocals of its diagonal in LDS, the row in registers.
 __global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__ d,
                                                     const int* __restrict__ act,
-                                                    const int* __restrict__ pre, int nact, int t) {
+                                                    const int* __restrict__ pre,
+                                                    const int* __restrict__ npc,
+                                                    const int64_t* __restrict__ woff,
+                                                    const double* __restrict__ part, int nact,
+                                                    int t) {
   constexpr int TB = TrsmOp::TB;
   __shared__ double Ld[TB][TB + 1];
+  __shared__ double dinv[TB];
   const int a = find_active(pre, nact, blockIdx.x);
   const TrsmDesc g = d[act[a]];
   const int chunk = blockIdx.x - pre[a];
@@ -931,6 +961,9 @@ __global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__
     const int r = i % TB, c = i / TB;
     Ld[r][c] = (r < w && c < w && r >= c) ? g.A[(c0 + r) + (size_t)(c0 + c) * g.lda] : 0.0;
   }
+  if (threadIdx.x < TB)
+    dinv[threadIdx.x] =
+        threadIdx.x < w ? 1.0 / g.A[(c0 + threadIdx.x) + (size_t)(c0 + threadIdx.x) * g.lda] : 0.0;
   __syncthreads();
   const int row = chunk * 256 + threadIdx.x;
   if (row >= g.nG) return;
@@ -938,13 +971,20 @@ __global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__
   double x[TB];
 #pragma unroll
   for (int j = 0; j < TB; ++j) x[j] = j < w ? b[(size_t)j * g.lda] : 0.0;
+  const int S = npc[a];
+  for (int p = 1; p < S; ++p) {
+    const double* q = part + woff[a] + (int64_t)(p - 1) * g.nG * TB + row;
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+      if (j < w) x[j] += q[(size_t)j * g.nG];
+  }
 #pragma unroll
   for (int k = TB - 1; k >= 0; --k) {
     if (k < w) {
       double v = x[k];
 #pragma unroll
       for (int i = k + 1; i < TB; ++i) v -= x[i] * Ld[i][k];
-      x[k] = v / Ld[k][k];
+      x[k] = v * dinv[k];
     }
   }
 #pragma unroll
@@ -956,9 +996,21 @@ void TrsmOp::finalize(hipStream_t st) {
   steps.clear();
   int maxb = 0;
   for (const auto& g : h) maxb = std::max(maxb, ceil_div(g.nI, TB));
-  std::vector<int> a, up, sp;
+  std::vector<int> a, up, sp, pc;
+  std::vector<int64_t> wo;
+  int64_t wmax = 0;
   for (int t = 0; t < maxb; ++t) {
     Step f{t, int(a.size()), 0, 0, 0};
+    // update tiles of this step without a split
+    int tiles1 = 0;
+    for (const auto& g : h) {
+      const int nb = ceil_div(g.nI, TB);
+      if (nb <= t) continue;
+      const int k0 = std::min(g.nI, (nb - t) * TB);
+      if (k0 < g.nI) tiles1 += ceil_div(g.nG, 64);
+    }
+    const int want = tiles1 > 0 ? ceil_div(SPLIT_TILES, tiles1) : 1;
+    int64_t wstep = 0;
     for (size_t i = 0; i < h.size(); ++i) {
       const auto& g = h[i];
       const int nb = ceil_div(g.nI, TB);
@@ -968,25 +1020,37 @@ void TrsmOp::finalize(hipStream_t st) {
       sp.push_back(f.sol_total);
       const int jb = nb - 1 - t;
       const int k0 = std::min(g.nI, (jb + 1) * TB);
-      if (k0 < g.nI) f.upd_total += ceil_div(g.nG, 64);
+      const int K = g.nI - k0;
+      // pieces of at least 256 of K, at most 8
+      const int S = K > 0 ? std::max(1, std::min({want, K / 256, 8})) : 1;
+      pc.push_back(S);
+      wo.push_back(wstep);
+      wstep += int64_t(S - 1) * g.nG * TB;
+      if (K > 0) f.upd_total += ceil_div(g.nG, 64) * S;
       f.sol_total += ceil_div(g.nG, 256);
       ++f.nact;
     }
+    wmax = std::max(wmax, wstep);
     steps.push_back(f);
   }
   d.upload(h, st);
   act.upload(a, st);
   upd_pre.upload(up, st);
   sol_pre.upload(sp, st);
+  npc.upload(pc, st);
+  woff.upload(wo, st);
+  part.alloc(size_t(std::max<int64_t>(wmax, 1)));
 }
 
 void TrsmOp::run(hipStream_t st) const {
   for (const Step& f : steps) {
     if (f.nact == 0) continue;
     if (f.upd_total > 0)
-      k_trsm_update<<<f.upd_total, 256, 0, st>>>(d.p, act.p + f.off, upd_pre.p + f.off, f.nact,
+      k_trsm_update<<<f.upd_total, 256, 0, st>>>(d.p, act.p + f.off, upd_pre.p + f.off,
+                                                 npc.p + f.off, woff.p + f.off, part.p, f.nact,
                                                  f.t);
-    k_trsm_solve<<<f.sol_total, 256, 0, st>>>(d.p, act.p + f.off, sol_pre.p + f.off, f.nact, f.t);
+    k_trsm_solve<<<f.sol_total, 256, 0, st>>>(d.p, act.p + f.off, sol_pre.p + f.off,
+                                              npc.p + f.off, woff.p + f.off, part.p, f.nact, f.t);
   }
   AMB_LAUNCH_CHECK();
 }

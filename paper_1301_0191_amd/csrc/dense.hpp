@@ -253,6 +253,8 @@ struct TrsmDesc {
 class TrsmOp {
  public:
   static constexpr int TB = 64;
+  // a step whose updates have fewer tiles than this splits K into pieces
+  static constexpr int SPLIT_TILES = 1024;
   std::vector<TrsmDesc> h;
   DBuf<TrsmDesc> d;
   struct Step {
@@ -260,6 +262,11 @@ class TrsmOp {
   };
   std::vector<Step> steps;
   DBuf<int> act, upd_pre, sol_pre;
+  // per step and active matrix: K pieces of the update (piece 0 updates B in
+  // place, piece p > 0 writes its product at woff + (p - 1) nG TB of part)
+  DBuf<int> npc;
+  DBuf<int64_t> woff;
+  DBuf<double> part;
   void add(double* A, int lda, int nI, int nG) {
     if (nI > 0 && nG > 0) h.push_back(TrsmDesc{A, lda, nI, nG});
   }
