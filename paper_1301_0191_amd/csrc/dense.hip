@@ -343,6 +343,49 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvDesc* __restrict__ d, 
   }
 }
 
+// Short columns (K <= SHORT_K): a group of 16 lanes per output column, 16
+// columns per workgroup; no lane leaves before the group reductions.
+template <int R>
+__global__ __launch_bounds__(256) void k_gemv_t16(const GemvDesc* __restrict__ d, int nd,
+                                                  double alpha, double beta) {
+  constexpr int G = 16;
+  const int wg = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
+  }
+  const GemvDesc g = d[lo];
+  const int col = (wg - g.wg_start) * (256 / G) + int(threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool ok = col < g.M;
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  if (ok) {
+    const double* __restrict__ a = static_cast<const double*>(g.A) + (size_t)col * g.lda;
+    for (int i = lane; i < g.K; i += G) {
+      const double av = a[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += av * g.X[i + (size_t)r * g.ldx];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = acc[r];
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    acc[r] = v;
+  }
+  if (ok && lane < R) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r == lane) v = acc[r];
+    double* y = g.Y + col + (size_t)lane * g.ldy;
+    *y = alpha * v + (beta != 0.0 ? beta * (*y) : 0.0);
+  }
+}
+
 // --------------------------------------------------------------------------
 // Symmetric GEMV from the tiles on or below the diagonal
 // --------------------------------------------------------------------------
@@ -630,10 +673,13 @@ void GemvOp::pack_a_f32(DBuf<float>& store, hipStream_t st) {
 }
 
 void GemvOp::finalize(hipStream_t st) {
+  int kmax = 0;
+  for (const auto& g : h) kmax = std::max(kmax, g.K);
+  short_k = !a32 && kmax <= SHORT_K;
   wgs = 0;
   for (auto& g : h) {
     g.wg_start = wgs;
-    wgs += a32 ? ceil_div(g.M, GN_ROWS) : ceil_div(g.M, 4);
+    wgs += a32 ? ceil_div(g.M, GN_ROWS) : short_k ? ceil_div(g.M, 16) : ceil_div(g.M, 4);
   }
   d.upload(h, st);
 }
@@ -662,6 +708,16 @@ void GemvOp::run(double alpha, double beta, int nrhs, hipStream_t st) const {
       case 1: k_gemv_n32<1><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
       case 2: k_gemv_n32<2><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
       case 3: k_gemv_n32<3><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+      default: throw Error(1, "GemvOp: nrhs must be in 1..16");
+    }
+    AMB_LAUNCH_CHECK();
+    return;
+  }
+  if (short_k) {
+    switch (nrhs) {
+      case 1: k_gemv_t16<1><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+      case 2: k_gemv_t16<2><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
+      case 3: k_gemv_t16<3><<<wgs, 256, 0, st>>>(d.p, nd, alpha, beta); break;
       default: throw Error(1, "GemvOp: nrhs must be in 1..16");
     }
     AMB_LAUNCH_CHECK();
@@ -895,68 +951,46 @@ int LdltOp::failed(hipStream_t st) {
 // Right-side triangular solve X L = B (TrsmOp)
 // --------------------------------------------------------------------------
 
-// Step t, block column jb = nb - 1 - t of every active matrix:
-// B[:, jb] -= X[:, jb+1..] L[jb+1.., jb], one 64 x 64 MFMA tile per workgroup.
-// With npc > 1 pieces the sum over K is split: piece 0 updates B in place,
-// piece p > 0 writes -X[:, Kp] L[Kp, jb] to the partial buffer (leading
-// dimension nG), which the solve adds in piece order.
-__global__ __launch_bounds__(256) void k_trsm_update(const TrsmDesc* __restrict__ d,
-                                                     const int* __restrict__ act,
-                                                     const int* __restrict__ pre,
-                                                     const int* __restrict__ npc,
-                                                     const int64_t* __restrict__ woff,
-                                                     double* __restrict__ part, int nact, int t) {
-  __shared__ TileSmem<2, 2> sm;
-  const int a = find_active(pre, nact, blockIdx.x);
-  const TrsmDesc g = d[act[a]];
-  const int l = blockIdx.x - pre[a];
-  constexpr int TB = TrsmOp::TB;
-  const int nb = (g.nI + TB - 1) / TB;
-  const int jb = nb - 1 - t;
-  const int c0 = jb * TB, w = min(TB, g.nI - c0), k0 = c0 + w;
-  const int tiles_m = (g.nG + 63) / 64;
-  const int S = npc[a], chunk = l % tiles_m, piece = l / tiles_m;
-  const int K = g.nI - k0;
-  // piece boundaries on multiples of 64
-  const int kp0 = piece == 0 ? 0 : (int(int64_t(K) * piece / S) & ~63);
-  const int kp1 = piece == S - 1 ? K : (int(int64_t(K) * (piece + 1) / S) & ~63);
-  double* B = g.A + g.nI;                       // rows nI.., column 0
-  double* C;
-  int ldc;
-  double beta;
-  if (piece == 0) {
-    C = B + (size_t)c0 * g.lda;
-    ldc = g.lda;
-    beta = 1.0;
-  } else {
-    C = part + woff[a] + (int64_t)(piece - 1) * g.nG * TB;
-    ldc = g.nG;
-    beta = 0.0;
+// Record lookup of a launch: the last record whose first workgroup is at or
+// before this one.
+__device__ __forceinline__ int find_rec(const TrsmOp::Rec* __restrict__ r, int n, int wg) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r[mid].start <= wg) lo = mid; else hi = mid - 1;
   }
-  mfma_tile<false, false, 2, 2>(B + (size_t)(k0 + kp0) * g.lda, g.lda,
-                                g.A + k0 + kp0 + (size_t)c0 * g.lda, g.lda, C, ldc, g.nG, w,
-                                kp1 - kp0, chunk * 64, 0, -1.0, beta, -1, sm);
+  return lo;
 }
 
-// Step t: every row x of B[:, jb] (plus the partial products of the update)
-// solves x L[jb, jb] = b (back substitution over the block's columns); L's
-// block and the reciprocals of its diagonal in LDS, the row in registers.
+// B[:, c0:c0+w] -= X[:, kb:ke] L[kb:ke, c0:c0+w] (X = the solved columns of
+// B), one 64 x 64 MFMA tile per workgroup.
+__global__ __launch_bounds__(256) void k_trsm_update(const TrsmDesc* __restrict__ d,
+                                                     const TrsmOp::Rec* __restrict__ recs, int n) {
+  __shared__ TileSmem<2, 2> sm;
+  const TrsmOp::Rec r = recs[find_rec(recs, n, blockIdx.x)];
+  const TrsmDesc g = d[r.m];
+  const int l = blockIdx.x - r.start;
+  const int tiles_m = (g.nG + 63) / 64;
+  const int tm = l % tiles_m, tn = l / tiles_m;
+  const int c = r.c0 + tn * 64, w = min(64, r.c0 + r.w - c);
+  double* B = g.A + g.nI;                       // rows nI.., column 0
+  mfma_tile<false, false, 2, 2>(B + (size_t)r.kb * g.lda, g.lda, g.A + r.kb + (size_t)c * g.lda,
+                                g.lda, B + (size_t)c * g.lda, g.lda, g.nG, w, r.ke - r.kb, tm * 64,
+                                0, -1.0, 1.0, -1, sm);
+}
+
+// Every row x of B[:, c0:c0+w] (w <= TB) solves x L[c0:c0+w, c0:c0+w] = b
+// (back substitution over the block's columns); L's block and the
+// reciprocals of its diagonal in LDS, the row in registers.
 __global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__ d,
-                                                    const int* __restrict__ act,
-                                                    const int* __restrict__ pre,
-                                                    const int* __restrict__ npc,
-                                                    const int64_t* __restrict__ woff,
-                                                    const double* __restrict__ part, int nact,
-                                                    int t) {
+                                                    const TrsmOp::Rec* __restrict__ recs, int n) {
   constexpr int TB = TrsmOp::TB;
   __shared__ double Ld[TB][TB + 1];
   __shared__ double dinv[TB];
-  const int a = find_active(pre, nact, blockIdx.x);
-  const TrsmDesc g = d[act[a]];
-  const int chunk = blockIdx.x - pre[a];
-  const int nb = (g.nI + TB - 1) / TB;
-  const int jb = nb - 1 - t;
-  const int c0 = jb * TB, w = min(TB, g.nI - c0);
+  const TrsmOp::Rec rc = recs[find_rec(recs, n, blockIdx.x)];
+  const TrsmDesc g = d[rc.m];
+  const int chunk = blockIdx.x - rc.start;
+  const int c0 = rc.c0, w = rc.w;
   for (int i = threadIdx.x; i < TB * TB; i += 256) {
     const int r = i % TB, c = i / TB;
     Ld[r][c] = (r < w && c < w && r >= c) ? g.A[(c0 + r) + (size_t)(c0 + c) * g.lda] : 0.0;
@@ -971,13 +1005,6 @@ __global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__
   double x[TB];
 #pragma unroll
   for (int j = 0; j < TB; ++j) x[j] = j < w ? b[(size_t)j * g.lda] : 0.0;
-  const int S = npc[a];
-  for (int p = 1; p < S; ++p) {
-    const double* q = part + woff[a] + (int64_t)(p - 1) * g.nG * TB + row;
-#pragma unroll
-    for (int j = 0; j < TB; ++j)
-      if (j < w) x[j] += q[(size_t)j * g.nG];
-  }
 #pragma unroll
   for (int k = TB - 1; k >= 0; --k) {
     if (k < w) {
@@ -992,65 +1019,75 @@ __global__ __launch_bounds__(256) void k_trsm_solve(const TrsmDesc* __restrict__
     if (j < w) b[(size_t)j * g.lda] = x[j];
 }
 
+// Columns are taken from the right in groups of GB blocks of TB: the group
+// first takes all solved columns to its right in one wide update, then its
+// blocks, right to left, take the solved blocks of the group (a narrow
+// update) and are solved.  Matrices run in lockstep by group and sub-step.
 void TrsmOp::finalize(hipStream_t st) {
-  steps.clear();
-  int maxb = 0;
-  for (const auto& g : h) maxb = std::max(maxb, ceil_div(g.nI, TB));
-  std::vector<int> a, up, sp, pc;
-  std::vector<int64_t> wo;
-  int64_t wmax = 0;
-  for (int t = 0; t < maxb; ++t) {
-    Step f{t, int(a.size()), 0, 0, 0};
-    // update tiles of this step without a split
-    int tiles1 = 0;
-    for (const auto& g : h) {
-      const int nb = ceil_div(g.nI, TB);
-      if (nb <= t) continue;
-      const int k0 = std::min(g.nI, (nb - t) * TB);
-      if (k0 < g.nI) tiles1 += ceil_div(g.nG, 64);
+  launches.clear();
+  std::vector<Rec> all;
+  int maxg = 0;
+  for (const auto& g : h) maxg = std::max(maxg, ceil_div(ceil_div(g.nI, TB), GB));
+  auto open = [&](bool solve) {
+    launches.push_back(Launch{solve, int(all.size()), 0, 0});
+  };
+  auto push = [&](int m, int c0, int w, int kb, int ke, bool solve) {
+    Launch& L = launches.back();
+    const auto& g = h[m];
+    const int wgs = solve ? ceil_div(g.nG, 256) : ceil_div(g.nG, 64) * ceil_div(w, 64);
+    all.push_back(Rec{m, c0, w, kb, ke, L.wgs});
+    L.wgs += wgs;
+    ++L.n;
+  };
+  for (int og = 0; og < maxg; ++og) {
+    // wide update of the group with everything solved to its right
+    open(false);
+    for (size_t m = 0; m < h.size(); ++m) {
+      const auto& g = h[m];
+      const int nb = ceil_div(g.nI, TB), ng = ceil_div(nb, GB);
+      if (og >= ng) continue;
+      const int jhi = nb - 1 - og * GB, jlo = std::max(0, jhi - GB + 1);
+      const int c0 = jlo * TB, c1 = std::min(g.nI, (jhi + 1) * TB);
+      if (c1 < g.nI) push(int(m), c0, c1 - c0, c1, g.nI, false);
     }
-    const int want = tiles1 > 0 ? ceil_div(SPLIT_TILES, tiles1) : 1;
-    int64_t wstep = 0;
-    for (size_t i = 0; i < h.size(); ++i) {
-      const auto& g = h[i];
-      const int nb = ceil_div(g.nI, TB);
-      if (nb <= t) continue;
-      a.push_back(int(i));
-      up.push_back(f.upd_total);
-      sp.push_back(f.sol_total);
-      const int jb = nb - 1 - t;
-      const int k0 = std::min(g.nI, (jb + 1) * TB);
-      const int K = g.nI - k0;
-      // pieces of at least 256 of K, at most 8
-      const int S = K > 0 ? std::max(1, std::min({want, K / 256, 8})) : 1;
-      pc.push_back(S);
-      wo.push_back(wstep);
-      wstep += int64_t(S - 1) * g.nG * TB;
-      if (K > 0) f.upd_total += ceil_div(g.nG, 64) * S;
-      f.sol_total += ceil_div(g.nG, 256);
-      ++f.nact;
+    for (int i = 0; i < GB; ++i) {
+      // block jhi - i: narrow update with the group's solved blocks, solve
+      open(false);
+      for (size_t m = 0; m < h.size(); ++m) {
+        const auto& g = h[m];
+        const int nb = ceil_div(g.nI, TB), ng = ceil_div(nb, GB);
+        if (og >= ng) continue;
+        const int jhi = nb - 1 - og * GB, j = jhi - i;
+        if (j < 0 || i == 0) continue;
+        const int c0 = j * TB, c1 = std::min(g.nI, (jhi + 1) * TB);
+        push(int(m), c0, TB, c0 + TB, c1, false);
+      }
+      open(true);
+      for (size_t m = 0; m < h.size(); ++m) {
+        const auto& g = h[m];
+        const int nb = ceil_div(g.nI, TB), ng = ceil_div(nb, GB);
+        if (og >= ng) continue;
+        const int j = nb - 1 - og * GB - i;
+        if (j < 0) continue;
+        push(int(m), j * TB, std::min(TB, g.nI - j * TB), 0, 0, true);
+      }
     }
-    wmax = std::max(wmax, wstep);
-    steps.push_back(f);
   }
+  // drop empty launches
+  std::vector<Launch> keep;
+  for (const auto& L : launches)
+    if (L.n > 0) keep.push_back(L);
+  launches.swap(keep);
   d.upload(h, st);
-  act.upload(a, st);
-  upd_pre.upload(up, st);
-  sol_pre.upload(sp, st);
-  npc.upload(pc, st);
-  woff.upload(wo, st);
-  part.alloc(size_t(std::max<int64_t>(wmax, 1)));
+  recs.upload(all, st);
 }
 
 void TrsmOp::run(hipStream_t st) const {
-  for (const Step& f : steps) {
-    if (f.nact == 0) continue;
-    if (f.upd_total > 0)
-      k_trsm_update<<<f.upd_total, 256, 0, st>>>(d.p, act.p + f.off, upd_pre.p + f.off,
-                                                 npc.p + f.off, woff.p + f.off, part.p, f.nact,
-                                                 f.t);
-    k_trsm_solve<<<f.sol_total, 256, 0, st>>>(d.p, act.p + f.off, sol_pre.p + f.off,
-                                              npc.p + f.off, woff.p + f.off, part.p, f.nact, f.t);
+  for (const Launch& L : launches) {
+    if (L.solve)
+      k_trsm_solve<<<L.wgs, 256, 0, st>>>(d.p, recs.p + L.off, L.n);
+    else
+      k_trsm_update<<<L.wgs, 256, 0, st>>>(d.p, recs.p + L.off, L.n);
   }
   AMB_LAUNCH_CHECK();
 }
@@ -1069,13 +1106,18 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// One workgroup per matrix, all R right-hand sides together (L is read once
-// per pass).  Block q of 64 rows: the 16 waves take every 16th solved column
-// (lanes = the block's rows, eight columns in flight per wave) and meet in
-// LDS; wave 0 then solves the 64 x 64 diagonal block, one lane per row.
+// Diagonal block ob of TrsvOp::OB rows (counted from the top in the forward
+// pass, from the bottom in the backward pass) of every matrix, one workgroup
+// per matrix, all R right-hand sides together; the rows outside the block
+// already hold the contributions of the blocks solved before (k_trsv_panel).
+// Inner block q of 64 rows: the 16 waves take every 16th solved column of the
+// outer block (lanes = the inner block's rows, eight columns in flight per
+// wave) and meet in LDS; wave 0 then solves the 64 x 64 diagonal block, one
+// lane per row.
 template <int R>
-__global__ __launch_bounds__(TRSV_THREADS) void k_trsv_chol(const TrsvDesc* __restrict__ d) {
-  constexpr int B = 64, NW = TRSV_THREADS / 64, U = 8;
+__global__ __launch_bounds__(TRSV_THREADS) void k_trsv_chol(const TrsvDesc* __restrict__ d,
+                                                            int pass, int ob) {
+  constexpr int B = 64, NW = TRSV_THREADS / 64, U = 8, OB = TrsvOp::OB;
   __shared__ double Ld[B][B + 1];
   __shared__ double part[2][NW][B];   // one right-hand side at a time, double buffered
   __shared__ double zb[R][B];
@@ -1085,15 +1127,19 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_chol(const TrsvDesc* __re
   const int n = g.nI, lda = g.lda;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nb = (n + B - 1) / B;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int q = 0; q < nb; ++q) {
-      // forward: block q from the top, L[r0.., c] for the solved c < r0;
-      // backward: block q from the bottom, L^T[r0.., c] = L[c, r0..] (the
-      // upper triangle holds L^T) for the solved c >= r0 + w
-      const int jb = pass == 0 ? q : nb - 1 - q;
+  const int nob = (n + OB - 1) / OB;
+  if (ob >= nob) return;
+  const int bo = pass == 0 ? ob : nob - 1 - ob;
+  const int o0 = bo * OB, o1 = min(n, o0 + OB);
+  const int qb = o0 / B, nq = (o1 - o0 + B - 1) / B;
+  {
+    for (int qq = 0; qq < nq; ++qq) {
+      // forward: inner block qq from the top, L[r0.., c] for the solved
+      // o0 <= c < r0; backward: from the bottom, L^T[r0.., c] = L[c, r0..]
+      // (the upper triangle holds L^T) for the solved r0 + w <= c < o1
+      const int jb = qb + (pass == 0 ? qq : nq - 1 - qq);
       const int r0 = jb * B, w = min(B, n - r0);
-      const int ca = pass == 0 ? 0 : r0 + w, cb = pass == 0 ? r0 : n;
+      const int ca = pass == 0 ? o0 : r0 + w, cb = pass == 0 ? r0 : o1;
       double acc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] = 0.0;
@@ -1170,10 +1216,87 @@ __global__ __launch_bounds__(TRSV_THREADS) void k_trsv_chol(const TrsvDesc* __re
   }
 }
 
-void launch_trsv_chol(const TrsvDesc* d, int n, int nrhs, hipStream_t st) {
-  if (n == 0 || nrhs == 0) return;
+// After diagonal block ob: the rows below it (forward, L) or above it
+// (backward, L^T from the upper triangle) subtract the block's columns times
+// its solved values.  One thread per row and right-hand sides, PANEL_ROWS
+// rows per workgroup (pre: first workgroup of every matrix); lanes read
+// consecutive rows of one column.
+template <int R>
+__global__ __launch_bounds__(256) void k_trsv_panel(const TrsvDesc* __restrict__ d,
+                                                    const int* __restrict__ pre, int nd, int pass,
+                                                    int ob) {
+  constexpr int OB = TrsvOp::OB, U = 8;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= int(blockIdx.x)) lo = mid; else hi = mid - 1;
+  }
+  const TrsvDesc g = d[lo];
+  const int n = g.nI;
+  const int nob = (n + OB - 1) / OB;
+  if (ob >= nob) return;
+  const int bo = pass == 0 ? ob : nob - 1 - ob;
+  const int o0 = bo * OB, o1 = min(n, o0 + OB);
+  const int ra = pass == 0 ? o1 : 0, rb = pass == 0 ? n : o0;
+  const int r = ra + (int(blockIdx.x) - pre[lo]) * 256 + int(threadIdx.x);
+  if (r >= rb) return;
+  double* x = g.x;
+  const int64_t ldx = g.ldx;
+  const double* __restrict__ a = g.A + r;
+  double acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = 0.0;
+  int c = o0;
+  for (; c + U <= o1; c += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = a[(size_t)(c + u) * g.lda];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) t += v[u] * x[c + u + q * ldx];
+      acc[q] += t;
+    }
+  }
+  for (; c < o1; ++c) {
+    const double v = a[(size_t)c * g.lda];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] += v * x[c + q * ldx];
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) x[r + q * ldx] -= acc[q];
+}
+
+void TrsvOp::finalize(hipStream_t st) {
+  std::vector<int> p;
+  nob = 0;
+  pwgs = 0;
+  for (const auto& g : h) {
+    p.push_back(pwgs);
+    pwgs += ceil_div(g.nI, 256);
+    nob = std::max(nob, ceil_div(g.nI, OB));
+  }
+  d.upload(h, st);
+  pre.upload(p, st);
+}
+
+template <int R>
+static void trsv_run(const TrsvOp& op, const TrsvDesc* d, const int* pre, int nd, int nob,
+                     int pwgs, hipStream_t st) {
+  for (int pass = 0; pass < 2; ++pass)
+    for (int ob = 0; ob < nob; ++ob) {
+      k_trsv_chol<R><<<nd, TRSV_THREADS, 0, st>>>(d, pass, ob);
+      if (ob + 1 < nob) k_trsv_panel<R><<<pwgs, 256, 0, st>>>(d, pre, nd, pass, ob);
+    }
+  (void)op;
+}
+
+void TrsvOp::run(int nrhs, hipStream_t st) const {
+  if (h.empty() || nrhs == 0) return;
+  const int nd = int(h.size());
   switch (nrhs) {
-#define AMB_CASE(R) case R: k_trsv_chol<R><<<n, TRSV_THREADS, 0, st>>>(d); break;
+#define AMB_CASE(R) case R: trsv_run<R>(*this, d.p, pre.p, nd, nob, pwgs, st); break;
     AMB_CASE(1) AMB_CASE(2) AMB_CASE(3) AMB_CASE(4) AMB_CASE(5) AMB_CASE(6) AMB_CASE(7)
     AMB_CASE(8) AMB_CASE(9) AMB_CASE(10) AMB_CASE(11) AMB_CASE(12) AMB_CASE(13) AMB_CASE(14)
     AMB_CASE(15) AMB_CASE(16)

@@ -139,7 +139,11 @@ class GemvOp {
   // from this many right-hand sides on, the product runs as an MFMA GEMM
   // (the operator is read once and the right-hand sides are staged in LDS)
   static constexpr int GEMM_FROM = 4;
+  // FP64 operators whose columns are all at most this long take 16 lanes per
+  // column instead of a wave
+  static constexpr int SHORT_K = 128;
   bool a32 = false;                 // A blocks are FP32 (pack_a_f32)
+  bool short_k = false;
   std::vector<GemvDesc> h;
   DBuf<GemvDesc> d;
   int wgs = 0;
@@ -241,10 +245,12 @@ class LdltOp {
 // In-place right-side triangular solve X L = B for a batch of matrices
 // after their partial Cholesky: L (nI x nI, lower, in the leading block of
 // A) and B (nG x nI, the block rows nI..nI+nG, columns 0..nI of A, i.e.
-// K_GI L^{-T}) are overwritten by X = B L^{-1} = K_GI K_II^{-1}.  Blocks of TB
-// columns from the right: each step updates one block column with the
-// columns already solved (an MFMA GEMM, K up to nI) and solves it with the
-// TB x TB diagonal block of L (one thread per row).
+// K_GI L^{-T}) are overwritten by X = B L^{-1} = K_GI K_II^{-1}.  Columns from
+// the right in groups of GB blocks of TB: a group first subtracts the product
+// of all solved columns to its right in one MFMA GEMM (K up to nI), then each
+// of its blocks, right to left, subtracts the group's solved blocks (K up to
+// (GB - 1) TB) and is solved with its TB x TB diagonal block of L (one thread
+// per row).
 struct TrsmDesc {
   double* A;
   int lda, nI, nG;
@@ -252,21 +258,22 @@ struct TrsmDesc {
 
 class TrsmOp {
  public:
-  static constexpr int TB = 64;
-  // a step whose updates have fewer tiles than this splits K into pieces
-  static constexpr int SPLIT_TILES = 1024;
+  static constexpr int TB = 64;   // columns per row solve
+  static constexpr int GB = 4;    // row-solve blocks per group (one wide update each)
   std::vector<TrsmDesc> h;
-  DBuf<TrsmDesc> d;
-  struct Step {
-    int t, off, nact, upd_total, sol_total;
+  // one launch: block updates (B[:, c0:c0+w] -= X[:, kb:ke] L[kb:ke, c0:c0+w],
+  // 64 x 64 tiles) or row solves (x L[c0:c0+w, c0:c0+w] = b, 256 rows per
+  // workgroup) of the matrices that have such a step
+  struct Rec {
+    int m, c0, w, kb, ke, start;   // matrix, columns, K range, first workgroup
   };
-  std::vector<Step> steps;
-  DBuf<int> act, upd_pre, sol_pre;
-  // per step and active matrix: K pieces of the update (piece 0 updates B in
-  // place, piece p > 0 writes its product at woff + (p - 1) nG TB of part)
-  DBuf<int> npc;
-  DBuf<int64_t> woff;
-  DBuf<double> part;
+  struct Launch {
+    bool solve;
+    int off, n, wgs;   // records [off, off + n) of recs
+  };
+  std::vector<Launch> launches;
+  DBuf<TrsmDesc> d;
+  DBuf<Rec> recs;
   void add(double* A, int lda, int nI, int nG) {
     if (nI > 0 && nG > 0) h.push_back(TrsmDesc{A, lda, nI, nG});
   }
@@ -275,16 +282,34 @@ class TrsmOp {
 };
 
 // Batched x <- K_II^{-1} x with the partial Cholesky factor of every matrix
-// (L lower in the leading nI x nI block of A and L^T in its upper triangle):
-// one workgroup per matrix for all (up to 16) right-hand sides, forward then
-// backward substitution in blocks of 64 rows.
+// (L lower in the leading nI x nI block of A and L^T in its upper triangle),
+// all (up to 16) right-hand sides together: forward then backward
+// substitution by diagonal blocks of OB rows, each solved by one workgroup per
+// matrix in blocks of 64 rows, and after each block one wide launch that
+// updates the remaining rows of every matrix with the block's solution.
 struct TrsvDesc {
   const double* A;
   int lda, nI;
   double* x;        // nI x nrhs, leading dimension ldx
   int64_t ldx;
 };
-void launch_trsv_chol(const TrsvDesc* d, int n, int nrhs, hipStream_t st);
+
+class TrsvOp {
+ public:
+  static constexpr int OB = 512;
+  std::vector<TrsvDesc> h;
+  void add(const double* A, int lda, int nI, double* x, int64_t ldx) {
+    if (nI > 0) h.push_back(TrsvDesc{A, lda, nI, x, ldx});
+  }
+  void finalize(hipStream_t st);
+  void run(int nrhs, hipStream_t st) const;
+  bool empty() const { return h.empty(); }
+
+ private:
+  DBuf<TrsvDesc> d;
+  DBuf<int> pre;   // first panel workgroup of every matrix
+  int nob = 0, pwgs = 0;
+};
 
 class SymOp {
  public:

@@ -29,8 +29,7 @@ struct Level {
   bool plain = false;
   TrsmOp trsm;
   SymOp sym_L;
-  DBuf<TrsvDesc> trsv;
-  int n_trsv = 0;
+  TrsvOp trsv;
   DBuf<int64_t> Iiota;
 
   // constraint-dependent part

@@ -275,13 +275,13 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
   L.g2c = GemvOp();
   L.g3 = GemvOp();
   L.g4 = GemvOp();
-  std::vector<TrsvDesc> tv;
+  L.trsv = TrsvOp();
   for (int s = 0; s < L.nsub; ++s) {
     const int N = L.augN[s], nI = L.nI[s], nG = L.nG[s], nsl = L.ns[s];
     double* A = L.aug.p + L.aug_off[s];
     if (L.plain) {
       // interior solves by the factor; K_II^{-1} K_IG u_B = (Aug[nI:nI+nG, 0:nI])^T u_B
-      if (nI > 0) tv.push_back(TrsvDesc{A, N, nI, L.w_xI.p + L.Ioff[s], L.nI_tot});
+      L.trsv.add(A, N, nI, L.w_xI.p + L.Ioff[s], L.nI_tot);
       L.g4.add(A + nI, N, nG, nI, L.w_uBs.p + L.Goff[s], int(L.nG_tot),
                L.w_y1.p + L.y1off[s] + nG, int(L.y1_tot));
     } else {
@@ -308,8 +308,7 @@ void build_apply_ops(ambddc_ctx& c, Level& L) {
     L.g3.add(B + nl + nG + int64_t(nl) * NN, NN, L.nc[s], nG, L.w_ucl.p + L.cloff[s],
              int(std::max<int64_t>(L.cl_tot, 1)), L.w_y2.p + L.y2off[s], int(L.y2_tot));
   }
-  L.n_trsv = int(tv.size());
-  if (L.plain) L.trsv.upload(tv, st);
+  if (L.plain) L.trsv.finalize(st);
   if (c.opt.precision >= 1) {
     // Alg. 1's dense operators are only read by the preconditioner: keep them
     // in FP32 (the FP64 blocks stay for the Schur complements and set-up).
@@ -1364,7 +1363,7 @@ void interior_solve(ambddc_ctx& c, const double* f, double* x, int nrhs) {
   launch_fill(x, size_t(n) * nrhs, 0.0, st);
   launch_gather(int(L.nI_tot), L.Imap.p, f, n, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
   if (L.plain) {
-    launch_trsv_chol(L.trsv.p, L.n_trsv, nrhs, st);
+    L.trsv.run(nrhs, st);
     launch_move(int(L.nI_tot), L.Iiota.p, L.w_xI.p, L.nI_tot, L.Imap.p, x, n, nrhs, st);
     return;
   }
@@ -1379,7 +1378,7 @@ void interior_correct(ambddc_ctx& c, const double* r, double* x, int nrhs, const
   const int64_t n = L.ndof;
   launch_gather(int(L.nI_tot), L.Imap.p, r, n, L.w_xI.p, L.nI_tot, nrhs, 1.0, st);
   if (L.plain) {
-    launch_trsv_chol(L.trsv.p, L.n_trsv, nrhs, st);
+    L.trsv.run(nrhs, st);
     launch_move_add_masked(int(L.nI_tot), L.Iiota.p, L.w_xI.p, L.nI_tot, L.Imap.p, x, n, nrhs,
                            mask, st);
     return;
