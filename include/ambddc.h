@@ -324,17 +324,21 @@ ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc_host, int32_t* n
  *                  whose slots all belong to converged pairs are skipped);
  *   "pair_gram"    Gram matrices V^T (A V), V^T (B V): 2 n nb^2 flops and
  *                  8 (2 n nb + nb^2) bytes per active pair and matrix;
- *   "schur"        batched partial LDL^T of the augmented subdomain matrices
- *                  (interior factorisation and Schur complement): per
- *                  subdomain nI^3/3 + nI^2 nG + nI nG^2 flops and
- *                  8 (nI + nG)^2 bytes;
+ *   "schur"        batched interior factorisations and Schur complements
+ *                  (partial Cholesky on level 1 with the triangular solve
+ *                  for K_GI K_II^-1, augmented partial LDL^T deeper): per
+ *                  subdomain nI^3/3 + nI^2 nG + nI nG^2 flops (level 1 also
+ *                  nG nI^2 for the solve) and 8 (nI + nG)^2 bytes;
  *   "bddc_apply"   one application of the multilevel preconditioner
- *                  (Alg. 1, all levels): the dense operators it reads, per
- *                  subdomain nI^2 + 2 nI nG + nG^2 + 2 nG nc entries, plus
- *                  the n_top^2 coarsest inverse; bytes 8 x entries (4 x the
- *                  subdomain entries with precision 1) + 8 x 6 vector
- *                  entries per DOF and right-hand side, flops
- *                  2 x entries x nrhs.
+ *                  (Alg. 1, all levels) to harmonic residuals: the dense
+ *                  operators it reads, per subdomain nI nG + nG^2 + 2 nG nc
+ *                  entries (deeper levels also nI^2 + nI nG), plus the
+ *                  n_top^2 coarsest inverse; flops 2 x entries x nrhs;
+ *                  bytes 8 x entries (4 x the deeper levels' and the Z, Psi
+ *                  entries with precision 1; nG (nG + 1) / 2 for Z in FP64
+ *                  with up to 3 right-hand sides, which read its lower
+ *                  tiles) + 8 x 6 vector entries per DOF and right-hand
+ *                  side.
  * ambddc_timing_read returns, for one class, the launches, the summed event
  * time in milliseconds and the summed algorithmic flops and bytes since the
  * last enable (any pointer may be NULL; it waits for the recorded events).
@@ -342,6 +346,18 @@ ambddc_status ambddc_get_top_coarse(ambddc_handle h, double* Kc_host, int32_t* n
 ambddc_status ambddc_timing_enable(ambddc_handle h, const char* classes);
 ambddc_status ambddc_timing_read(ambddc_handle h, const char* cls, int32_t* launches,
                                  double* total_ms, double* flops, double* bytes);
+
+/* ---- PCG iteration graphs ----
+ * flags & 1: ambddc_solve with up to 3 right-hand sides and kernel-class
+ * timing off runs each PCG iteration from its second on as two HIP graphs
+ * (the mat-vec through the convergence flags, then the preconditioner),
+ * captured on a private stream of the library and launched on the handle's
+ * stream; they are captured again after a set-up and for new solve
+ * arguments.  Results are identical to the launch-by-launch iteration.  Off
+ * by default (flags 0): on MI355X a replayed node costs about as much as the
+ * launch it replaces, and every set-up forces a new capture.
+ * Errors: E_INVALID_ARG for a null handle or unknown flag bits. */
+ambddc_status ambddc_set_graphs(ambddc_handle h, int32_t flags);
 
 const char* ambddc_last_error(void);
 void ambddc_destroy(ambddc_handle h);

@@ -100,6 +100,7 @@ _SIGS = {
     "ambddc_misfit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                 C.POINTER(C.c_double)]),
     "ambddc_timing_enable": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "ambddc_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "ambddc_timing_read": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),

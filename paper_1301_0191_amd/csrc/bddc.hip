@@ -381,9 +381,10 @@ void launch_dot_cols(int n, int nrhs, const double* a, const double* b, double* 
 
 __global__ void k_pcg_xr(int n, int nrhs, const double* rz, const double* pq, const int* active,
                          double* x, double* r, const double* p, const double* q, double* ahist,
-                         int it, int maxit) {
+                         const int* itp, int maxit) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
+  const int it = *itp;
   // a zero direction (a residual that is exactly zero) takes no step
   const double a = active[c] && pq[c] != 0.0 ? rz[c] / pq[c] : 0.0;
   if (i == 0 && active[c]) ahist[it + (size_t)c * maxit] = a;
@@ -395,26 +396,31 @@ __global__ void k_pcg_xr(int n, int nrhs, const double* rz, const double* pq, co
 
 void launch_pcg_update_x_r(int n, int nrhs, const double* rz, const double* pq, const int* active,
                            double* x, double* r, const double* p, const double* q, double* alpha_hist,
-                           int it, int maxit, hipStream_t st) {
+                           const int* itp, int maxit, hipStream_t st) {
   dim3 g(ceil_div(n, 256), nrhs);
-  k_pcg_xr<<<g, 256, 0, st>>>(n, nrhs, rz, pq, active, x, r, p, q, alpha_hist, it, maxit);
+  k_pcg_xr<<<g, 256, 0, st>>>(n, nrhs, rz, pq, active, x, r, p, q, alpha_hist, itp, maxit);
   AMB_LAUNCH_CHECK();
 }
 
 // beta = rz_new / rz; 0 for a column whose residual was just replaced by
-// the true one (restart: p = z), whose repl flag is cleared here.
+// the true one (restart: p = z), whose repl flag is cleared here.  Closes
+// the iteration: the device iteration counter *itp advances.
 __global__ void k_pcg_beta(int nrhs, const double* rz_new, double* rz, double* beta,
-                           const int* active, int* repl, double* bhist, int it, int maxit) {
+                           const int* active, int* repl, double* bhist, int* itp, int maxit) {
   const int c = threadIdx.x;
-  if (c >= nrhs) return;
-  const bool restart = repl && repl[c];
-  if (restart) repl[c] = 0;
-  const double b = active[c] && !restart && rz[c] != 0.0 ? rz_new[c] / rz[c] : 0.0;
-  beta[c] = b;
-  if (active[c]) {
-    bhist[it + (size_t)c * maxit] = b;
-    rz[c] = rz_new[c];
+  const int it = *itp;
+  if (c < nrhs) {
+    const bool restart = repl && repl[c];
+    if (restart) repl[c] = 0;
+    const double b = active[c] && !restart && rz[c] != 0.0 ? rz_new[c] / rz[c] : 0.0;
+    beta[c] = b;
+    if (active[c]) {
+      bhist[it + (size_t)c * maxit] = b;
+      rz[c] = rz_new[c];
+    }
   }
+  __syncthreads();
+  if (c == 0) *itp = it + 1;
 }
 
 __global__ void k_pcg_p(int n, const double* beta, const int* active, double* p, const double* z) {
@@ -427,10 +433,10 @@ __global__ void k_pcg_p(int n, const double* beta, const int* active, double* p,
 
 // beta = rz_new / rz (stored after rz_new in the same array: rz_new[nrhs..2nrhs) used as scratch)
 void launch_pcg_update_p(int n, int nrhs, const double* rz_new, double* rz, const int* active,
-                         int* restart, double* p, const double* z, double* beta_hist, int it,
+                         int* restart, double* p, const double* z, double* beta_hist, int* itp,
                          int maxit, hipStream_t st) {
   double* beta = rz + nrhs;   // scratch right after rz
-  k_pcg_beta<<<1, 64, 0, st>>>(nrhs, rz_new, rz, beta, active, restart, beta_hist, it, maxit);
+  k_pcg_beta<<<1, 64, 0, st>>>(nrhs, rz_new, rz, beta, active, restart, beta_hist, itp, maxit);
   dim3 g(ceil_div(n, 256), nrhs);
   k_pcg_p<<<g, 256, 0, st>>>(n, beta, active, p, z);
   AMB_LAUNCH_CHECK();
@@ -457,6 +463,7 @@ __global__ void k_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal,
     cnt[1] = a;
     cnt[2] = 0;
     cnt[3] = 0;
+    cnt[4] = 0;   // iteration counter
   }
 }
 
@@ -469,8 +476,9 @@ void launch_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* 
 // After iteration `it`: every active column has taken it + 1 steps; meets[c]
 // says its recursive residual rr[c] <= rtol^2 ff[c].
 __global__ void k_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2,
-                            const int* act, int* nal, int* meets, int* cnt, int it) {
+                            const int* act, int* nal, int* meets, int* cnt, const int* itp) {
   const int c = threadIdx.x;
+  const int it = *itp;
   if (c < nrhs) {
     const int m = act[c] && rr[c] <= rtol2 * ff[c];
     meets[c] = m;
@@ -485,8 +493,8 @@ __global__ void k_pcg_meets(int nrhs, const double* rr, const double* ff, double
 }
 
 void launch_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2, const int* act,
-                      int* nal, int* meets, int* cnt, int it, hipStream_t st) {
-  k_pcg_meets<<<1, 64, 0, st>>>(nrhs, rr, ff, rtol2, act, nal, meets, cnt, it);
+                      int* nal, int* meets, int* cnt, const int* itp, hipStream_t st) {
+  k_pcg_meets<<<1, 64, 0, st>>>(nrhs, rr, ff, rtol2, act, nal, meets, cnt, itp);
   AMB_LAUNCH_CHECK();
 }
 

@@ -119,16 +119,17 @@ void launch_dot_cols(int n, int nrhs, const double* a, const double* b, double* 
                      hipStream_t st);
 void launch_pcg_update_x_r(int n, int nrhs, const double* rz, const double* pq, const int* active,
                            double* x, double* r, const double* p, const double* q, double* alpha_hist,
-                           int it, int maxit, hipStream_t st);
+                           const int* itp, int maxit, hipStream_t st);
 void launch_pcg_update_p(int n, int nrhs, const double* rz_new, double* rz, const int* active,
-                         int* restart, double* p, const double* z, double* beta_hist, int it,
+                         int* restart, double* p, const double* z, double* beta_hist, int* itp,
                          int maxit, hipStream_t st);
 void launch_lanczos_cond(int nrhs, const int* nalpha, const double* alpha, const double* beta,
                          int maxit, double* out, hipStream_t st);
+// cnt: 5 ints (meets, active, replaced, stalled counts, iteration counter)
 void launch_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* repl, int* stall,
                            double* tprev, int* cnt, hipStream_t st);
 void launch_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2, const int* act,
-                      int* nal, int* meets, int* cnt, int it, hipStream_t st);
+                      int* nal, int* meets, int* cnt, const int* itp, hipStream_t st);
 void launch_pcg_true(int nrhs, const double* tt, const double* ff, double rtol2, int* act,
                      const int* meets, int* repl, int* stall, double* tprev, int* cnt,
                      hipStream_t st);

@@ -126,7 +126,23 @@ struct ambddc_ctx {
   // pinned host copy of the PCG counters and the event that follows its copy
   int* hcnt = nullptr;
   hipEvent_t ev_cnt = nullptr;
+  // PCG iteration graphs: captured on cap_st, launched on st; valid for one
+  // set-up (setup_epoch) and one set of solve arguments (pcg_gkey)
+  int setup_epoch = 0, pcg_gepoch = -1;
+  hipStream_t cap_st = nullptr;
+  int graphs = 0;   // ambddc_set_graphs flags
+  hipGraphExec_t pcg_g1 = nullptr, pcg_g2 = nullptr;
+  const void* pcg_gkey[5] = {};
+  double pcg_grtol = 0.0;
+  void drop_pcg_graphs() {
+    if (pcg_g1) (void)hipGraphExecDestroy(pcg_g1);
+    if (pcg_g2) (void)hipGraphExecDestroy(pcg_g2);
+    pcg_g1 = pcg_g2 = nullptr;
+    pcg_gepoch = -1;
+  }
   ~ambddc_ctx() {
+    drop_pcg_graphs();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
     if (ev_cnt) (void)hipEventDestroy(ev_cnt);
     if (hcnt) (void)hipHostFree(hcnt);
   }
@@ -1428,6 +1444,7 @@ void setup_impl(ambddc_ctx& c, const double* coeff, const double* nu) {
   hipStream_t st = c.st;
   const double t0 = now_s();
   c.ready = false;
+  ++c.setup_epoch;   // the operators the PCG graphs point at are rebuilt
   std::memset(&c.stats, 0, sizeof(c.stats));
   {
     const int big = std::numeric_limits<int>::max();
@@ -1517,7 +1534,7 @@ struct PcgWork {
   double *ah, *bh; // ldh x nrhs coefficient histories
   double* lz;      // 3 nrhs + 2 ldh nrhs: condition estimates and Sturm workspace
   double* tprev;   // nrhs: true residual at the column's last check
-  int *act, *nal, *meets, *repl, *stall, *cnt;   // nrhs each; cnt: 4
+  int *act, *nal, *meets, *repl, *stall, *cnt;   // nrhs each; cnt: 5 (cnt[4]: iteration)
   int ldh;
 };
 
@@ -1525,7 +1542,7 @@ struct PcgWork {
 void pcg_work_size(int64_t n, int nrhs, int ldh, int64_t& nd, int64_t& ni) {
   nd = 4 * n * nrhs + 8 * int64_t(nrhs) + 256 * int64_t(nrhs) + 2 * int64_t(ldh) * nrhs +
        3 * int64_t(nrhs) + 2 * int64_t(ldh) * nrhs + int64_t(nrhs);
-  ni = 5 * int64_t(nrhs) + 4;
+  ni = 5 * int64_t(nrhs) + 8;
 }
 
 // Carve a PcgWork out of nd doubles at d and ni ints at ip.
@@ -1635,20 +1652,79 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
   launch_dot_cols(n, nrhs, w.r, w.z, w.part, rz, st);
   launch_copy(w.p, w.z, nn, st);
   read_cnt();
+  int* itp = w.cnt + 4;   // device iteration counter (the history slot of the step)
+  // one step's mat-vec through the convergence flags, the counters copied
+  // back at its end; then the preconditioner of the new residual
+  auto step1 = [&](hipStream_t s) {
+    launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, s);
+    launch_zero_rows(int(L1.nI_tot), L1.Imap.p, w.q, n, nrhs, nullptr, s);
+    launch_dot_cols(n, nrhs, w.p, w.q, w.part, pq, s);
+    launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, itp, w.ldh, s);
+    launch_dot_cols(n, nrhs, w.r, w.r, w.part, rr, s);
+    launch_pcg_meets(nrhs, rr, ff, rtol2, w.act, w.nal, w.meets, w.cnt, itp, s);
+    AMB_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+  };
+  auto step2 = [&](hipStream_t s) {
+    apply_level(c, 0, w.r, n, w.z, n, nrhs, true);   // on c.st, which is s here
+    launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, s);
+  };
+  // When switched on, without kernel-class timing (whose events cannot sit
+  // in a graph) and for up to 3 right-hand sides (no product builds anything
+  // on first use), the two parts run as HIP graphs from the second step on:
+  // captured once per set-up and solve arguments, replayed every step.
+  const bool use_graph = (c.graphs & 1) && timed && !c.kt.any() && nrhs <= SymvOp::MAX_RHS;
+  const void* key[5] = {f, x, w.r, w.cnt, reinterpret_cast<const void*>(intptr_t(nrhs))};
+  auto capture = [&](auto&& fn) {
+    hipStream_t cs = c.cap_st;
+    hipStream_t saved = c.st;
+    AMB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    c.st = cs;
+    hipGraph_t g = nullptr;
+    try {
+      fn(cs);
+    } catch (...) {
+      c.st = saved;
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    c.st = saved;
+    AMB_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    AMB_HIP(err);
+    return e;
+  };
+  auto graphs_ready = [&]() {
+    if (c.pcg_g1 && c.pcg_gepoch == c.setup_epoch && c.pcg_grtol == rtol &&
+        std::equal(key, key + 5, c.pcg_gkey))
+      return;
+    c.drop_pcg_graphs();
+    if (!c.cap_st) AMB_HIP(hipStreamCreateWithFlags(&c.cap_st, hipStreamNonBlocking));
+    c.pcg_g1 = capture(step1);
+    c.pcg_g2 = capture(step2);
+    std::copy(key, key + 5, c.pcg_gkey);
+    c.pcg_grtol = rtol;
+    c.pcg_gepoch = c.setup_epoch;
+  };
   int nact = hc[1];
   int repl = 0;
   for (int it = 0; it < maxit && nact > 0; ++it) {
-    launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, st);
-    launch_zero_rows(int(L1.nI_tot), L1.Imap.p, w.q, n, nrhs, nullptr, st);
-    launch_dot_cols(n, nrhs, w.p, w.q, w.part, pq, st);
-    launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, it, w.ldh, st);
-    launch_dot_cols(n, nrhs, w.r, w.r, w.part, rr, st);
-    launch_pcg_meets(nrhs, rr, ff, rtol2, w.act, w.nal, w.meets, w.cnt, it, st);
     // The counters travel back while the preconditioner of this residual is
     // already queued: it stays valid unless a check below replaces columns of r.
-    fetch_cnt();
-    precondition();
-    launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, st);
+    if (use_graph && it > 0) {
+      graphs_ready();
+      AMB_HIP(hipGraphLaunch(c.pcg_g1, st));
+      AMB_HIP(hipEventRecord(c.ev_cnt, st));
+      AMB_HIP(hipGraphLaunch(c.pcg_g2, st));
+    } else {
+      step1(st);
+      AMB_HIP(hipEventRecord(c.ev_cnt, st));
+      if (kt) c.kt.begin("bddc_apply", st);
+      step2(st);
+      if (kt) c.kt.end("bddc_apply", st, apf, apb);
+    }
     AMB_HIP(hipEventSynchronize(c.ev_cnt));
     if (hc[0] > 0) {
       // The recursive residual drifts from f - K x by rounding (most on
@@ -1676,7 +1752,7 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
         launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, st);
       }
     }
-    launch_pcg_update_p(n, nrhs, rzn, rz, w.act, w.repl, w.p, w.z, w.bh, it, w.ldh, st);
+    launch_pcg_update_p(n, nrhs, rzn, rz, w.act, w.repl, w.p, w.z, w.bh, itp, w.ldh, st);
   }
   // iterations per column and the true residuals ||f - K x|| / ||f||
   int hnal[16];
@@ -2126,6 +2202,15 @@ ambddc_status ambddc_timing_enable(ambddc_handle h, const char* classes) {
       a = b + 1;
     }
     h->kt.enable(list);
+  }));
+}
+
+ambddc_status ambddc_set_graphs(ambddc_handle h, int32_t flags) {
+  return ambddc_status(hguard(h, [&] {
+    if (!h) throw Error(AMBDDC_E_INVALID_ARG, "null handle");
+    if (flags & ~1) throw Error(AMBDDC_E_INVALID_ARG, "unknown graph flags");
+    h->graphs = flags;
+    if (!(flags & 1)) h->drop_pcg_graphs();
   }));
 }
 

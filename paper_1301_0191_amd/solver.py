@@ -302,6 +302,11 @@ class Handle:
                                                        C.byref(n)))
         return K
 
+    # ---- PCG iteration graphs ----
+    def set_graphs(self, on):
+        """Replay PCG iterations as HIP graphs (ambddc_set_graphs)."""
+        _lib.check(self._lib.ambddc_set_graphs(self._h, 1 if on else 0))
+
     # ---- kernel timing ----
     def timing_enable(self, classes):
         """Time the listed kernel classes (list or comma-separated string)
