@@ -1,5 +1,6 @@
 // Kernels of the BDDC structures (weights, constraint and Neumann matrices,
 // coarse element matrices) and of the preconditioner application and PCG.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -370,6 +371,56 @@ __global__ __launch_bounds__(256) void k_dot_final(int nb, const double* part, d
   if (threadIdx.x == 0) out[r] = red[0] + red[1] + red[2] + red[3];
 }
 
+// One-launch column dots: every block writes its partial and releases it
+// (device scope) before counting itself in at the column's counter; the
+// block that arrives last acquires the partials, sums them in block order
+// and resets the counter for the next call.  Blocks of at least DOT_MIN
+// entries, at most DOT_BLOCKS of them: on short vectors the cache
+// write-backs of the release would cost more than the partial sums.
+__global__ __launch_bounds__(256) void k_dot_fin(int n, const double* a, const double* b,
+                                                 double* part, int* cnt, double* out) {
+  const int r = blockIdx.y;
+  const int nb = gridDim.x;
+  const double* x = a + (size_t)r * n;
+  const double* y = b + (size_t)r * n;
+  double v = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    v += x[i] * y[i];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __shared__ double red[4];
+  __shared__ int last;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x + r * nb] = red[0] + red[1] + red[2] + red[3];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    last = atomicAdd(&cnt[r], 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    v += part[i + r * nb];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[r] = red[0] + red[1] + red[2] + red[3];
+    cnt[r] = 0;
+  }
+}
+
+// part: DOT_BLOCKS * nrhs doubles; cnt: nrhs ints, zero between calls.
+void launch_dot_cols_fin(int n, int nrhs, const double* a, const double* b, double* part,
+                         int* cnt, double* out, hipStream_t st) {
+  constexpr int DOT_MIN = 512;
+  dim3 g(std::max(1, std::min(DOT_BLOCKS, n / DOT_MIN)), nrhs);
+  k_dot_fin<<<g, 256, 0, st>>>(n, a, b, part, cnt, out);
+  AMB_LAUNCH_CHECK();
+}
+
 // Deterministic two-stage column dots: part needs DOT_BLOCKS * nrhs doubles.
 void launch_dot_cols(int n, int nrhs, const double* a, const double* b, double* part, double* out,
                      hipStream_t st) {
@@ -465,6 +516,7 @@ __global__ void k_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal,
     cnt[3] = 0;
     cnt[4] = 0;   // iteration counter
   }
+  if (c < nrhs) cnt[8 + c] = 0;   // one-launch dot counters
 }
 
 void launch_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* repl, int* stall,

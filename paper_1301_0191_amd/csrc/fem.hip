@@ -335,12 +335,15 @@ void launch_csr_values(const CsrMaps& m, const int* edofs, int ne, const double*
 __global__ __launch_bounds__(256) void k_spmv_any(int n, int nrhs, const int* __restrict__ rowptr,
                                                   const int* __restrict__ cols,
                                                   const double* __restrict__ vals,
-                                                  const double* __restrict__ x, double* y) {
+                                                  const double* __restrict__ x, double* y,
+                                                  const unsigned char* __restrict__ zmask) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const bool z = zmask && zmask[i];
   for (int r = 0; r < nrhs; ++r) {
     double acc = 0.0;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += vals[k] * x[cols[k] + (size_t)r * n];
+    if (!z)
+      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += vals[k] * x[cols[k] + (size_t)r * n];
     y[i + (size_t)r * n] = acc;
   }
 }
@@ -354,10 +357,17 @@ template <int R, int G>
 __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rowptr,
                                                 const int* __restrict__ cols,
                                                 const double* __restrict__ vals,
-                                                const double* __restrict__ x, double* y) {
+                                                const double* __restrict__ x, double* y,
+                                                const unsigned char* __restrict__ zmask) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = t / G, lane = t % G;
   if (i >= n) return;   // whole groups leave together
+  if (zmask && zmask[i]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane == r % G) y[i + (size_t)r * n] = 0.0;
+    return;
+  }
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
@@ -379,27 +389,39 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
 
 template <int G>
 static void spmv_g(const CsrMaps& m, const double* vals, const double* x, double* y, int nrhs,
-                   hipStream_t st) {
+                   hipStream_t st, const unsigned char* zm) {
   const int g = ceil_div(m.n, 256 / G);
   switch (nrhs) {
-    case 1: k_spmv_g<1, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 2: k_spmv_g<2, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 4: k_spmv_g<4, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 8: k_spmv_g<8, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
-    case 16: k_spmv_g<16, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y); break;
+    case 1: k_spmv_g<1, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y, zm); break;
+    case 2: k_spmv_g<2, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y, zm); break;
+    case 4: k_spmv_g<4, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y, zm); break;
+    case 8: k_spmv_g<8, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y, zm); break;
+    case 16: k_spmv_g<16, G><<<g, 256, 0, st>>>(m.n, m.rowptr.p, m.cols.p, vals, x, y, zm); break;
     default:
-      k_spmv_any<<<ceil_div(m.n, 256), 256, 0, st>>>(m.n, nrhs, m.rowptr.p, m.cols.p, vals, x, y);
+      k_spmv_any<<<ceil_div(m.n, 256), 256, 0, st>>>(m.n, nrhs, m.rowptr.p, m.cols.p, vals, x, y,
+                                                     zm);
   }
 }
 
 void launch_spmv(const CsrMaps& m, const double* vals, const double* x, double* y, int nrhs,
-                 hipStream_t st) {
+                 hipStream_t st, const unsigned char* zmask) {
   if (m.n == 0) return;
   // lanes per row from the mean row length
   const double avg = double(m.nnz) / m.n;
-  if (avg > 48.0) spmv_g<32>(m, vals, x, y, nrhs, st);
-  else if (avg > 12.0) spmv_g<16>(m, vals, x, y, nrhs, st);
-  else spmv_g<4>(m, vals, x, y, nrhs, st);
+  if (avg > 48.0) spmv_g<32>(m, vals, x, y, nrhs, st, zmask);
+  else if (avg > 12.0) spmv_g<16>(m, vals, x, y, nrhs, st, zmask);
+  else spmv_g<4>(m, vals, x, y, nrhs, st, zmask);
+  AMB_LAUNCH_CHECK();
+}
+
+__global__ void k_mark_rows(int n, const int64_t* __restrict__ pos, unsigned char* mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) mask[pos[i]] = 1;
+}
+
+void launch_mark_rows(int n, const int64_t* pos, unsigned char* mask, hipStream_t st) {
+  if (n == 0) return;
+  k_mark_rows<<<ceil_div(n, 256), 256, 0, st>>>(n, pos, mask);
   AMB_LAUNCH_CHECK();
 }
 

@@ -38,8 +38,11 @@ void launch_assemble_cols(const AssemblyMaps& m, int ldmax, const double* emat,
                           const int64_t* tgt_off, const int* tgt_ld, double* tgt, hipStream_t st);
 void launch_csr_values(const CsrMaps& m, const int* edofs, int ne, const double* Ke, double* vals,
                        hipStream_t st);
+// zmask (optional, n bytes): rows with a nonzero byte are written as zero
 void launch_spmv(const CsrMaps& m, const double* vals, const double* x, double* y, int nrhs,
-                 hipStream_t st);
+                 hipStream_t st, const unsigned char* zmask = nullptr);
+// mask[pos[i]] = 1 for i < n
+void launch_mark_rows(int n, const int64_t* pos, unsigned char* mask, hipStream_t st);
 void launch_element_gradient(int n_elem, int ne, int n, int nrhs, const int* edofs, const double* Ke,
                              const double* X, const double* L, double* grad, hipStream_t st);
 
@@ -117,6 +120,9 @@ void launch_diag_copy(int n, const int64_t* pos, const double* A, double* out, h
 // ---- Krylov helpers ----
 void launch_dot_cols(int n, int nrhs, const double* a, const double* b, double* part, double* out,
                      hipStream_t st);
+// one launch; cnt: nrhs ints that are zero between calls (left zero)
+void launch_dot_cols_fin(int n, int nrhs, const double* a, const double* b, double* part,
+                         int* cnt, double* out, hipStream_t st);
 void launch_pcg_update_x_r(int n, int nrhs, const double* rz, const double* pq, const int* active,
                            double* x, double* r, const double* p, const double* q, double* alpha_hist,
                            const int* itp, int maxit, hipStream_t st);
@@ -125,7 +131,8 @@ void launch_pcg_update_p(int n, int nrhs, const double* rz_new, double* rz, cons
                          int maxit, hipStream_t st);
 void launch_lanczos_cond(int nrhs, const int* nalpha, const double* alpha, const double* beta,
                          int maxit, double* out, hipStream_t st);
-// cnt: 5 ints (meets, active, replaced, stalled counts, iteration counter)
+// cnt: 8 + nrhs ints (meets, active, replaced, stalled counts, iteration
+// counter, 3 spare, then the counters of launch_dot_cols_fin, zeroed here)
 void launch_pcg_init_flags(int nrhs, const double* ff, int* act, int* nal, int* repl, int* stall,
                            double* tprev, int* cnt, hipStream_t st);
 void launch_pcg_meets(int nrhs, const double* rr, const double* ff, double rtol2, const int* act,

@@ -109,6 +109,7 @@ struct ambddc_ctx {
   DBuf<int> en, edofs;
   CsrMaps csr;
   DBuf<double> csr_vals, Ke;
+  DBuf<unsigned char> imask;   // level-1 interior rows of the global vectors
   std::vector<std::unique_ptr<Level>> L;
   Top top;
   bool ready = false;
@@ -1534,7 +1535,8 @@ struct PcgWork {
   double *ah, *bh; // ldh x nrhs coefficient histories
   double* lz;      // 3 nrhs + 2 ldh nrhs: condition estimates and Sturm workspace
   double* tprev;   // nrhs: true residual at the column's last check
-  int *act, *nal, *meets, *repl, *stall, *cnt;   // nrhs each; cnt: 5 (cnt[4]: iteration)
+  int *act, *nal, *meets, *repl, *stall, *cnt;   // nrhs each; cnt: 8 + nrhs (cnt[4]: iteration,
+                                                 // cnt[8..]: one-launch dot counters)
   int ldh;
 };
 
@@ -1542,7 +1544,7 @@ struct PcgWork {
 void pcg_work_size(int64_t n, int nrhs, int ldh, int64_t& nd, int64_t& ni) {
   nd = 4 * n * nrhs + 8 * int64_t(nrhs) + 256 * int64_t(nrhs) + 2 * int64_t(ldh) * nrhs +
        3 * int64_t(nrhs) + 2 * int64_t(ldh) * nrhs + int64_t(nrhs);
-  ni = 5 * int64_t(nrhs) + 8;
+  ni = 6 * int64_t(nrhs) + 8;
 }
 
 // Carve a PcgWork out of nd doubles at d and ni ints at ip.
@@ -1655,18 +1657,18 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
   int* itp = w.cnt + 4;   // device iteration counter (the history slot of the step)
   // one step's mat-vec through the convergence flags, the counters copied
   // back at its end; then the preconditioner of the new residual
+  int* dcnt = w.cnt + 8;
   auto step1 = [&](hipStream_t s) {
-    launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, s);
-    launch_zero_rows(int(L1.nI_tot), L1.Imap.p, w.q, n, nrhs, nullptr, s);
-    launch_dot_cols(n, nrhs, w.p, w.q, w.part, pq, s);
+    launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, s, c.imask.p);   // interior rows zero
+    launch_dot_cols_fin(n, nrhs, w.p, w.q, w.part, dcnt, pq, s);
     launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, itp, w.ldh, s);
-    launch_dot_cols(n, nrhs, w.r, w.r, w.part, rr, s);
+    launch_dot_cols_fin(n, nrhs, w.r, w.r, w.part, dcnt, rr, s);
     launch_pcg_meets(nrhs, rr, ff, rtol2, w.act, w.nal, w.meets, w.cnt, itp, s);
     AMB_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
   };
   auto step2 = [&](hipStream_t s) {
     apply_level(c, 0, w.r, n, w.z, n, nrhs, true);   // on c.st, which is s here
-    launch_dot_cols(n, nrhs, w.r, w.z, w.part, rzn, s);
+    launch_dot_cols_fin(n, nrhs, w.r, w.z, w.part, dcnt, rzn, s);
   };
   // When switched on, without kernel-class timing (whose events cannot sit
   // in a graph) and for up to 3 right-hand sides (no product builds anything
@@ -2064,6 +2066,10 @@ ambddc_status ambddc_create(const ambddc_mesh* mesh, const ambddc_decomp* dec,
     std::vector<int64_t> eoff(mesh->n_elems);
     for (int e2 = 0; e2 < mesh->n_elems; ++e2) eoff[e2] = int64_t(e2) * ne * ne;
     build_level_maps(*c, *L0, c->Ke.p, eoff, true);
+    // rows of the level-1 interiors, which the PCG mat-vec writes as zero
+    c->imask.alloc(size_t(std::max(L0->ndof, 1)));
+    c->imask.zero(st);
+    launch_mark_rows(int(L0->nI_tot), L0->Imap.p, c->imask.p, st);
     L0->rigid.alloc(size_t(L0->ndof) * L0->nrb);
     {
       DBuf<int> fof;
