@@ -1657,18 +1657,24 @@ int pcg_core(ambddc_ctx& c, const PcgWork& w, const double* f, int nrhs, double 
   int* itp = w.cnt + 4;   // device iteration counter (the history slot of the step)
   // one step's mat-vec through the convergence flags, the counters copied
   // back at its end; then the preconditioner of the new residual
+  // The step's dot products in one launch each for up to 3 columns; with
+  // more, the blocks' cache write-backs cost more than the second launch.
   int* dcnt = w.cnt + 8;
+  auto dots = [&](const double* a, const double* b, double* out, hipStream_t s) {
+    if (nrhs <= 3) launch_dot_cols_fin(n, nrhs, a, b, w.part, dcnt, out, s);
+    else launch_dot_cols(n, nrhs, a, b, w.part, out, s);
+  };
   auto step1 = [&](hipStream_t s) {
     launch_spmv(c.csr, c.csr_vals.p, w.p, w.q, nrhs, s, c.imask.p);   // interior rows zero
-    launch_dot_cols_fin(n, nrhs, w.p, w.q, w.part, dcnt, pq, s);
+    dots(w.p, w.q, pq, s);
     launch_pcg_update_x_r(n, nrhs, rz, pq, w.act, x, w.r, w.p, w.q, w.ah, itp, w.ldh, s);
-    launch_dot_cols_fin(n, nrhs, w.r, w.r, w.part, dcnt, rr, s);
+    dots(w.r, w.r, rr, s);
     launch_pcg_meets(nrhs, rr, ff, rtol2, w.act, w.nal, w.meets, w.cnt, itp, s);
     AMB_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
   };
   auto step2 = [&](hipStream_t s) {
     apply_level(c, 0, w.r, n, w.z, n, nrhs, true);   // on c.st, which is s here
-    launch_dot_cols_fin(n, nrhs, w.r, w.z, w.part, dcnt, rzn, s);
+    dots(w.r, w.z, rzn, s);
   };
   // When switched on, without kernel-class timing (whose events cannot sit
   // in a graph) and for up to 3 right-hand sides (no product builds anything
